@@ -1,0 +1,294 @@
+"""Benchmark: count sketch Kaczmarz time to relative error 1e-10 on one MI355X.
+
+A step is one pass of the hot path over the workload: the count sketch
+(hash, grouping, segmented signed row-sum, norms) followed by the persistent
+MWRK solve to the tolerance.  The default workload is the dense coherent
+system (A 200000 x 1000 U[0,1) FP64, d = 20000, tol 1e-10).  Inputs are
+generated on the device before timing; the timed region covers only the
+library's kernels.  The JSON line also carries the roofline of the dominant
+kernel (the solve), the sketch bandwidth, the mixed-precision, batched and
+sparse-input measurements, and the CPU oracle timed on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "CSK time-to-rel-err-1e-10 (s) + GEMV/sketch HBM GB/s; mixed/batched vs FP64"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def timed(fn, reps=1):
+    import torch
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    out = None
+    for _ in range(reps):
+        out = fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / reps / 1e3, out
+
+
+def main_workload(args, P, W, torch):
+    c = W.config("dense_coherent")
+    m, n, d = c["m"], c["n"], c["d"]
+    dev = "cuda:0"
+    log(f"[bench] generating dense_coherent A {m}x{n} FP64 on {dev}")
+    s = W.uniform01(m, n, c["seed"], device=dev)
+    torch.cuda.synchronize()
+
+    import ctypes
+    from paper_2004_02480_amd import _abi
+    # persistent buffers so the timed loop allocates nothing
+    x = torch.empty(n, dtype=torch.float64, device=dev)
+    res = torch.zeros(_abi.RESULT_BYTES, dtype=torch.uint8, device=dev)
+    nb = ctypes.c_size_t(0)
+    P.lib.csk_solve_workspace_size(d, n, P.CSK_F64, ctypes.byref(nb))
+    ws = torch.empty(nb.value + 512, dtype=torch.uint8, device=dev)
+    ws = ws[(-ws.data_ptr()) % 256:]
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    sk_ms, sv_ms = [], []
+
+    def step(record):
+        if record:
+            ev[0].record()
+        sk = P.csk_sketch(s.A, s.b, d, c["sketch_seed"])
+        if record:
+            ev[1].record()
+        P.csk_solve(sk.At64, sk.bt, nu2=sk.nu2, x_ref=s.x_star, tol=c["tol"], maxit=c["maxit"],
+                    out=x, result=res, workspace=ws, sync=False)
+        if record:
+            ev[2].record()
+        return sk
+
+    log(f"[bench] warmup {args.warmup} step(s)")
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    log(f"[bench] timing {args.steps} step(s)")
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    t_start.record()
+    sk = None
+    for _ in range(args.steps):
+        sk = step(True)
+        # per-phase events are read back after each step; the host waits only
+        # on the events of the step that just ended
+        ev[2].synchronize()
+        sk_ms.append(ev[0].elapsed_time(ev[1]))
+        sv_ms.append(ev[1].elapsed_time(ev[2]))
+    t_end.record()
+    torch.cuda.synchronize()
+    total_ms = t_start.elapsed_time(t_end) / args.steps
+    it, st, fb, meas, nref = P.parse_results(res)[0]
+    rel = ((x - s.x_star).norm() / s.x_star.norm()).item()
+    log(f"[bench] dense_coherent: status={P.csk_status_string(st)} iters={it} relerr={rel:.3e} "
+        f"step={total_ms:.2f} ms (sketch {min(sk_ms):.3f} ms, solve {min(sv_ms):.2f} ms)")
+    if st != P.CSK_OK or rel > c["tol"]:
+        raise SystemExit(f"dense_coherent did not converge: {P.csk_status_string(st)} relerr={rel}")
+    sketch_bytes = m * n * 8 + m * 8 + d * n * 8 + d * 8 + d * 8
+    iter_bytes = d * n * 8 + 16 * d
+    solve_s = sum(sv_ms) / len(sv_ms) / 1e3
+    sketch_s = sum(sk_ms) / len(sk_ms) / 1e3
+    out = dict(total_s=total_ms / 1e3, sketch_s=sketch_s, solve_s=solve_s, iters=it, relerr=rel,
+               sketch_gbs=sketch_bytes / sketch_s / 1e9, iter_bytes=iter_bytes,
+               solve_gbs=it * iter_bytes / solve_s / 1e9, us_per_iter=solve_s / max(it, 1) * 1e6,
+               sketch_bytes=sketch_bytes, m=m, n=n, d=d)
+    del sk
+    return out, s, c
+
+
+def cpu_baseline(s, c, iters_gpu, budget_iters=200):
+    """The oracle as it stands (single thread) on the same workload: the full
+    sketch, then `budget_iters` MWRK iterations, extrapolated to the GPU's
+    iteration count."""
+    import numpy as np
+    import oracle
+    A = s.A.cpu().numpy()
+    b = s.b.cpu().numpy()
+    xs = s.x_star.cpu().numpy()
+    t0 = time.perf_counter()
+    At, bt = oracle.sketch_dense(A, b, c["d"], c["sketch_seed"])
+    t1 = time.perf_counter()
+    oracle.mwrk(At, bt, xref=xs, tol=0.0, maxit=budget_iters)
+    t2 = time.perf_counter()
+    per_iter = (t2 - t1) / budget_iters
+    est = (t1 - t0) + per_iter * iters_gpu
+    del A, At
+    np.asarray(0)
+    return dict(value=est, unit="s", cores=1, kind="oracle",
+                sample=f"full sketch ({t1 - t0:.2f} s) + {budget_iters} of {iters_gpu} MWRK iterations "
+                       f"({per_iter * 1e3:.1f} ms each), extrapolated to the GPU's iteration count")
+
+
+def mixed_workload(P, W, torch, reps=2):
+    """Row-scaled FP32 A 500000 x 1000, d = 10000: FP64 path vs BF16 / FP16
+    storage with FP64 refresh, time to 1e-10 (sketch + solve)."""
+    c = W.config("row_scaled")
+    dev = "cuda:0"
+    log("[bench] generating row_scaled A 500000x1000 FP32")
+    s = W.row_scaled(c["m"], c["n"], c["seed"], device=dev)
+    torch.cuda.synchronize()
+    out = {}
+    for name, lp in (("f64", None), ("bf16", torch.bfloat16), ("f16", torch.float16), ("f32", torch.float32)):
+        def run():
+            sk = P.csk_sketch(s.A, s.b, c["d"], c["sketch_seed"], lp_dtype=lp)
+            if lp is None:
+                return P.csk_solve(sk.At64, sk.bt, nu2=sk.nu2, x_ref=s.x_star, tol=c["tol"], maxit=c["maxit"],
+                                   sync=False)
+            return P.csk_solve(sk.At_lp, sk.bt, At64=sk.At64, nu2=sk.nu2, x_ref=s.x_star, tol=c["tol"],
+                               maxit=c["maxit"], sync=False)
+        run()
+        t, (x, raw) = timed(run, reps)
+        it, st, fb, meas, nref = P.parse_results(raw)[0]
+        rel = ((x - s.x_star).norm() / s.x_star.norm()).item()
+        out[name] = dict(time_s=t, iters=it, status=P.csk_status_string(st), relerr=rel, refreshes=nref,
+                         fp64_fallback=fb)
+        log(f"[bench] row_scaled {name}: {t * 1e3:.2f} ms iters={it} rel={rel:.2e} {P.csk_status_string(st)}")
+    for name in ("bf16", "f16", "f32"):
+        out[name]["speedup_vs_f64"] = out["f64"]["time_s"] / out[name]["time_s"]
+    del s
+    torch.cuda.empty_cache()
+    return out
+
+
+def batched_workload(P, W, torch):
+    """512 uneven Gaussian FP32 systems, sketch + solve to 1e-8 in one pass."""
+    c = W.config("batched")
+    dev = "cuda:0"
+    shapes, redraws = W.batched_shapes(c["nsys"], c["seed"], c["sketch_seed"])
+    log(f"[bench] generating {len(shapes)} batched systems ({redraws} redraws)")
+    systems = []
+    for sh in shapes:
+        s = W.gaussian(sh.m, sh.n, sh.seed, dtype=torch.float32, device=dev)
+        systems.append(dict(A=s.A, b=s.b, d=sh.d, seed=sh.sketch_seed, x_ref=s.x_star))
+    torch.cuda.synchronize()
+    P.csk_solve_batched(systems[:4], lp_dtype=torch.float32, tol=c["tol"], maxit=c["maxit"])
+    t, (xs, raw, ws) = timed(lambda: P.csk_solve_batched(systems, lp_dtype=torch.float32, tol=c["tol"],
+                                                          maxit=c["maxit"], sync=False))
+    res = P.parse_results(raw)
+    ok = sum(1 for r in res if r[1] == P.CSK_OK)
+    worst = max(((x - sd["x_ref"]).norm() / sd["x_ref"].norm()).item() for x, sd in zip(xs, systems))
+    a_bytes = sum(sh.m * sh.n * 4 for sh in shapes)
+    log(f"[bench] batched: {t * 1e3:.1f} ms for {len(shapes)} systems, {ok} converged, worst rel {worst:.2e}")
+    del systems
+    torch.cuda.empty_cache()
+    return dict(time_s=t, systems=len(shapes), converged=ok, systems_per_s=len(shapes) / t, worst_relerr=worst,
+                total_iters=int(sum(r[0] for r in res)), a_bytes=a_bytes, redraws=redraws)
+
+
+def csr_workload(P, W, torch, solve=True):
+    """CSR A 1e6 x 5000 at 0.1%, d = 50000: sketch bandwidth, and the mixed
+    FP32 solve to 1e-8."""
+    c = W.config("sparse_csr")
+    dev = "cuda:0"
+    log("[bench] generating sparse_csr 1e6 x 5000 @ 0.1%")
+    s = W.sparse_csr(c["m"], c["n"], c["density"], c["seed"])
+    rp = torch.from_numpy(s.row_ptr).to(dev)
+    col = torch.from_numpy(s.col).to(dev)
+    val = torch.from_numpy(s.val).to(dev)
+    b = torch.from_numpy(s.b).to(dev)
+    xs = torch.from_numpy(s.x_star).to(dev)
+    run = lambda: P.csk_sketch_csr(rp, col, val, c["n"], b, c["d"], c["sketch_seed"], lp_dtype=torch.float32)
+    run()
+    t, sk = timed(run, 3)
+    nnz = int(s.row_ptr[-1])
+    byts = nnz * 8 + (c["m"] + 1) * 8 + c["m"] * 8 + c["d"] * c["n"] * (4 + 8) + 16 * c["d"]
+    out = dict(sketch_s=t, sketch_gbs=byts / t / 1e9, nnz=nnz)
+    log(f"[bench] sparse_csr sketch {t * 1e3:.2f} ms ({byts / t / 1e9:.0f} GB/s)")
+    if solve:
+        t2, (x, raw) = timed(lambda: P.csk_solve(sk.At_lp, sk.bt, At64=sk.At64, nu2=sk.nu2, x_ref=xs, tol=c["tol"],
+                                                 maxit=c["maxit"], sync=False))
+        it, st, fb, meas, nref = P.parse_results(raw)[0]
+        rel = ((x - xs).norm() / xs.norm()).item()
+        out.update(solve_s=t2, iters=it, status=P.csk_status_string(st), relerr=rel,
+                   us_per_iter=t2 / max(it, 1) * 1e6)
+        log(f"[bench] sparse_csr solve {t2:.3f} s iters={it} rel={rel:.2e} {P.csk_status_string(st)}")
+    del sk
+    torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--quick", action="store_true", help="main workload only (for profiling)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a design note, "
+              "not a measured path", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2004_02480_amd as P
+    from paper_2004_02480_amd import workloads as W
+
+    P.lib  # fails loudly if libcsk.so is missing
+    main_res, s, c = main_workload(args, P, W, torch)
+    extra = {}
+    cpu = None
+    if not args.quick:
+        if not args.no_cpu_baseline:
+            log("[bench] CPU oracle baseline (bounded sample)")
+            cpu = cpu_baseline(s, c, main_res["iters"])
+            log(f"[bench] cpu_baseline ~{cpu['value']:.1f} s ({cpu['sample']})")
+        del s
+        torch.cuda.empty_cache()
+        extra["row_scaled_mixed"] = mixed_workload(P, W, torch)
+        extra["sparse_csr"] = csr_workload(P, W, torch)
+        extra["batched_512"] = batched_workload(P, W, torch)
+
+    line = {
+        "metric": METRIC,
+        "value": main_res["total_s"],
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_res["total_s"] * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "dense_coherent", "m": main_res["m"], "n": main_res["n"], "d": main_res["d"],
+                   "dist": "U[0,1)", "tol": c["tol"], "parallelism": "single-gpu"},
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_solve_grid",
+            "achieved": main_res["solve_gbs"],
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": main_res["solve_gbs"] / HBM_PEAK_GBS,
+            "traffic": None,
+        },
+        "sketch": {"kernel_chain": "k_hash_hist..k_segsum", "time_s": main_res["sketch_s"],
+                   "gbs": main_res["sketch_gbs"], "frac": main_res["sketch_gbs"] / HBM_PEAK_GBS,
+                   "bytes": main_res["sketch_bytes"]},
+        "solve": {"time_s": main_res["solve_s"], "iters": main_res["iters"], "us_per_iter": main_res["us_per_iter"],
+                  "bytes_per_iter": main_res["iter_bytes"], "relerr": main_res["relerr"]},
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

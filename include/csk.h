@@ -1,0 +1,241 @@
+/*
+ * csk.h -- C ABI of libcsk, the MI355X (gfx950) implementation of the count
+ * sketch Kaczmarz (CSK) method of Zhang & Li, "A Count Sketch Kaczmarz
+ * Method For Solving Large Overdetermined Linear Systems" (arXiv 2004.02480).
+ *
+ * The method (Algorithm 1 of the paper) solves a consistent overdetermined
+ * system A x = b, A in R^{m x n}, m >> n (Section 1, eq. (1)) in two steps:
+ *   1. Initialize: draw a count sketch transform S = Phi D in R^{d x m}
+ *      (Definition 1: a random map h:[m]->[d] and random signs D_ii = +-1)
+ *      and form At = S A (d x n) and bt = S b (d);
+ *   2. Loop: i_k = argmax_i |bt_i - At^(i) x_k| / ||At^(i)||_2, then
+ *      x_{k+1} = x_k + (bt_{i_k} - At^(i_k) x_k) / ||At^(i_k)||^2 At^(i_k)^T,
+ *      until the stopping rule of Section 3 holds.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers are DEVICE pointers unless marked (host).  Matrices are
+ *    row-major with an explicit leading dimension (elements between row
+ *    starts, >= the row length).  Indices are 0-based.
+ *  - The caller owns every buffer.  The library allocates no device memory
+ *    on these paths: scratch space is the caller's workspace `ws` of
+ *    `ws_bytes` bytes (size from the matching *_workspace_size query; the
+ *    pointer must be 256-byte aligned).  Nothing is retained past the
+ *    stream-ordered work.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Every call is asynchronous: it validates its arguments on the host,
+ *    enqueues kernels on `stream` and returns.  A CSK_ERR_* return from the
+ *    call itself means nothing was enqueued (argument errors) or a launch
+ *    failed (CSK_ERR_DEVICE).  Outcomes decided on the device (converged,
+ *    not converged, non-finite data, degenerate sketch, cancelled) are
+ *    written to a csk_solve_result in device memory.
+ *  - Calls are reentrant; concurrent calls must use distinct workspaces.
+ *  - Determinism: for fixed inputs, sizes and launch configuration every
+ *    output is bitwise reproducible run to run.
+ *
+ * The hash (the concrete random generator behind Definition 1)
+ * ------------------------------------------------------------
+ * The paper fixes only the distribution of h and D.  This library draws,
+ * for input row i (0-based) and a 64-bit seed, the word
+ *     w_i = M(seed + (i+1) * 0x9E3779B97F4A7C15)      (mod 2^64)
+ * where M is the SplitMix64 output function (Steele, Lea & Flood, OOPSLA
+ * 2014): z ^= z>>30; z *= 0xBF58476D1CE4E5B9; z ^= z>>27;
+ * z *= 0x94D049BB133111EB; z ^= z>>31.  (w_i is the (i+1)-th output of a
+ * SplitMix64 generator seeded with `seed`.)  Then
+ *     h(i) = ((w_i >> 32) * d) >> 32           (bucket in [0, d))
+ *     D_ii = -1 if (w_i & 1) else +1.
+ *
+ * Sketch summation order (what makes At bit-exact)
+ * ------------------------------------------------
+ * At[j][c] is the sequential FP64 sum, starting at +0.0, of D_ii * A[i][c]
+ * over the rows i with h(i) = j taken in ASCENDING i.  FP32 input is widened
+ * exactly first.  Low-precision copies are rounded from that FP64 value in
+ * two round-to-nearest-even steps: FP64 -> FP32 -> (BF16 | FP16).
+ */
+#ifndef CSK_H
+#define CSK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+typedef int32_t csk_status;
+#define CSK_OK 0               /* converged / call succeeded                  */
+#define CSK_NOT_CONVERGED 1    /* maxit projections applied; x is valid       */
+#define CSK_ERR_INVALID_ARG 2  /* bad size, pointer, leading dimension, mode  */
+#define CSK_ERR_UNSUPPORTED 3  /* dtype or shape combination not built        */
+#define CSK_ERR_DEVICE 4       /* a HIP call failed (message: csk_last_error) */
+#define CSK_ERR_WORKSPACE 5    /* ws_bytes smaller than the query's answer    */
+#define CSK_ERR_NONFINITE 6    /* a weighted residual was NaN or infinite     */
+#define CSK_ERR_DEGENERATE 7   /* every row of At has zero norm               */
+#define CSK_CANCELLED 8        /* the cancel word became nonzero              */
+
+/* ---- element types ----------------------------------------------------- */
+typedef int32_t csk_dtype;
+#define CSK_F64 0
+#define CSK_F32 1
+#define CSK_F16 2   /* IEEE binary16 */
+#define CSK_BF16 3  /* bfloat16 (1-8-7) */
+
+/* ---- stopping rules ---------------------------------------------------- */
+/* CSK_STOP_REL_ERR: Section 3's relative solution error
+ *   RES = ||x_k - x_ref||^2 / ||x_ref||^2 <= tol^2  (tol on the unsquared
+ *   relative error; if ||x_ref|| = 0, ||x_k||^2 <= tol^2).  Needs x_ref.
+ * CSK_STOP_REL_RESID: ||bt - At x_k||_2 <= tol ||bt||_2 (sketched residual;
+ *   a project choice for callers without a reference solution).
+ * Both are tested at the top of iteration k, before the k-th projection, so
+ * `iters` counts the projections applied. */
+#define CSK_STOP_REL_ERR 0
+#define CSK_STOP_REL_RESID 1
+
+typedef struct csk_solve_opts {
+    double tol;              /* see the stopping rules above                     */
+    int64_t maxit;           /* at most this many projections (>= 0)             */
+    int32_t stop_mode;       /* CSK_STOP_REL_ERR or CSK_STOP_REL_RESID            */
+    int32_t refresh_every;   /* mixed precision: exact FP64 residual every K
+                                iterations (0 -> 64)                             */
+    const double* x_ref;     /* n, device; required for CSK_STOP_REL_ERR         */
+    const volatile int32_t* cancel; /* nullable; host-mapped pinned or device
+                                word polled every check_every iterations; a
+                                nonzero value ends the solve with CSK_CANCELLED */
+    int32_t check_every;     /* cancel poll interval (0 -> 256)                  */
+    int32_t grid;            /* persistent grid size; 0 -> automatic             */
+    int32_t block;           /* threads per workgroup; 0 -> automatic            */
+    int32_t single_wg;       /* -1 auto, 0 force grid path, 1 force one WG       */
+} csk_solve_opts;
+
+/* Written by the device at the end of a solve (device memory). */
+typedef struct csk_solve_result {
+    int64_t iters;           /* projections applied                               */
+    int32_t status;          /* CSK_OK, CSK_NOT_CONVERGED, CSK_ERR_NONFINITE,
+                                CSK_ERR_DEGENERATE or CSK_CANCELLED               */
+    int32_t fp64_fallback;   /* mixed precision: 1 if the solve finished in
+                                plain FP64 iterations after stagnating            */
+    double final_measure;    /* the stop measure at exit: RES (REL_ERR) or
+                                ||r||^2/||bt||^2 (REL_RESID)                      */
+    int64_t refreshes;       /* mixed precision: exact residual refreshes         */
+} csk_solve_result;
+
+/* Static text for a status code. */
+const char* csk_status_string(csk_status s);
+/* Text of the last host-side failure on the calling thread ("" if none). */
+const char* csk_last_error(void);
+/* ABI version (major*10000 + minor*100 + patch). */
+int32_t csk_version(void);
+
+/* ---- A1: the hash alone (Definition 1) --------------------------------- *
+ * bucket[i] = h(i) and sign[i] = D_ii for i in [0, m).  Either output may be
+ * NULL.  Requires m >= 1, 1 <= d < 2^31.                                     */
+csk_status csk_hash(uint64_t seed, int64_t m, int64_t d, uint32_t* bucket, int8_t* sign,
+                    void* stream);
+
+/* ---- A1-A5: the dense sketch (Algorithm 1, Initialize) ----------------- *
+ * Computes At = S A and Bt = S B for the A (m x n, dtype a_dtype in {F64,
+ * F32}, leading dimension lda) and optional B (m x nrhs FP64, leading
+ * dimension ldb; nrhs = 1 for the vector b of Algorithm 1).
+ * Outputs (each nullable, at least one of At64 / At_lp non-NULL):
+ *   At64   d x n FP64, leading dimension ldat64;
+ *   At_lp  d x n in lp_dtype (F32, F16 or BF16), leading dimension ldat_lp,
+ *          the two-step RNE rounding of the FP64 sketch;
+ *   Bt     d x nrhs FP64, leading dimension ldbt (required when B is given);
+ *   nu2    d FP64: ||At64^(j)||^2, the squared norm of the FP64 row (zero for
+ *          empty buckets), computed from the FP64 sums even if At64 is NULL;
+ *   perm   m u32: rows grouped by bucket, ascending within a bucket;
+ *   ptr    d+1 u32: bucket j owns perm[ptr[j] .. ptr[j+1]), ptr[d] = m.
+ * Requires 1 <= m < 2^31, n >= 1, 1 <= d < 2^31, lda >= n.  The paper asks
+ * for d < m; that is recommended, not enforced (the sketch stays defined).  */
+csk_status csk_sketch_workspace_size(int64_t m, int64_t n, int64_t d, int64_t nrhs, size_t* bytes /*host*/);
+csk_status csk_sketch(const void* A, csk_dtype a_dtype, int64_t m, int64_t n, int64_t lda,
+                      const double* B, int64_t nrhs, int64_t ldb,
+                      int64_t d, uint64_t seed,
+                      double* At64, int64_t ldat64,
+                      void* At_lp, csk_dtype lp_dtype, int64_t ldat_lp,
+                      double* Bt, int64_t ldbt,
+                      double* nu2, uint32_t* perm, uint32_t* ptr,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* ---- A10: the sketch of a CSR matrix ------------------------------------ *
+ * A given as row_ptr (m+1, int64, row_ptr[0] = 0, nondecreasing), col (nnz,
+ * int32 in [0, n), distinct within a row) and val (nnz, FP32).  Same outputs
+ * and summation order as csk_sketch (each dense entry of At is the ascending-
+ * row sum of the stored entries that land on it; absent entries add nothing).
+ * b (m FP64) and bt (d FP64) are nullable together.                          */
+csk_status csk_sketch_csr_workspace_size(int64_t m, int64_t n, int64_t d, size_t* bytes /*host*/);
+csk_status csk_sketch_csr(const int64_t* row_ptr, const int32_t* col, const float* val,
+                          int64_t m, int64_t n, int64_t nnz, const double* b,
+                          int64_t d, uint64_t seed,
+                          double* At64, int64_t ldat64,
+                          void* At_lp, csk_dtype lp_dtype, int64_t ldat_lp,
+                          double* bt, double* nu2,
+                          void* ws, size_t ws_bytes, void* stream);
+
+/* ---- A6/A7: the MWRK loop on the sketched system (Algorithm 1, loop) ---- *
+ * at_dtype = F64: At is the FP64 sketch (At64 may be NULL or equal to At);
+ *   plain FP64 iterations.
+ * at_dtype in {F32, F16, BF16}: mixed precision.  At is the low-precision
+ *   sketch and At64 (required) the FP64 one.  Every refresh_every iterations
+ *   the exact residual r_ref = bt - At64 x is recomputed in FP64 and x_ref
+ *   saved; in between r = r_ref - At * (x - x_ref) with FP32 accumulation.
+ *   Selection weights and projections use the FP64 row and nu2.  If the
+ *   exact stop measure fails to decrease over two refresh windows the solve
+ *   continues with plain FP64 iterations (result.fp64_fallback = 1).
+ * nu2: d FP64 squared row norms of At64 (nullable: computed into ws).
+ * x0: n FP64 start (nullable: zero, as in Section 3).  x: n FP64 output.
+ * Rows of zero norm are never selected; ties go to the lowest row index.
+ * Requires d >= 1, 1 <= n <= 8192, ldat >= n, d < 2^31.                      */
+csk_status csk_solve_workspace_size(int64_t d, int64_t n, csk_dtype at_dtype, size_t* bytes /*host*/);
+csk_status csk_solve(const void* At, csk_dtype at_dtype, int64_t ldat,
+                     const double* At64, int64_t ldat64,
+                     int64_t d, int64_t n, const double* bt, const double* nu2,
+                     const double* x0, double* x,
+                     const csk_solve_opts* opts /*host*/, csk_solve_result* res,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/* ---- A8: many independent systems, sketch + solve in one pass ---------- *
+ * Each descriptor (host array) names one system's device buffers.  A is
+ * a_dtype (F64 or F32); the solve runs in lp_dtype (F64 = plain, else mixed
+ * with an FP64 copy kept in ws) with opts shared by all systems (x_ref in
+ * opts is ignored; each system has its own).  res: nsys results (device).  */
+typedef struct csk_system_desc {
+    const void* A;        /* m x n, leading dimension lda                        */
+    const double* b;      /* m                                                   */
+    const double* x_ref;  /* n, or NULL (then the system uses CSK_STOP_REL_RESID) */
+    double* x;            /* n, output                                           */
+    int64_t m, n, lda, d;
+    uint64_t seed;
+} csk_system_desc;
+csk_status csk_solve_batched_workspace_size(const csk_system_desc* sys /*host*/, int32_t nsys,
+                                            csk_dtype a_dtype, csk_dtype lp_dtype, size_t* bytes /*host*/);
+csk_status csk_solve_batched(const csk_system_desc* sys /*host*/, int32_t nsys,
+                             csk_dtype a_dtype, csk_dtype lp_dtype,
+                             const csk_solve_opts* opts /*host*/, csk_solve_result* res,
+                             void* ws, size_t ws_bytes, void* stream);
+
+/* ---- A9: one sketch, many right-hand sides ----------------------------- *
+ * Runs the loop of Algorithm 1 independently for each column j of Bt (d x
+ * nrhs FP64) on the shared At: X[:, j] (n x nrhs, leading dimension ldx)
+ * solves At X[:, j] = Bt[:, j].  The residuals of all columns are formed
+ * together as R = R_ref - At_lp (X - X_ref) with At_lp in BF16 or F16 on the
+ * matrix cores (FP32 accumulation) and an exact FP64 refresh
+ * R_ref = Bt - At64 X_ref every refresh_every iterations.  Xref (n x nrhs,
+ * leading dimension ldxref) is the reference for CSK_STOP_REL_ERR (per
+ * column).  res: nrhs results (device).  Requires n <= 1024.                */
+csk_status csk_solve_mrhs_workspace_size(int64_t d, int64_t n, int64_t nrhs, size_t* bytes /*host*/);
+csk_status csk_solve_mrhs(const void* At_lp, csk_dtype lp_dtype, int64_t ldat_lp,
+                          const double* At64, int64_t ldat64,
+                          int64_t d, int64_t n,
+                          const double* Bt, int64_t nrhs, int64_t ldbt,
+                          const double* nu2,
+                          const double* X0, double* X, int64_t ldx,
+                          const double* Xref, int64_t ldxref,
+                          const csk_solve_opts* opts /*host*/, csk_solve_result* res,
+                          void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CSK_H */

@@ -1,0 +1,123 @@
+"""ctypes declarations of libcsk's C ABI (include/csk.h).
+
+Argument marshalling only: every computation happens in the HIP library.  If
+the library has not been built this module raises at import time; there is no
+fallback path.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcsk.so")
+
+# status codes
+CSK_OK = 0
+CSK_NOT_CONVERGED = 1
+CSK_ERR_INVALID_ARG = 2
+CSK_ERR_UNSUPPORTED = 3
+CSK_ERR_DEVICE = 4
+CSK_ERR_WORKSPACE = 5
+CSK_ERR_NONFINITE = 6
+CSK_ERR_DEGENERATE = 7
+CSK_CANCELLED = 8
+
+# dtypes
+CSK_F64 = 0
+CSK_F32 = 1
+CSK_F16 = 2
+CSK_BF16 = 3
+
+CSK_STOP_REL_ERR = 0
+CSK_STOP_REL_RESID = 1
+
+EXPORTED = [
+    "csk_status_string", "csk_last_error", "csk_version", "csk_hash",
+    "csk_sketch_workspace_size", "csk_sketch",
+    "csk_sketch_csr_workspace_size", "csk_sketch_csr",
+    "csk_solve_workspace_size", "csk_solve",
+    "csk_solve_batched_workspace_size", "csk_solve_batched",
+    "csk_solve_mrhs_workspace_size", "csk_solve_mrhs",
+]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [
+        ("tol", ctypes.c_double),
+        ("maxit", ctypes.c_int64),
+        ("stop_mode", ctypes.c_int32),
+        ("refresh_every", ctypes.c_int32),
+        ("x_ref", ctypes.c_void_p),
+        ("cancel", ctypes.c_void_p),
+        ("check_every", ctypes.c_int32),
+        ("grid", ctypes.c_int32),
+        ("block", ctypes.c_int32),
+        ("single_wg", ctypes.c_int32),
+    ]
+
+
+class SystemDesc(ctypes.Structure):
+    _fields_ = [
+        ("A", ctypes.c_void_p),
+        ("b", ctypes.c_void_p),
+        ("x_ref", ctypes.c_void_p),
+        ("x", ctypes.c_void_p),
+        ("m", ctypes.c_int64),
+        ("n", ctypes.c_int64),
+        ("lda", ctypes.c_int64),
+        ("d", ctypes.c_int64),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
+# csk_solve_result: int64 iters; int32 status; int32 fp64_fallback;
+# double final_measure; int64 refreshes  -> 32 bytes
+RESULT_BYTES = 32
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(
+            f"libcsk.so not found at {path}; build it first with "
+            "`python -c 'import __graft_entry__ as g; g.build()'` "
+            "or `python paper_2004_02480_amd/build.py`")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    I64 = ctypes.c_int64
+    I32 = ctypes.c_int32
+    U64 = ctypes.c_uint64
+    SZ = ctypes.c_size_t
+    PSZ = ctypes.POINTER(ctypes.c_size_t)
+    lib.csk_status_string.restype = ctypes.c_char_p
+    lib.csk_status_string.argtypes = [I32]
+    lib.csk_last_error.restype = ctypes.c_char_p
+    lib.csk_last_error.argtypes = []
+    lib.csk_version.restype = I32
+    lib.csk_version.argtypes = []
+    lib.csk_hash.restype = I32
+    lib.csk_hash.argtypes = [U64, I64, I64, P, P, P]
+    lib.csk_sketch_workspace_size.restype = I32
+    lib.csk_sketch_workspace_size.argtypes = [I64, I64, I64, I64, PSZ]
+    lib.csk_sketch.restype = I32
+    lib.csk_sketch.argtypes = [P, I32, I64, I64, I64, P, I64, I64, I64, U64,
+                               P, I64, P, I32, I64, P, I64, P, P, P, P, SZ, P]
+    lib.csk_sketch_csr_workspace_size.restype = I32
+    lib.csk_sketch_csr_workspace_size.argtypes = [I64, I64, I64, PSZ]
+    lib.csk_sketch_csr.restype = I32
+    lib.csk_sketch_csr.argtypes = [P, P, P, I64, I64, I64, P, I64, U64,
+                                   P, I64, P, I32, I64, P, P, P, SZ, P]
+    lib.csk_solve_workspace_size.restype = I32
+    lib.csk_solve_workspace_size.argtypes = [I64, I64, I32, PSZ]
+    lib.csk_solve.restype = I32
+    lib.csk_solve.argtypes = [P, I32, I64, P, I64, I64, I64, P, P, P, P,
+                              ctypes.POINTER(SolveOpts), P, P, SZ, P]
+    lib.csk_solve_batched_workspace_size.restype = I32
+    lib.csk_solve_batched_workspace_size.argtypes = [ctypes.POINTER(SystemDesc), I32, I32, I32, PSZ]
+    lib.csk_solve_batched.restype = I32
+    lib.csk_solve_batched.argtypes = [ctypes.POINTER(SystemDesc), I32, I32, I32,
+                                      ctypes.POINTER(SolveOpts), P, P, SZ, P]
+    lib.csk_solve_mrhs_workspace_size.restype = I32
+    lib.csk_solve_mrhs_workspace_size.argtypes = [I64, I64, I64, PSZ]
+    lib.csk_solve_mrhs.restype = I32
+    lib.csk_solve_mrhs.argtypes = [P, I32, I64, P, I64, I64, I64, P, I64, I64, P,
+                                   P, P, I64, P, I64, ctypes.POINTER(SolveOpts), P, P, SZ, P]
+    return lib

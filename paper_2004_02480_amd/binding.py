@@ -1,0 +1,327 @@
+"""Python binding of libcsk (count sketch Kaczmarz on AMD MI355X).
+
+Thin layer over the C ABI in ``include/csk.h``: the functions below carry the
+same names as the C entry points, take PyTorch tensors (device memory) and
+the current HIP stream, allocate outputs and workspace with PyTorch, and
+raise :class:`CskError` on a failing status.  All arithmetic of the method
+runs in the HIP kernels of ``libcsk.so``; there is no fallback path.
+
+Method (Zhang & Li, arXiv 2004.02480, Algorithm 1): sketch ``At = S A``,
+``bt = S b`` with the count sketch of Definition 1, then run the maximal
+weighted residual Kaczmarz loop on ``(At, bt)``.
+"""
+import ctypes
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import torch
+
+from . import _abi
+from ._abi import (CSK_BF16, CSK_CANCELLED, CSK_ERR_DEGENERATE, CSK_ERR_DEVICE,  # noqa: F401
+                   CSK_ERR_INVALID_ARG, CSK_ERR_NONFINITE, CSK_ERR_UNSUPPORTED,
+                   CSK_ERR_WORKSPACE, CSK_F16, CSK_F32, CSK_F64, CSK_NOT_CONVERGED, CSK_OK,
+                   CSK_STOP_REL_ERR, CSK_STOP_REL_RESID)
+
+_lib = _abi.load()
+
+__all__ = ["CskError", "SketchOut", "SolveResult", "csk_hash", "csk_sketch", "csk_sketch_csr",
+           "csk_solve", "csk_solve_batched", "csk_solve_mrhs", "csk_status_string", "lib"]
+
+lib = _lib
+
+_TORCH_TO_CSK = {torch.float64: CSK_F64, torch.float32: CSK_F32,
+                 torch.float16: CSK_F16, torch.bfloat16: CSK_BF16}
+_CSK_TO_TORCH = {v: k for k, v in _TORCH_TO_CSK.items()}
+
+
+class CskError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = _lib.csk_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {csk_status_string(status)}" + (f" ({msg})" if msg else ""))
+
+
+def csk_status_string(status: int) -> str:
+    return _lib.csk_status_string(int(status)).decode()
+
+
+def _check(status: int, where: str):
+    if status != CSK_OK:
+        raise CskError(status, where)
+
+
+def _stream(stream=None) -> ctypes.c_void_p:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    buf = torch.empty(int(nbytes) + 512, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf[off:off + int(nbytes) + 256]
+
+
+def _need_cuda(t: torch.Tensor, name: str):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda):
+        raise ValueError(f"{name} must be a device tensor")
+
+
+def _rowmajor(t: torch.Tensor, name: str) -> int:
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError(f"{name} must be a 2-D tensor with unit column stride")
+    return t.stride(0)
+
+
+def csk_hash(seed: int, m: int, d: int, *, device="cuda", stream=None):
+    """(bucket, sign): h(i) as int32 (values < d) and D_ii as int8, Definition 1."""
+    bucket = torch.empty(m, dtype=torch.int32, device=device)
+    sign = torch.empty(m, dtype=torch.int8, device=device)
+    _check(_lib.csk_hash(ctypes.c_uint64(seed & (2**64 - 1)), m, d, _ptr(bucket), _ptr(sign),
+                         _stream(stream)), "csk_hash")
+    return bucket, sign
+
+
+@dataclass
+class SketchOut:
+    At64: Optional[torch.Tensor]
+    At_lp: Optional[torch.Tensor]
+    bt: Optional[torch.Tensor]
+    nu2: torch.Tensor
+    perm: Optional[torch.Tensor]
+    ptr: Optional[torch.Tensor]
+
+
+def csk_sketch(A: torch.Tensor, b: Optional[torch.Tensor], d: int, seed: int, *,
+               lp_dtype: Optional[torch.dtype] = None, want_f64: bool = True,
+               want_perm: bool = False, stream=None) -> SketchOut:
+    """At = S A and bt = S b (Algorithm 1, Initialize).
+
+    A: m x n, float64 or float32, row-major.  b: m (vector) or m x nrhs,
+    float64, or None.  lp_dtype: also return the low-precision copy."""
+    _need_cuda(A, "A")
+    if A.dtype not in (torch.float64, torch.float32):
+        raise ValueError("A must be float64 or float32")
+    lda = _rowmajor(A, "A")
+    m, n = A.shape
+    dev = A.device
+    At64 = torch.empty((d, n), dtype=torch.float64, device=dev) if want_f64 else None
+    At_lp = torch.empty((d, n), dtype=lp_dtype, device=dev) if lp_dtype is not None else None
+    if At64 is None and At_lp is None:
+        raise ValueError("nothing to compute")
+    nu2 = torch.empty(d, dtype=torch.float64, device=dev)
+    B = bt = None
+    nrhs, ldb, ldbt = 0, 1, 1
+    if b is not None:
+        _need_cuda(b, "b")
+        if b.dtype != torch.float64:
+            raise ValueError("b must be float64")
+        if b.dim() == 1:
+            B = b.contiguous()
+            nrhs, ldb = 1, 1
+            bt = torch.empty(d, dtype=torch.float64, device=dev)
+            ldbt = 1
+        else:
+            B = b
+            nrhs = b.shape[1]
+            ldb = _rowmajor(b, "b")
+            bt = torch.empty((d, nrhs), dtype=torch.float64, device=dev)
+            ldbt = nrhs
+    perm = torch.empty(m, dtype=torch.int32, device=dev) if want_perm else None
+    ptr = torch.empty(d + 1, dtype=torch.int32, device=dev) if want_perm else None
+    nbytes = ctypes.c_size_t(0)
+    _check(_lib.csk_sketch_workspace_size(m, n, d, nrhs, ctypes.byref(nbytes)), "csk_sketch_workspace_size")
+    ws = _workspace(nbytes.value, dev)
+    lp_code = _TORCH_TO_CSK[lp_dtype] if lp_dtype is not None else CSK_F64
+    _check(_lib.csk_sketch(_ptr(A), _TORCH_TO_CSK[A.dtype], m, n, lda, _ptr(B), nrhs, ldb, d,
+                           ctypes.c_uint64(seed & (2**64 - 1)),
+                           _ptr(At64), n, _ptr(At_lp), lp_code, n, _ptr(bt), ldbt, _ptr(nu2),
+                           _ptr(perm), _ptr(ptr), _ptr(ws), ws.numel(), _stream(stream)), "csk_sketch")
+    return SketchOut(At64, At_lp, bt, nu2, perm, ptr)
+
+
+def csk_sketch_csr(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, n: int,
+                   b: Optional[torch.Tensor], d: int, seed: int, *,
+                   lp_dtype: Optional[torch.dtype] = None, want_f64: bool = True,
+                   stream=None) -> SketchOut:
+    """Dense (At, bt) from a CSR A (int64 row_ptr, int32 col, float32 val)."""
+    for t, nm in ((row_ptr, "row_ptr"), (col, "col"), (val, "val")):
+        _need_cuda(t, nm)
+    if row_ptr.dtype != torch.int64 or col.dtype != torch.int32 or val.dtype != torch.float32:
+        raise ValueError("row_ptr int64, col int32, val float32 expected")
+    m = row_ptr.numel() - 1
+    nnz = col.numel()
+    dev = row_ptr.device
+    At64 = torch.empty((d, n), dtype=torch.float64, device=dev) if want_f64 else None
+    At_lp = torch.empty((d, n), dtype=lp_dtype, device=dev) if lp_dtype is not None else None
+    nu2 = torch.empty(d, dtype=torch.float64, device=dev)
+    bt = torch.empty(d, dtype=torch.float64, device=dev) if b is not None else None
+    nbytes = ctypes.c_size_t(0)
+    _check(_lib.csk_sketch_csr_workspace_size(m, n, d, ctypes.byref(nbytes)), "csk_sketch_csr_workspace_size")
+    ws = _workspace(nbytes.value, dev)
+    lp_code = _TORCH_TO_CSK[lp_dtype] if lp_dtype is not None else CSK_F64
+    _check(_lib.csk_sketch_csr(_ptr(row_ptr), _ptr(col), _ptr(val), m, n, nnz,
+                               _ptr(b.contiguous() if b is not None else None), d,
+                               ctypes.c_uint64(seed & (2**64 - 1)), _ptr(At64), n, _ptr(At_lp), lp_code, n,
+                               _ptr(bt), _ptr(nu2), _ptr(ws), ws.numel(), _stream(stream)), "csk_sketch_csr")
+    return SketchOut(At64, At_lp, bt, nu2, None, None)
+
+
+@dataclass
+class SolveResult:
+    x: torch.Tensor
+    iters: int
+    status: int
+    fp64_fallback: int
+    final_measure: float
+    refreshes: int
+
+    @property
+    def status_name(self) -> str:
+        return csk_status_string(self.status)
+
+
+def parse_results(raw: torch.Tensor) -> List[tuple]:
+    """Decode csk_solve_result records (device or host uint8 tensor)."""
+    host = raw.cpu().numpy()
+    out = []
+    import numpy as np
+    for k in range(host.size // _abi.RESULT_BYTES):
+        rec = host[k * _abi.RESULT_BYTES:(k + 1) * _abi.RESULT_BYTES]
+        iters = int(np.frombuffer(rec[0:8].tobytes(), np.int64)[0])
+        status, fb = (int(v) for v in np.frombuffer(rec[8:16].tobytes(), np.int32))
+        meas = float(np.frombuffer(rec[16:24].tobytes(), np.float64)[0])
+        nref = int(np.frombuffer(rec[24:32].tobytes(), np.int64)[0])
+        out.append((iters, status, fb, meas, nref))
+    return out
+
+
+def _opts(tol, maxit, stop_mode, refresh_every, x_ref, cancel, check_every, grid, single_wg):
+    o = _abi.SolveOpts()
+    o.tol = float(tol)
+    o.maxit = int(maxit)
+    o.stop_mode = int(stop_mode)
+    o.refresh_every = int(refresh_every)
+    o.x_ref = None if x_ref is None else x_ref.data_ptr()
+    o.cancel = None if cancel is None else int(cancel)
+    o.check_every = int(check_every)
+    o.grid = int(grid)
+    o.block = 0
+    o.single_wg = int(single_wg)
+    return o
+
+
+def csk_solve(At: torch.Tensor, bt: torch.Tensor, *, At64: Optional[torch.Tensor] = None,
+              nu2: Optional[torch.Tensor] = None, x0: Optional[torch.Tensor] = None,
+              x_ref: Optional[torch.Tensor] = None, tol: float = 1e-10, maxit: int = 100000,
+              stop_mode: Optional[int] = None, refresh_every: int = 64, cancel: Optional[int] = None,
+              check_every: int = 256, grid: int = 0, single_wg: int = -1,
+              out: Optional[torch.Tensor] = None, result: Optional[torch.Tensor] = None,
+              workspace: Optional[torch.Tensor] = None, sync: bool = True, stream=None):
+    """MWRK on (At, bt) (Algorithm 1, loop).
+
+    At: d x n float64 (plain) or float32/float16/bfloat16 (mixed, At64 required).
+    Returns a SolveResult when sync=True, else (x, raw_result_tensor)."""
+    _need_cuda(At, "At")
+    ldat = _rowmajor(At, "At")
+    d, n = At.shape
+    at_code = _TORCH_TO_CSK[At.dtype]
+    ldat64 = ldat
+    if At64 is not None:
+        ldat64 = _rowmajor(At64, "At64")
+    if stop_mode is None:
+        stop_mode = CSK_STOP_REL_ERR if x_ref is not None else CSK_STOP_REL_RESID
+    dev = At.device
+    x = out if out is not None else torch.empty(n, dtype=torch.float64, device=dev)
+    res = result if result is not None else torch.zeros(_abi.RESULT_BYTES, dtype=torch.uint8, device=dev)
+    if workspace is None:
+        nbytes = ctypes.c_size_t(0)
+        _check(_lib.csk_solve_workspace_size(d, n, at_code, ctypes.byref(nbytes)), "csk_solve_workspace_size")
+        workspace = _workspace(nbytes.value, dev)
+    o = _opts(tol, maxit, stop_mode, refresh_every, x_ref, cancel, check_every, grid, single_wg)
+    _check(_lib.csk_solve(_ptr(At), at_code, ldat, _ptr(At64), ldat64, d, n, _ptr(bt), _ptr(nu2), _ptr(x0),
+                          _ptr(x), ctypes.byref(o), _ptr(res), _ptr(workspace), workspace.numel(),
+                          _stream(stream)), "csk_solve")
+    if not sync:
+        return x, res
+    (stream or torch.cuda.current_stream()).synchronize()
+    it, st, fb, meas, nref = parse_results(res)[0]
+    return SolveResult(x, it, st, fb, meas, nref)
+
+
+def csk_solve_batched(systems: Sequence[dict], *, lp_dtype: torch.dtype = torch.float32, tol: float = 1e-8,
+                      maxit: int = 200000, refresh_every: int = 64, sync: bool = True, stream=None):
+    """Sketch and solve many independent systems in one pass.
+
+    Each system is a dict with A (m x n, float32 or float64), b (m float64),
+    d, seed and optional x_ref (n float64).  Returns (xs, results)."""
+    nsys = len(systems)
+    a_dtype = systems[0]["A"].dtype
+    descs = (_abi.SystemDesc * nsys)()
+    xs = []
+    keep = []
+    for s, sysd in enumerate(systems):
+        A = sysd["A"]
+        if A.dtype != a_dtype:
+            raise ValueError("all systems must share A's dtype")
+        _need_cuda(A, "A")
+        lda = _rowmajor(A, "A")
+        m, n = A.shape
+        b = sysd["b"].contiguous()
+        xr = sysd.get("x_ref")
+        x = torch.empty(n, dtype=torch.float64, device=A.device)
+        xs.append(x)
+        keep += [A, b, xr]
+        dsc = descs[s]
+        dsc.A = A.data_ptr()
+        dsc.b = b.data_ptr()
+        dsc.x_ref = None if xr is None else xr.data_ptr()
+        dsc.x = x.data_ptr()
+        dsc.m, dsc.n, dsc.lda, dsc.d = m, n, lda, int(sysd["d"])
+        dsc.seed = int(sysd["seed"]) & (2**64 - 1)
+    dev = systems[0]["A"].device
+    a_code = _TORCH_TO_CSK[a_dtype]
+    lp_code = _TORCH_TO_CSK[lp_dtype]
+    nbytes = ctypes.c_size_t(0)
+    _check(_lib.csk_solve_batched_workspace_size(descs, nsys, a_code, lp_code, ctypes.byref(nbytes)),
+           "csk_solve_batched_workspace_size")
+    ws = _workspace(nbytes.value, dev)
+    res = torch.zeros(_abi.RESULT_BYTES * nsys, dtype=torch.uint8, device=dev)
+    o = _opts(tol, maxit, CSK_STOP_REL_ERR, refresh_every, None, None, 256, 0, -1)
+    _check(_lib.csk_solve_batched(descs, nsys, a_code, lp_code, ctypes.byref(o), _ptr(res), _ptr(ws),
+                                  ws.numel(), _stream(stream)), "csk_solve_batched")
+    if not sync:
+        return xs, res, ws
+    (stream or torch.cuda.current_stream()).synchronize()
+    return xs, parse_results(res)
+
+
+def csk_solve_mrhs(At_lp: torch.Tensor, At64: torch.Tensor, Bt: torch.Tensor, nu2: torch.Tensor, *,
+                   X0: Optional[torch.Tensor] = None, Xref: Optional[torch.Tensor] = None,
+                   tol: float = 1e-8, maxit: int = 200000, refresh_every: int = 64,
+                   stop_mode: Optional[int] = None, sync: bool = True, stream=None):
+    """Solve At X[:, j] = Bt[:, j] for every column j (shared sketch)."""
+    _need_cuda(At_lp, "At_lp")
+    d, n = At_lp.shape
+    nrhs = Bt.shape[1]
+    dev = At_lp.device
+    if stop_mode is None:
+        stop_mode = CSK_STOP_REL_ERR if Xref is not None else CSK_STOP_REL_RESID
+    X = torch.empty((n, nrhs), dtype=torch.float64, device=dev)
+    nbytes = ctypes.c_size_t(0)
+    _check(_lib.csk_solve_mrhs_workspace_size(d, n, nrhs, ctypes.byref(nbytes)), "csk_solve_mrhs_workspace_size")
+    ws = _workspace(nbytes.value, dev)
+    res = torch.zeros(_abi.RESULT_BYTES * nrhs, dtype=torch.uint8, device=dev)
+    o = _opts(tol, maxit, stop_mode, refresh_every, None, None, 256, 0, -1)
+    _check(_lib.csk_solve_mrhs(_ptr(At_lp), _TORCH_TO_CSK[At_lp.dtype], _rowmajor(At_lp, "At_lp"), _ptr(At64),
+                               _rowmajor(At64, "At64"), d, n, _ptr(Bt), nrhs, _rowmajor(Bt, "Bt"), _ptr(nu2),
+                               _ptr(X0), _ptr(X), nrhs, _ptr(Xref), nrhs if Xref is not None else 0,
+                               ctypes.byref(o), _ptr(res), _ptr(ws), ws.numel(), _stream(stream)),
+           "csk_solve_mrhs")
+    if not sync:
+        return X, res
+    (stream or torch.cuda.current_stream()).synchronize()
+    return X, parse_results(res)

@@ -1,0 +1,495 @@
+// csk_api.hip -- the extern "C" boundary of libcsk (declared in csk.h):
+// argument validation, workspace layout and the launch sequence of each
+// entry point.  All compute happens in the kernels of sketch.hip,
+// sketch_csr.hip, solve.hip and mrhs.hip.
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <vector>
+
+#include "csk_sketch.h"
+#include "csk_solve.h"
+#include "csk_mrhs.h"
+
+namespace csk {
+
+namespace {
+thread_local char g_err[512] = {0};
+}
+
+void set_error(const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+
+csk_status hip_fail(hipError_t e, const char* what)
+{
+    set_error("%s: %s", what, hipGetErrorString(e));
+    return CSK_ERR_DEVICE;
+}
+
+int device_cu_count()
+{
+    static std::mutex mu;
+    static std::vector<int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1;
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)cache.size() <= dev) cache.resize(dev + 1, 0);
+    if (cache[dev] == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+        cache[dev] = cus;
+    }
+    return cache[dev];
+}
+
+// ---- kernels local to the boundary --------------------------------------
+namespace {
+
+__global__ void k_hash_rows(uint64_t seed, int64_t m, uint32_t d, uint32_t* bucket, int8_t* sign)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t w = draw_word(seed, static_cast<uint64_t>(i));
+        if (bucket) bucket[i] = draw_bucket(w, d);
+        if (sign) sign[i] = (w & 1ull) ? int8_t(-1) : int8_t(1);
+    }
+}
+
+struct SysPack {
+    SolveSys s[24];
+};
+
+__global__ void k_store_solve_descs(SysPack pack, int count, SolveSys* dst)
+{
+    if ((int)threadIdx.x < count) dst[threadIdx.x] = pack.s[threadIdx.x];
+}
+
+struct OrderPack {
+    int32_t v[512];
+};
+
+__global__ void k_store_order(OrderPack pack, int count, int32_t* dst)
+{
+    for (int k = threadIdx.x; k < count; k += blockDim.x) dst[k] = pack.v[k];
+}
+
+hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+bool lp_ok(csk_dtype t) { return t == CSK_F32 || t == CSK_F16 || t == CSK_BF16; }
+
+constexpr int64_t kMaxN = 8192;
+
+csk_status check_opts(const csk_solve_opts* o)
+{
+    if (!o) { set_error("opts is NULL"); return CSK_ERR_INVALID_ARG; }
+    if (!(o->tol >= 0.0)) { set_error("tol must be >= 0"); return CSK_ERR_INVALID_ARG; }
+    if (o->maxit < 0) { set_error("maxit must be >= 0"); return CSK_ERR_INVALID_ARG; }
+    if (o->stop_mode != CSK_STOP_REL_ERR && o->stop_mode != CSK_STOP_REL_RESID) {
+        set_error("unknown stop_mode %d", o->stop_mode);
+        return CSK_ERR_INVALID_ARG;
+    }
+    if (o->refresh_every < 0 || o->check_every < 0 || o->grid < 0) {
+        set_error("refresh_every, check_every and grid must be >= 0");
+        return CSK_ERR_INVALID_ARG;
+    }
+    if (o->grid > 65536) { set_error("grid too large"); return CSK_ERR_INVALID_ARG; }
+    return CSK_OK;
+}
+
+// Batched layout: per system, a block of the workspace holding its sketch
+// (low-precision and FP64 copies with rows padded to 64 bytes), bt, nu2 and
+// the refresh residual.
+struct BatchLayout {
+    std::vector<int64_t> off_lp, off_64, off_bt, off_nu2, off_rref, ld_lp, ld_64;
+    size_t data_bytes = 0;
+};
+
+BatchLayout batch_layout(const csk_system_desc* sys, int32_t nsys, csk_dtype lp_dtype)
+{
+    BatchLayout L;
+    const size_t lpsz = dtype_size(lp_dtype);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        off = (off + 255) & ~size_t(255);
+        const size_t at = off;
+        off += bytes;
+        return (int64_t)at;
+    };
+    for (int s = 0; s < nsys; ++s) {
+        const int64_t n = sys[s].n, d = sys[s].d;
+        const int64_t ld64 = (n + 7) & ~int64_t(7);
+        const int64_t ldlp = (n + 31) & ~int64_t(31);
+        L.ld_64.push_back(ld64);
+        L.ld_lp.push_back(ldlp);
+        L.off_64.push_back(take((size_t)d * ld64 * 8));
+        L.off_lp.push_back(lp_dtype == CSK_F64 ? -1 : take((size_t)d * ldlp * lpsz));
+        L.off_bt.push_back(take((size_t)d * 8));
+        L.off_nu2.push_back(take((size_t)d * 8));
+        L.off_rref.push_back(take((size_t)d * 8));
+    }
+    L.data_bytes = (off + 255) & ~size_t(255);
+    return L;
+}
+
+csk_status check_batch(const csk_system_desc* sys, int32_t nsys, csk_dtype a_dtype, csk_dtype lp_dtype)
+{
+    if (!sys || nsys < 1) { set_error("need at least one system"); return CSK_ERR_INVALID_ARG; }
+    if (a_dtype != CSK_F64 && a_dtype != CSK_F32) { set_error("A must be F64 or F32"); return CSK_ERR_UNSUPPORTED; }
+    if (lp_dtype != CSK_F64 && !lp_ok(lp_dtype)) { set_error("bad lp_dtype"); return CSK_ERR_UNSUPPORTED; }
+    for (int s = 0; s < nsys; ++s) {
+        const csk_system_desc& D = sys[s];
+        if (!D.A || !D.b || !D.x) { set_error("system %d: A, b and x are required", s); return CSK_ERR_INVALID_ARG; }
+        if (D.m < 1 || D.n < 1 || D.d < 1 || D.lda < D.n || D.m >= INT32_MAX || D.d >= INT32_MAX) {
+            set_error("system %d: bad sizes (m=%lld n=%lld d=%lld lda=%lld)", s, (long long)D.m, (long long)D.n,
+                      (long long)D.d, (long long)D.lda);
+            return CSK_ERR_INVALID_ARG;
+        }
+        if (D.n > kMaxN) { set_error("system %d: n=%lld exceeds %lld", s, (long long)D.n, (long long)kMaxN); return CSK_ERR_UNSUPPORTED; }
+    }
+    return CSK_OK;
+}
+
+}  // namespace
+}  // namespace csk
+
+using namespace csk;
+
+extern "C" {
+
+const char* csk_status_string(csk_status s)
+{
+    switch (s) {
+    case CSK_OK: return "CSK_OK";
+    case CSK_NOT_CONVERGED: return "CSK_NOT_CONVERGED";
+    case CSK_ERR_INVALID_ARG: return "CSK_ERR_INVALID_ARG";
+    case CSK_ERR_UNSUPPORTED: return "CSK_ERR_UNSUPPORTED";
+    case CSK_ERR_DEVICE: return "CSK_ERR_DEVICE";
+    case CSK_ERR_WORKSPACE: return "CSK_ERR_WORKSPACE";
+    case CSK_ERR_NONFINITE: return "CSK_ERR_NONFINITE";
+    case CSK_ERR_DEGENERATE: return "CSK_ERR_DEGENERATE";
+    case CSK_CANCELLED: return "CSK_CANCELLED";
+    default: return "CSK_UNKNOWN_STATUS";
+    }
+}
+
+const char* csk_last_error(void) { return g_err; }
+
+int32_t csk_version(void) { return 10000; }
+
+csk_status csk_hash(uint64_t seed, int64_t m, int64_t d, uint32_t* bucket, int8_t* sign, void* stream)
+{
+    g_err[0] = 0;
+    if (m < 1 || d < 1 || d >= INT32_MAX) { set_error("need m >= 1 and 1 <= d < 2^31"); return CSK_ERR_INVALID_ARG; }
+    if (!bucket && !sign) return CSK_OK;
+    const int grid = (int)std::min<int64_t>((m + 255) / 256, 16384);
+    k_hash_rows<<<grid, 256, 0, as_stream(stream)>>>(seed, m, (uint32_t)d, bucket, sign);
+    CSK_LAUNCH_CHECK("k_hash_rows");
+    return CSK_OK;
+}
+
+csk_status csk_sketch_workspace_size(int64_t m, int64_t n, int64_t d, int64_t nrhs, size_t* bytes)
+{
+    g_err[0] = 0;
+    if (!bytes || m < 1 || n < 1 || d < 1 || nrhs < 0) { set_error("bad sizes"); return CSK_ERR_INVALID_ARG; }
+    const int64_t T = d * std::max(sketch_chunks(n, CSK_F64), sketch_chunks(std::max<int64_t>(nrhs, 1), CSK_F64));
+    *bytes = sketch_ws_bytes(m, d, T, 1);
+    return CSK_OK;
+}
+
+csk_status csk_sketch(const void* A, csk_dtype a_dtype, int64_t m, int64_t n, int64_t lda,
+                      const double* B, int64_t nrhs, int64_t ldb, int64_t d, uint64_t seed,
+                      double* At64, int64_t ldat64, void* At_lp, csk_dtype lp_dtype, int64_t ldat_lp,
+                      double* Bt, int64_t ldbt, double* nu2, uint32_t* perm, uint32_t* ptr,
+                      void* ws, size_t ws_bytes, void* stream)
+{
+    g_err[0] = 0;
+    if (!A) { set_error("A is NULL"); return CSK_ERR_INVALID_ARG; }
+    if (a_dtype != CSK_F64 && a_dtype != CSK_F32) { set_error("A must be F64 or F32"); return CSK_ERR_UNSUPPORTED; }
+    if (m < 1 || n < 1 || d < 1 || m >= INT32_MAX || d >= INT32_MAX || n >= INT32_MAX) {
+        set_error("need 1 <= m, d < 2^31 and n >= 1");
+        return CSK_ERR_INVALID_ARG;
+    }
+    if (lda < n) { set_error("lda < n"); return CSK_ERR_INVALID_ARG; }
+    if (!At64 && !At_lp) { set_error("one of At64 / At_lp is required"); return CSK_ERR_INVALID_ARG; }
+    if (At64 && ldat64 < n) { set_error("ldat64 < n"); return CSK_ERR_INVALID_ARG; }
+    if (At_lp && !lp_ok(lp_dtype)) { set_error("lp_dtype must be F32, F16 or BF16"); return CSK_ERR_UNSUPPORTED; }
+    if (At_lp && ldat_lp < n) { set_error("ldat_lp < n"); return CSK_ERR_INVALID_ARG; }
+    if (B) {
+        if (nrhs < 1 || ldb < nrhs || !Bt || ldbt < nrhs) { set_error("bad B / Bt arguments"); return CSK_ERR_INVALID_ARG; }
+    }
+    if (!ws) { set_error("workspace is NULL"); return CSK_ERR_INVALID_ARG; }
+    if (reinterpret_cast<uintptr_t>(ws) & 255u) { set_error("workspace must be 256-byte aligned"); return CSK_ERR_INVALID_ARG; }
+    size_t need = 0;
+    csk_sketch_workspace_size(m, n, d, B ? nrhs : 0, &need);
+    if (ws_bytes < need) { set_error("workspace: need %zu bytes, got %zu", need, ws_bytes); return CSK_ERR_WORKSPACE; }
+    SketchJob J{};
+    J.A = A;
+    J.B = B;
+    J.At64 = At64;
+    J.Atlp = At_lp;
+    J.Bt = Bt;
+    J.nu2 = nu2;
+    J.m = m;
+    J.n = n;
+    J.lda = lda;
+    J.nrhs = B ? nrhs : 0;
+    J.ldb = ldb;
+    J.d = d;
+    J.ldat64 = ldat64;
+    J.ldatlp = ldat_lp;
+    J.ldbt = ldbt;
+    J.seed = seed;
+    return sketch_run(&J, 1, a_dtype, At_lp ? lp_dtype : (csk_dtype)0, perm, ptr, ws, ws_bytes, as_stream(stream));
+}
+
+csk_status csk_sketch_csr_workspace_size(int64_t m, int64_t n, int64_t d, size_t* bytes)
+{
+    g_err[0] = 0;
+    if (!bytes || m < 1 || n < 1 || d < 1) { set_error("bad sizes"); return CSK_ERR_INVALID_ARG; }
+    *bytes = sketch_ws_bytes(m, d, d, 1);
+    return CSK_OK;
+}
+
+csk_status csk_sketch_csr(const int64_t* row_ptr, const int32_t* col, const float* val, int64_t m, int64_t n,
+                          int64_t nnz, const double* b, int64_t d, uint64_t seed, double* At64, int64_t ldat64,
+                          void* At_lp, csk_dtype lp_dtype, int64_t ldat_lp, double* bt, double* nu2, void* ws,
+                          size_t ws_bytes, void* stream)
+{
+    g_err[0] = 0;
+    if (!row_ptr || (nnz > 0 && (!col || !val))) { set_error("row_ptr / col / val required"); return CSK_ERR_INVALID_ARG; }
+    if (m < 1 || n < 1 || d < 1 || nnz < 0 || m >= INT32_MAX || d >= INT32_MAX || n >= INT32_MAX) {
+        set_error("need 1 <= m, d < 2^31, n >= 1, nnz >= 0");
+        return CSK_ERR_INVALID_ARG;
+    }
+    if (!At64 && !At_lp) { set_error("one of At64 / At_lp is required"); return CSK_ERR_INVALID_ARG; }
+    if (At64 && ldat64 < n) { set_error("ldat64 < n"); return CSK_ERR_INVALID_ARG; }
+    if (At_lp && (!lp_ok(lp_dtype) || ldat_lp < n)) { set_error("bad At_lp arguments"); return CSK_ERR_INVALID_ARG; }
+    if ((b == nullptr) != (bt == nullptr)) { set_error("b and bt go together"); return CSK_ERR_INVALID_ARG; }
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u)) { set_error("workspace NULL or unaligned"); return CSK_ERR_INVALID_ARG; }
+    size_t need = 0;
+    csk_sketch_csr_workspace_size(m, n, d, &need);
+    if (ws_bytes < need) { set_error("workspace: need %zu bytes, got %zu", need, ws_bytes); return CSK_ERR_WORKSPACE; }
+    return sketch_csr_run(row_ptr, col, val, m, n, nnz, b, d, seed, At64, ldat64, At_lp,
+                          At_lp ? lp_dtype : (csk_dtype)0, ldat_lp, bt, nu2, ws, ws_bytes, as_stream(stream));
+}
+
+csk_status csk_solve_workspace_size(int64_t d, int64_t n, csk_dtype at_dtype, size_t* bytes)
+{
+    g_err[0] = 0;
+    if (!bytes || d < 1 || n < 1 || dtype_size(at_dtype) == 0) { set_error("bad sizes"); return CSK_ERR_INVALID_ARG; }
+    *bytes = solve_ws_bytes(d, n, 65536);
+    return CSK_OK;
+}
+
+csk_status csk_solve(const void* At, csk_dtype at_dtype, int64_t ldat, const double* At64, int64_t ldat64,
+                     int64_t d, int64_t n, const double* bt, const double* nu2, const double* x0, double* x,
+                     const csk_solve_opts* opts, csk_solve_result* res, void* ws, size_t ws_bytes, void* stream)
+{
+    g_err[0] = 0;
+    csk_status st = check_opts(opts);
+    if (st != CSK_OK) return st;
+    if (d < 1 || n < 1 || d >= INT32_MAX) { set_error("need 1 <= d < 2^31, n >= 1"); return CSK_ERR_INVALID_ARG; }
+    if (n > kMaxN) { set_error("n=%lld exceeds %lld", (long long)n, (long long)kMaxN); return CSK_ERR_UNSUPPORTED; }
+    if (!bt || !x || !res) { set_error("bt, x and res are required"); return CSK_ERR_INVALID_ARG; }
+    if (at_dtype == CSK_F64) {
+        if (!At && !At64) { set_error("At is NULL"); return CSK_ERR_INVALID_ARG; }
+        if (!At64) { At64 = static_cast<const double*>(At); ldat64 = ldat; }
+        if (!At) { At = At64; ldat = ldat64; }
+        if (ldat < n || ldat64 < n) { set_error("ldat < n"); return CSK_ERR_INVALID_ARG; }
+    } else if (lp_ok(at_dtype)) {
+        if (!At || !At64) { set_error("mixed precision needs At and At64"); return CSK_ERR_INVALID_ARG; }
+        if (ldat < n || ldat64 < n) { set_error("leading dimension < n"); return CSK_ERR_INVALID_ARG; }
+    } else {
+        set_error("unknown dtype %d", at_dtype);
+        return CSK_ERR_UNSUPPORTED;
+    }
+    if (opts->stop_mode == CSK_STOP_REL_ERR && !opts->x_ref) {
+        set_error("CSK_STOP_REL_ERR needs opts->x_ref");
+        return CSK_ERR_INVALID_ARG;
+    }
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u)) { set_error("workspace NULL or unaligned"); return CSK_ERR_INVALID_ARG; }
+    const SolvePlan plan = solve_plan(d, n, at_dtype, ldat, At, opts);
+    if (ws_bytes < solve_ws_bytes(d, n, plan.grid)) {
+        set_error("workspace: need %zu bytes, got %zu", solve_ws_bytes(d, n, plan.grid), ws_bytes);
+        return CSK_ERR_WORKSPACE;
+    }
+    SolveSys S{};
+    S.At = At;
+    S.At64 = At64;
+    S.bt = bt;
+    S.nu2 = nu2;
+    S.x0 = x0;
+    S.xref = opts->stop_mode == CSK_STOP_REL_ERR ? opts->x_ref : opts->x_ref;
+    S.x = x;
+    S.res = res;
+    S.ldat = ldat;
+    S.ldat64 = ldat64;
+    S.d = (int32_t)d;
+    S.n = (int32_t)n;
+    S.stop_mode = opts->stop_mode;
+    return solve_run(S, at_dtype, opts, ws, ws_bytes, as_stream(stream));
+}
+
+csk_status csk_solve_batched_workspace_size(const csk_system_desc* sys, int32_t nsys, csk_dtype a_dtype,
+                                            csk_dtype lp_dtype, size_t* bytes)
+{
+    g_err[0] = 0;
+    if (!bytes) { set_error("bytes is NULL"); return CSK_ERR_INVALID_ARG; }
+    csk_status st = check_batch(sys, nsys, a_dtype, lp_dtype);
+    if (st != CSK_OK) return st;
+    const BatchLayout L = batch_layout(sys, nsys, lp_dtype);
+    int64_t M = 0, D = 0, T = 0;
+    for (int s = 0; s < nsys; ++s) {
+        M += sys[s].m;
+        D += sys[s].d;
+        T += sys[s].d * sketch_chunks(sys[s].n, a_dtype);
+    }
+    Carve c(nullptr);
+    c.take<char>(L.data_bytes);
+    c.take<char>(sketch_ws_bytes(M, D, T, nsys));
+    c.take<SolveSys>(nsys);
+    c.take<int32_t>(nsys);
+    c.take<uint32_t>(64);
+    *bytes = c.bytes();
+    return CSK_OK;
+}
+
+csk_status csk_solve_batched(const csk_system_desc* sys, int32_t nsys, csk_dtype a_dtype, csk_dtype lp_dtype,
+                             const csk_solve_opts* opts, csk_solve_result* res, void* ws, size_t ws_bytes,
+                             void* stream)
+{
+    g_err[0] = 0;
+    csk_status st = check_opts(opts);
+    if (st != CSK_OK) return st;
+    st = check_batch(sys, nsys, a_dtype, lp_dtype);
+    if (st != CSK_OK) return st;
+    if (!res) { set_error("res is NULL"); return CSK_ERR_INVALID_ARG; }
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u)) { set_error("workspace NULL or unaligned"); return CSK_ERR_INVALID_ARG; }
+    size_t need = 0;
+    csk_solve_batched_workspace_size(sys, nsys, a_dtype, lp_dtype, &need);
+    if (ws_bytes < need) { set_error("workspace: need %zu bytes, got %zu", need, ws_bytes); return CSK_ERR_WORKSPACE; }
+    hipStream_t stm = as_stream(stream);
+
+    const BatchLayout L = batch_layout(sys, nsys, lp_dtype);
+    int64_t M = 0, D = 0, T = 0, n_max = 0;
+    for (int s = 0; s < nsys; ++s) {
+        M += sys[s].m;
+        D += sys[s].d;
+        T += sys[s].d * sketch_chunks(sys[s].n, a_dtype);
+        n_max = std::max(n_max, sys[s].n);
+    }
+    Carve c(ws);
+    char* data = c.take<char>(L.data_bytes);
+    const size_t sk_bytes = sketch_ws_bytes(M, D, T, nsys);
+    char* sk_ws = c.take<char>(sk_bytes);
+    SolveSys* d_sys = c.take<SolveSys>(nsys);
+    int32_t* d_order = c.take<int32_t>(nsys);
+    uint32_t* d_queue = c.take<uint32_t>(64);
+
+    // 1. sketch every system in one pipeline
+    std::vector<SketchJob> jobs(nsys);
+    for (int s = 0; s < nsys; ++s) {
+        SketchJob& J = jobs[s];
+        J = SketchJob{};
+        J.A = sys[s].A;
+        J.B = sys[s].b;
+        J.nrhs = 1;
+        J.ldb = 1;
+        J.m = sys[s].m;
+        J.n = sys[s].n;
+        J.lda = sys[s].lda;
+        J.d = sys[s].d;
+        J.seed = sys[s].seed;
+        J.At64 = reinterpret_cast<double*>(data + L.off_64[s]);
+        J.ldat64 = L.ld_64[s];
+        J.Atlp = lp_dtype == CSK_F64 ? nullptr : data + L.off_lp[s];
+        J.ldatlp = L.ld_lp[s];
+        J.Bt = reinterpret_cast<double*>(data + L.off_bt[s]);
+        J.ldbt = 1;
+        J.nu2 = reinterpret_cast<double*>(data + L.off_nu2[s]);
+    }
+    st = sketch_run(jobs.data(), nsys, a_dtype, lp_dtype == CSK_F64 ? (csk_dtype)0 : lp_dtype, nullptr, nullptr,
+                    sk_ws, sk_bytes, stm);
+    if (st != CSK_OK) return st;
+
+    // 2. solver descriptors, largest estimated work first
+    std::vector<SolveSys> hs(nsys);
+    for (int s = 0; s < nsys; ++s) {
+        SolveSys& S = hs[s];
+        S = SolveSys{};
+        S.At64 = jobs[s].At64;
+        S.ldat64 = jobs[s].ldat64;
+        S.At = lp_dtype == CSK_F64 ? static_cast<const void*>(S.At64) : jobs[s].Atlp;
+        S.ldat = lp_dtype == CSK_F64 ? S.ldat64 : jobs[s].ldatlp;
+        S.bt = jobs[s].Bt;
+        S.nu2 = jobs[s].nu2;
+        S.x0 = nullptr;
+        S.xref = sys[s].x_ref;
+        S.x = sys[s].x;
+        S.rref = reinterpret_cast<double*>(data + L.off_rref[s]);
+        S.res = res + s;
+        S.d = (int32_t)sys[s].d;
+        S.n = (int32_t)sys[s].n;
+        S.stop_mode = sys[s].x_ref ? CSK_STOP_REL_ERR : CSK_STOP_REL_RESID;
+    }
+    for (int k = 0; k < nsys; k += 24) {
+        SysPack pack;
+        const int cnt = std::min(24, nsys - k);
+        for (int q = 0; q < cnt; ++q) pack.s[q] = hs[k + q];
+        k_store_solve_descs<<<1, 64, 0, stm>>>(pack, cnt, d_sys + k);
+        CSK_LAUNCH_CHECK("k_store_solve_descs");
+    }
+    std::vector<int32_t> order(nsys);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        const double ca = (double)sys[a].d * (double)sys[a].n * (double)sys[a].n;
+        const double cb = (double)sys[b].d * (double)sys[b].n * (double)sys[b].n;
+        return ca > cb;
+    });
+    for (int k = 0; k < nsys; k += 512) {
+        OrderPack pack;
+        const int cnt = std::min(512, nsys - k);
+        for (int q = 0; q < cnt; ++q) pack.v[q] = order[k + q];
+        k_store_order<<<1, 256, 0, stm>>>(pack, cnt, d_order + k);
+        CSK_LAUNCH_CHECK("k_store_order");
+    }
+    return solve_batched_run(d_sys, d_order, nsys, n_max, lp_dtype, opts, d_queue, stm);
+}
+
+csk_status csk_solve_mrhs_workspace_size(int64_t d, int64_t n, int64_t nrhs, size_t* bytes)
+{
+    g_err[0] = 0;
+    if (!bytes || d < 1 || n < 1 || nrhs < 1) { set_error("bad sizes"); return CSK_ERR_INVALID_ARG; }
+    *bytes = mrhs_ws_bytes(d, n, nrhs);
+    return CSK_OK;
+}
+
+csk_status csk_solve_mrhs(const void* At_lp, csk_dtype lp_dtype, int64_t ldat_lp, const double* At64,
+                          int64_t ldat64, int64_t d, int64_t n, const double* Bt, int64_t nrhs, int64_t ldbt,
+                          const double* nu2, const double* X0, double* X, int64_t ldx, const double* Xref,
+                          int64_t ldxref, const csk_solve_opts* opts, csk_solve_result* res, void* ws,
+                          size_t ws_bytes, void* stream)
+{
+    g_err[0] = 0;
+    csk_status st = check_opts(opts);
+    if (st != CSK_OK) return st;
+    if (lp_dtype != CSK_BF16 && lp_dtype != CSK_F16) { set_error("lp_dtype must be BF16 or F16"); return CSK_ERR_UNSUPPORTED; }
+    if (!At_lp || !At64 || !Bt || !X || !res || !nu2) { set_error("At_lp, At64, Bt, nu2, X and res are required"); return CSK_ERR_INVALID_ARG; }
+    if (d < 1 || n < 1 || nrhs < 1 || d >= INT32_MAX || nrhs >= INT32_MAX) { set_error("bad sizes"); return CSK_ERR_INVALID_ARG; }
+    if (n > 1024) { set_error("n=%lld exceeds 1024", (long long)n); return CSK_ERR_UNSUPPORTED; }
+    if (ldat_lp < n || ldat64 < n || ldbt < nrhs || ldx < nrhs) { set_error("leading dimension too small"); return CSK_ERR_INVALID_ARG; }
+    if (opts->stop_mode == CSK_STOP_REL_ERR && (!Xref || ldxref < nrhs)) { set_error("CSK_STOP_REL_ERR needs Xref"); return CSK_ERR_INVALID_ARG; }
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u)) { set_error("workspace NULL or unaligned"); return CSK_ERR_INVALID_ARG; }
+    if (ws_bytes < mrhs_ws_bytes(d, n, nrhs)) { set_error("workspace: need %zu bytes, got %zu", mrhs_ws_bytes(d, n, nrhs), ws_bytes); return CSK_ERR_WORKSPACE; }
+    return mrhs_run(At_lp, lp_dtype, ldat_lp, At64, ldat64, d, n, Bt, nrhs, ldbt, nu2, X0, X, ldx, Xref, ldxref,
+                    opts, res, ws, ws_bytes, as_stream(stream));
+}
+
+}  // extern "C"

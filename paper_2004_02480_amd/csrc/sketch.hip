@@ -1,0 +1,887 @@
+// sketch.hip -- Algorithm 1, Initialize: At = S A and Bt = S B with the count
+// sketch of Definition 1, for one system or a batch of systems.
+//
+// Pipeline (all on the caller's stream, no host round trip):
+//   k_hash_hist      hash every row (h(i), D_ii) and count rows per bucket
+//   k_scan_*         exclusive scan of the counts -> bucket offsets ptr
+//   k_scatter        place each row index in its bucket's segment of perm
+//   k_sort_segments  sort each segment ascending (one wavefront, in LDS)
+//   k_long_segments  segments longer than the LDS sort capacity are rebuilt
+//                    in ascending order by an ordered scan of the rows
+//   k_segsum         one wavefront per (bucket, column chunk): stream the
+//                    bucket's rows of A in ascending row order, accumulate the
+//                    signed sum in FP64 registers (one lane owns each output
+//                    element, so each sum is sequential and bit-exact), then
+//                    store At64 / the rounded low-precision copy, the squared
+//                    row norm and bt.
+//   k_nu2_finalize   adds per-chunk squared norms in chunk order.
+// The hot kernel is k_segsum: it reads A exactly once (m*n elements) and
+// writes At once, so it is bound by HBM bandwidth.
+#include "csk_sketch.h"
+
+#include <algorithm>
+#include <vector>
+
+namespace csk {
+namespace {
+
+constexpr int kSortCap = 512;     // longest segment sorted by one wavefront in LDS
+constexpr int kScanTile = 4096;   // counts per block in the scan (256 threads x 16)
+
+struct Batch {
+    const SketchSys* sys;        // nsys descriptors (device)
+    const int64_t* row_offs;     // nsys+1 prefix over rows (device)
+    const int64_t* bkt_offs;     // nsys+1 prefix over buckets
+    const int64_t* task_offs;    // nsys+1 prefix over segsum tasks
+    uint32_t* cnt;               // D
+    uint32_t* ptr;               // D+1
+    uint32_t* perm;              // M (row index local to its system)
+    double* nu2part;             // T
+    uint32_t* scan_part;         // ceil(D / kScanTile)
+    int64_t M, D, T;
+    int32_t nsys;
+};
+
+// Largest s with offs[s] <= g (offs[0] = 0, strictly increasing).
+__device__ __forceinline__ int find_sys(const int64_t* offs, int nsys, int64_t g)
+{
+    int lo = 0, hi = nsys;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (offs[mid] <= g) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_fill_u32(uint32_t* p, int64_t count, uint32_t v)
+{
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < count;
+         k += (int64_t)gridDim.x * blockDim.x)
+        p[k] = v;
+}
+
+__global__ __launch_bounds__(256) void k_hash_hist(Batch b)
+{
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < b.M;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const int s = b.nsys == 1 ? 0 : find_sys(b.row_offs, b.nsys, g);
+        const SketchSys& S = b.sys[s];
+        const uint64_t w = draw_word(S.seed, static_cast<uint64_t>(g - S.row_off));
+        atomicAdd(&b.cnt[S.bkt_off + draw_bucket(w, static_cast<uint32_t>(S.d))], 1u);
+    }
+}
+
+// Inclusive scan of one u32 per thread over a block of NT threads; returns
+// the inclusive value and the block total in *total.
+template <int NT>
+__device__ __forceinline__ uint32_t block_incl_scan(uint32_t v, uint32_t* total)
+{
+    __shared__ uint32_t wsum[NT / kWave];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        uint32_t t = __shfl_up(v, off, kWave);
+        if (lane >= off) v += t;
+    }
+    if (lane == kWave - 1) wsum[wid] = v;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < NT / kWave; ++w) {
+        uint32_t t = wsum[w];
+        if (w < wid) before += t;
+        all += t;
+    }
+    __syncthreads();
+    *total = all;
+    return v + before;
+}
+
+__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict__ cnt, int64_t D,
+                                                    uint32_t* __restrict__ part)
+{
+    const int64_t base = blockIdx.x * (int64_t)kScanTile;
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanTile / 256; ++k) {
+        const int64_t j = base + k * 256 + threadIdx.x;
+        if (j < D) s += cnt[j];
+    }
+    uint32_t total;
+    block_incl_scan<256>(s, &total);
+    if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_top(uint32_t* __restrict__ part, int64_t nb,
+                                                  uint32_t* __restrict__ ptr, int64_t D)
+{
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < nb; base += 1024) {
+        const int64_t j = base + threadIdx.x;
+        const uint32_t v = j < nb ? part[j] : 0u;
+        uint32_t total;
+        const uint32_t incl = block_incl_scan<1024>(v, &total);
+        if (j < nb) part[j] = carry + incl - v;
+        carry += total;
+    }
+    if (threadIdx.x == 0) ptr[D] = carry;
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__ cnt, int64_t D,
+                                                   const uint32_t* __restrict__ part,
+                                                   uint32_t* __restrict__ ptr)
+{
+    constexpr int kPer = kScanTile / 256;
+    const int64_t base = blockIdx.x * (int64_t)kScanTile + threadIdx.x * (int64_t)kPer;
+    uint32_t v[kPer];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        v[k] = (base + k < D) ? cnt[base + k] : 0u;
+        s += v[k];
+    }
+    uint32_t total;
+    uint32_t run = block_incl_scan<256>(s, &total) - s + part[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        if (base + k < D) ptr[base + k] = run;
+        run += v[k];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scatter(Batch b)
+{
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < b.M;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const int s = b.nsys == 1 ? 0 : find_sys(b.row_offs, b.nsys, g);
+        const SketchSys& S = b.sys[s];
+        const uint64_t i = static_cast<uint64_t>(g - S.row_off);
+        const int64_t gb = S.bkt_off + draw_bucket(draw_word(S.seed, i), static_cast<uint32_t>(S.d));
+        // Counting down through cnt leaves it zero; the order inside the
+        // segment is fixed afterwards by the sort.
+        const uint32_t pos = atomicSub(&b.cnt[gb], 1u) - 1u;
+        b.perm[b.ptr[gb] + pos] = static_cast<uint32_t>(i);
+    }
+}
+
+// Four wavefronts per block, one bucket each per round; rank sort in LDS
+// (row indices within a segment are distinct).
+__global__ __launch_bounds__(256) void k_sort_segments(Batch b)
+{
+    __shared__ uint32_t buf[4][kSortCap];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const int64_t rounds = (b.D + 4 * (int64_t)gridDim.x - 1) / (4 * (int64_t)gridDim.x);
+    for (int64_t rd = 0; rd < rounds; ++rd) {
+        const int64_t gb = (rd * gridDim.x + blockIdx.x) * 4 + wid;
+        uint32_t beg = 0, len = 0;
+        if (gb < b.D) {
+            beg = b.ptr[gb];
+            len = b.ptr[gb + 1] - beg;
+        }
+        const bool active = len > 1 && len <= (uint32_t)kSortCap;
+        if (active)
+            for (uint32_t e = lane; e < len; e += kWave) buf[wid][e] = b.perm[beg + e];
+        __syncthreads();
+        if (active) {
+            for (uint32_t e = lane; e < len; e += kWave) {
+                const uint32_t v = buf[wid][e];
+                uint32_t rank = 0;
+                for (uint32_t k = 0; k < len; ++k) rank += buf[wid][k] < v ? 1u : 0u;
+                b.perm[beg + rank] = v;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Segments longer than kSortCap: rebuild the segment in ascending row order
+// by scanning the system's rows in order and compacting those that hash to
+// the bucket (ballot + block prefix).
+__global__ __launch_bounds__(256) void k_long_segments(Batch b)
+{
+    __shared__ uint32_t wcount[4];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    for (int64_t gb = blockIdx.x; gb < b.D; gb += gridDim.x) {
+        const uint32_t beg = b.ptr[gb];
+        const uint32_t len = b.ptr[gb + 1] - beg;
+        if (len <= (uint32_t)kSortCap) continue;
+        const int s = b.nsys == 1 ? 0 : find_sys(b.bkt_offs, b.nsys, gb);
+        const SketchSys& S = b.sys[s];
+        const uint32_t j = static_cast<uint32_t>(gb - S.bkt_off);
+        uint32_t running = 0;
+        for (int64_t base = 0; base < S.m; base += 256) {
+            const int64_t i = base + threadIdx.x;
+            const bool hit = i < S.m &&
+                draw_bucket(draw_word(S.seed, static_cast<uint64_t>(i)), static_cast<uint32_t>(S.d)) == j;
+            const unsigned long long mask = __ballot(hit);
+            const uint32_t below = __popcll(mask & ((1ull << lane) - 1ull));
+            if (lane == 0) wcount[wid] = __popcll(mask);
+            __syncthreads();
+            uint32_t before = 0, all = 0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                if (w < wid) before += wcount[w];
+                all += wcount[w];
+            }
+            if (hit) b.perm[beg + running + before + below] = static_cast<uint32_t>(i);
+            running += all;
+            __syncthreads();
+        }
+    }
+}
+
+template <class T> struct VecOf;
+template <> struct VecOf<double> { static constexpr int kW = 2; using type = double2; };
+template <> struct VecOf<float> { static constexpr int kW = 4; using type = float4; };
+
+template <class T, int VW> struct Loader;
+template <class T> struct Loader<T, 1> {
+    __device__ static void load(const T* p, double* out) { out[0] = static_cast<double>(*p); }
+};
+template <> struct Loader<double, 2> {
+    __device__ static void load(const double* p, double* out)
+    {
+        const double2 v = *reinterpret_cast<const double2*>(p);
+        out[0] = v.x;
+        out[1] = v.y;
+    }
+};
+template <> struct Loader<float, 4> {
+    __device__ static void load(const float* p, double* out)
+    {
+        const float4 v = *reinterpret_cast<const float4*>(p);
+        out[0] = v.x;
+        out[1] = v.y;
+        out[2] = v.z;
+        out[3] = v.w;
+    }
+};
+
+// LP: 0 none, 1 f32, 2 f16, 3 bf16 (matches csk_dtype values for 1..3).
+template <int LP>
+__device__ __forceinline__ void store_lp(void* base, int64_t off, double v)
+{
+    if constexpr (LP == CSK_F32) static_cast<float*>(base)[off] = round_store<tag_f32>(v);
+    if constexpr (LP == CSK_F16) static_cast<uint16_t*>(base)[off] = round_store<tag_f16>(v);
+    if constexpr (LP == CSK_BF16) static_cast<uint16_t*>(base)[off] = round_store<tag_bf16>(v);
+}
+
+// One wavefront per (bucket, column chunk).  A chunk is VPL vectors of VW
+// elements per lane, i.e. 64*VW*VPL columns.  Rows of the bucket are taken
+// in ascending order (perm is sorted), U at a time for memory-level
+// parallelism; every accumulation stays in the order of the rows.
+template <class TA, int VW, int VPL, int U, int LP>
+__global__ __launch_bounds__(256) void k_segsum(Batch b)
+{
+    constexpr int CW = kWave * VW * VPL;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    for (int64_t t = blockIdx.x * 4 + threadIdx.x / kWave; t < b.T; t += nwaves) {
+        const int s = b.nsys == 1 ? 0 : find_sys(b.task_offs, b.nsys, t);
+        const SketchSys& S = b.sys[s];
+        const int64_t lt = t - S.task_off;
+        const int64_t j = lt / S.nchunks;
+        const int c = static_cast<int>(lt - j * S.nchunks);
+        const int n = S.n;
+        const int col0 = c * CW;
+        const TA* __restrict__ A = static_cast<const TA*>(S.A);
+        const uint32_t beg = b.ptr[S.bkt_off + j];
+        const uint32_t end = b.ptr[S.bkt_off + j + 1];
+        const bool with_b = (S.B != nullptr) && c == 0;
+
+        double acc[VPL][VW];
+#pragma unroll
+        for (int v = 0; v < VPL; ++v)
+#pragma unroll
+            for (int e = 0; e < VW; ++e) acc[v][e] = 0.0;
+        double bacc = 0.0;
+
+        for (uint32_t p = beg; p < end; p += U) {
+            uint32_t row[U];
+            double sg[U];
+            double val[U][VPL][VW];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool ok = p + u < end;
+                row[u] = ok ? b.perm[p + u] : 0u;
+                sg[u] = draw_sign(draw_word(S.seed, row[u]));
+#pragma unroll
+                for (int v = 0; v < VPL; ++v) {
+                    const int col = col0 + (v * kWave + lane) * VW;
+                    const TA* src = A + (int64_t)row[u] * S.lda + col;
+                    if (ok && col + VW <= n) {
+                        Loader<TA, VW>::load(src, val[u][v]);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < VW; ++e)
+                            val[u][v][e] = (ok && col + e < n) ? static_cast<double>(src[e]) : 0.0;
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (p + u < end) {
+#pragma unroll
+                    for (int v = 0; v < VPL; ++v)
+#pragma unroll
+                        for (int e = 0; e < VW; ++e) acc[v][e] = acc[v][e] + sg[u] * val[u][v][e];
+                    if (with_b) bacc = bacc + sg[u] * S.B[(int64_t)row[u] * S.ldb];
+                }
+            }
+        }
+
+        double nrm = 0.0;
+#pragma unroll
+        for (int v = 0; v < VPL; ++v) {
+            const int col = col0 + (v * kWave + lane) * VW;
+#pragma unroll
+            for (int e = 0; e < VW; ++e) {
+                if (col + e < n) {
+                    nrm += acc[v][e] * acc[v][e];
+                    if (S.At64) S.At64[j * S.ldat64 + col + e] = acc[v][e];
+                    if constexpr (LP != 0) store_lp<LP>(S.Atlp, j * S.ldatlp + col + e, acc[v][e]);
+                }
+            }
+        }
+        nrm = wave_sum(nrm);
+        if (lane == 0) {
+            if (S.nchunks == 1) {
+                if (S.nu2) S.nu2[j] = nrm;
+            } else {
+                b.nu2part[t] = nrm;
+            }
+            if (with_b) S.Bt[j * S.ldbt] = bacc;
+        }
+    }
+}
+
+__global__ void k_nu2_finalize(Batch b)
+{
+    for (int64_t gb = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; gb < b.D;
+         gb += (int64_t)gridDim.x * blockDim.x) {
+        const int s = b.nsys == 1 ? 0 : find_sys(b.bkt_offs, b.nsys, gb);
+        const SketchSys& S = b.sys[s];
+        if (S.nchunks <= 1 || S.nu2 == nullptr) continue;
+        const int64_t j = gb - S.bkt_off;
+        double acc = 0.0;
+        for (int c = 0; c < S.nchunks; ++c) acc += b.nu2part[S.task_off + j * S.nchunks + c];
+        S.nu2[j] = acc;
+    }
+}
+
+
+// ---------------------------------------------------------------------------
+// CSR input.  One workgroup per bucket: the bucket's stored entries are staged
+// in LDS in ascending row order (signed, widened to FP64), wavefront 0 adds
+// them row by row into an FP64 accumulator row in LDS (lanes take distinct
+// columns of one row, rows follow in order, so each column's sum is
+// sequential in the row order), then the whole workgroup writes the dense
+// row(s) and reduces the squared norm.  Entries beyond the staging capacity
+// are read straight from global memory by the same ordered walk.
+// ---------------------------------------------------------------------------
+constexpr int kCsrNT = 256;
+constexpr int kCsrStage = 1024;   // staged entries per bucket
+constexpr int kCsrRows = 256;     // staged rows per bucket
+
+template <int LP>
+__global__ __launch_bounds__(kCsrNT) void k_segsum_csr(Batch b, const int64_t* __restrict__ row_ptr,
+                                                       const int32_t* __restrict__ colidx,
+                                                       const float* __restrict__ val, int chunk)
+{
+    extern __shared__ __align__(16) char smem[];
+    double* acc = reinterpret_cast<double*>(smem);              // chunk columns
+    __shared__ double s_val[kCsrStage];
+    __shared__ int32_t s_col[kCsrStage];
+    __shared__ int32_t s_rowend[kCsrRows];                      // staged-entry end per row
+    __shared__ double s_b[kCsrRows];
+    __shared__ uint32_t s_wsum[kCsrNT / kWave];
+    __shared__ double s_red[kCsrNT / kWave];
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wid = tid / kWave;
+    const SketchSys S = b.sys[0];
+    const int n = S.n;
+    for (int64_t j = blockIdx.x; j < S.d; j += gridDim.x) {
+        const uint32_t beg = b.ptr[j], end = b.ptr[j + 1];
+        const uint32_t len = end - beg;
+        // stage: thread t takes row beg+t (first kCsrRows rows)
+        const bool staged = len <= (uint32_t)kCsrRows;
+        uint32_t mycnt = 0;
+        int64_t rs = 0;
+        double sg = 0.0;
+        uint32_t myrow = 0;
+        if (staged && (uint32_t)tid < len) {
+            myrow = b.perm[beg + tid];
+            sg = draw_sign(draw_word(S.seed, myrow));
+            rs = row_ptr[myrow];
+            mycnt = (uint32_t)(row_ptr[myrow + 1] - rs);
+            s_b[tid] = S.B ? sg * S.B[myrow] : 0.0;
+        }
+        // block exclusive scan of per-row counts
+        uint32_t v = mycnt;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t t = __shfl_up(v, off, kWave);
+            if (lane >= off) v += t;
+        }
+        if (lane == kWave - 1) s_wsum[wid] = v;
+        __syncthreads();
+        uint32_t before = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < kCsrNT / kWave; ++w) {
+            if (w < wid) before += s_wsum[w];
+            total += s_wsum[w];
+        }
+        const uint32_t start = before + v - mycnt;
+        const bool fits = staged && total <= (uint32_t)kCsrStage;
+        if (fits && (uint32_t)tid < len) {
+            for (uint32_t e = 0; e < mycnt; ++e) {
+                s_col[start + e] = colidx[rs + e];
+                s_val[start + e] = sg * static_cast<double>(val[rs + e]);
+            }
+            s_rowend[tid] = (int32_t)(start + mycnt);
+        }
+        double nrm = 0.0;
+        for (int c0 = 0; c0 < n; c0 += chunk) {
+            const int cw = min(chunk, n - c0);
+            for (int c = tid; c < cw; c += kCsrNT) acc[c] = 0.0;
+            __syncthreads();
+            if (wid == 0) {
+                if (fits) {
+                    int32_t e0 = 0;
+                    for (uint32_t p = 0; p < len; ++p) {
+                        const int32_t e1 = s_rowend[p];
+                        for (int32_t e = e0 + lane; e < e1; e += kWave) {
+                            const int c = s_col[e] - c0;
+                            if (c >= 0 && c < cw) acc[c] = acc[c] + s_val[e];
+                        }
+                        e0 = e1;
+                    }
+                } else {
+                    for (uint32_t p = beg; p < end; ++p) {
+                        const uint32_t row = b.perm[p];
+                        const double sgn = draw_sign(draw_word(S.seed, row));
+                        const int64_t e1 = row_ptr[row + 1];
+                        for (int64_t e = row_ptr[row] + lane; e < e1; e += kWave) {
+                            const int c = colidx[e] - c0;
+                            if (c >= 0 && c < cw) acc[c] = acc[c] + sgn * static_cast<double>(val[e]);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            for (int c = tid; c < cw; c += kCsrNT) {
+                const double a = acc[c];
+                nrm += a * a;
+                if (S.At64) S.At64[j * S.ldat64 + c0 + c] = a;
+                if constexpr (LP != 0) store_lp<LP>(S.Atlp, j * S.ldatlp + c0 + c, a);
+            }
+            __syncthreads();
+        }
+        nrm = wave_sum(nrm);
+        if (lane == 0) s_red[wid] = nrm;
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+            for (int w = 0; w < kCsrNT / kWave; ++w) t += s_red[w];
+            if (S.nu2) S.nu2[j] = t;
+            if (S.Bt) {
+                double bacc = 0.0;
+                if (staged) {
+                    for (uint32_t p = 0; p < len; ++p) bacc = bacc + s_b[p];
+                } else {
+                    for (uint32_t p = beg; p < end; ++p) {
+                        const uint32_t row = b.perm[p];
+                        bacc = bacc + draw_sign(draw_word(S.seed, row)) * S.B[row];
+                    }
+                }
+                S.Bt[j] = bacc;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Descriptors travel to the device as kernel arguments, 8 at a time, so the
+// call needs no host staging buffer and stays capturable.
+struct DescPack {
+    SketchSys s[24];
+};
+
+__global__ void k_store_descs(DescPack pack, int count, SketchSys* dst)
+{
+    if (threadIdx.x < count) dst[threadIdx.x] = pack.s[threadIdx.x];
+}
+
+struct OffPack {
+    int64_t v[400];
+};
+
+__global__ void k_store_offs(OffPack pack, int count, int64_t* dst)
+{
+    for (int k = threadIdx.x; k < count; k += blockDim.x) dst[k] = pack.v[k];
+}
+
+int grid_for(int64_t items, int per_block, int cap)
+{
+    int64_t g = (items + per_block - 1) / per_block;
+    return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(g, cap)));
+}
+
+// Column-chunk geometry: VW elements per vector (16 bytes), VPL vectors per
+// lane.  For FP64 input a chunk covers 128*VPL columns, for FP32 256*VPL.
+struct Geometry {
+    int vw, vpl;
+};
+
+Geometry pick_geometry(int64_t n_max, csk_dtype a_dtype, bool vec_ok)
+{
+    const int vw = vec_ok ? (a_dtype == CSK_F64 ? 2 : 4) : 1;
+    const int64_t per_vpl = (int64_t)kWave * vw;
+    int vpl = static_cast<int>(std::min<int64_t>(4, (n_max + per_vpl - 1) / per_vpl));
+    if (vpl == 3) vpl = 4;
+    return {vw, std::max(1, vpl)};
+}
+
+template <class TA, int VW, int VPL, int LP>
+void launch_segsum_lp(const Batch& b, hipStream_t st)
+{
+    constexpr int U = (VPL >= 4) ? 4 : 8;
+    k_segsum<TA, VW, VPL, U, LP><<<grid_for(b.T, 4, 1 << 20), 256, 0, st>>>(b);
+}
+
+template <class TA, int VW, int VPL>
+void launch_segsum_vpl(const Batch& b, csk_dtype lp, hipStream_t st)
+{
+    switch (lp) {
+    case CSK_F32: launch_segsum_lp<TA, VW, VPL, CSK_F32>(b, st); break;
+    case CSK_F16: launch_segsum_lp<TA, VW, VPL, CSK_F16>(b, st); break;
+    case CSK_BF16: launch_segsum_lp<TA, VW, VPL, CSK_BF16>(b, st); break;
+    default: launch_segsum_lp<TA, VW, VPL, 0>(b, st); break;
+    }
+}
+
+template <class TA, int VW>
+void launch_segsum_vw(const Batch& b, int vpl, csk_dtype lp, hipStream_t st)
+{
+    switch (vpl) {
+    case 1: launch_segsum_vpl<TA, VW, 1>(b, lp, st); break;
+    case 2: launch_segsum_vpl<TA, VW, 2>(b, lp, st); break;
+    default: launch_segsum_vpl<TA, VW, 4>(b, lp, st); break;
+    }
+}
+
+void launch_segsum(const Batch& b, csk_dtype a_dtype, Geometry g, csk_dtype lp, hipStream_t st)
+{
+    if (a_dtype == CSK_F64) {
+        if (g.vw == 2) launch_segsum_vw<double, 2>(b, g.vpl, lp, st);
+        else launch_segsum_vw<double, 1>(b, g.vpl, lp, st);
+    } else {
+        if (g.vw == 4) launch_segsum_vw<float, 4>(b, g.vpl, lp, st);
+        else launch_segsum_vw<float, 1>(b, g.vpl, lp, st);
+    }
+}
+
+// Hash, count, scan, scatter and sort: afterwards perm[ptr[gb] .. ptr[gb+1])
+// lists the rows of global bucket gb in ascending order.
+csk_status group_rows(const Batch& b, hipStream_t st)
+{
+    const int64_t M = b.M, D = b.D;
+    const int nb_scan = static_cast<int>((D + kScanTile - 1) / kScanTile);
+    k_fill_u32<<<grid_for(D, 256, 4096), 256, 0, st>>>(b.cnt, D, 0u);
+    CSK_LAUNCH_CHECK("k_fill_u32");
+    k_hash_hist<<<grid_for(M, 256, 16384), 256, 0, st>>>(b);
+    CSK_LAUNCH_CHECK("k_hash_hist");
+    k_scan_reduce<<<nb_scan, 256, 0, st>>>(b.cnt, D, b.scan_part);
+    CSK_LAUNCH_CHECK("k_scan_reduce");
+    k_scan_top<<<1, 1024, 0, st>>>(b.scan_part, nb_scan, b.ptr, D);
+    CSK_LAUNCH_CHECK("k_scan_top");
+    k_scan_apply<<<nb_scan, 256, 0, st>>>(b.cnt, D, b.scan_part, b.ptr);
+    CSK_LAUNCH_CHECK("k_scan_apply");
+    k_scatter<<<grid_for(M, 256, 16384), 256, 0, st>>>(b);
+    CSK_LAUNCH_CHECK("k_scatter");
+    k_sort_segments<<<grid_for(D, 4, 8192), 256, 0, st>>>(b);
+    CSK_LAUNCH_CHECK("k_sort_segments");
+    k_long_segments<<<grid_for(D, 1, 1024), 256, 0, st>>>(b);
+    CSK_LAUNCH_CHECK("k_long_segments");
+    return CSK_OK;
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+}  // namespace
+
+int64_t sketch_chunks(int64_t n, csk_dtype a_dtype)
+{
+    (void)a_dtype;
+    // Upper bound used for workspace sizing: the smallest chunk is 64 columns.
+    return (n + kWave - 1) / kWave;
+}
+
+size_t sketch_ws_bytes(int64_t M, int64_t D, int64_t T, int32_t nsys)
+{
+    Carve c(nullptr);
+    c.take<SketchSys>(nsys);
+    c.take<SketchSys>(nsys);
+    c.take<int64_t>(nsys + 1);
+    c.take<int64_t>(nsys + 1);
+    c.take<int64_t>(nsys + 1);
+    c.take<int64_t>(nsys + 1);
+    c.take<uint32_t>(D);
+    c.take<uint32_t>(D + 1);
+    c.take<uint32_t>(M);
+    c.take<double>(T);
+    c.take<uint32_t>(D / kScanTile + 2);
+    return c.bytes();
+}
+
+static csk_status upload_descs(const std::vector<SketchSys>& h, SketchSys* d, hipStream_t st)
+{
+    for (size_t k = 0; k < h.size(); k += 24) {
+        DescPack pack;
+        const int cnt = static_cast<int>(std::min<size_t>(24, h.size() - k));
+        for (int q = 0; q < cnt; ++q) pack.s[q] = h[k + q];
+        k_store_descs<<<1, 64, 0, st>>>(pack, cnt, d + k);
+        CSK_LAUNCH_CHECK("k_store_descs");
+    }
+    return CSK_OK;
+}
+
+static csk_status upload_offs(const std::vector<int64_t>& h, int64_t* d, hipStream_t st)
+{
+    for (size_t k = 0; k < h.size(); k += 400) {
+        OffPack pack;
+        const int cnt = static_cast<int>(std::min<size_t>(400, h.size() - k));
+        for (int q = 0; q < cnt; ++q) pack.v[q] = h[k + q];
+        k_store_offs<<<1, 64, 0, st>>>(pack, cnt, d + k);
+        CSK_LAUNCH_CHECK("k_store_offs");
+    }
+    return CSK_OK;
+}
+
+csk_status sketch_run(const SketchJob* jobs, int32_t nsys, csk_dtype a_dtype, csk_dtype lp_dtype,
+                      uint32_t* perm_out, uint32_t* ptr_out, void* ws, size_t ws_bytes, hipStream_t st)
+{
+    // Geometry shared by the batch: vector loads only when every system's
+    // rows are 16-byte aligned.
+    int64_t n_max = 0, nrhs_max = 0;
+    bool vec_ok = true, vec_ok_b = true;
+    const size_t esz = dtype_size(a_dtype);
+    for (int s = 0; s < nsys; ++s) {
+        const SketchJob& J = jobs[s];
+        n_max = std::max(n_max, J.n);
+        const int vw = (a_dtype == CSK_F64) ? 2 : 4;
+        (void)vw;
+        if (!aligned16(J.A) || (J.lda * esz) % 16 != 0) vec_ok = false;
+        if (J.B && J.nrhs > 1) {
+            nrhs_max = std::max(nrhs_max, J.nrhs);
+            if (!aligned16(J.B) || (J.ldb * 8) % 16 != 0) vec_ok_b = false;
+        }
+    }
+    const Geometry g = pick_geometry(n_max, a_dtype, vec_ok);
+    const int64_t cw = (int64_t)kWave * g.vw * g.vpl;
+
+    std::vector<SketchSys> hs(nsys);
+    std::vector<int64_t> row_offs(nsys + 1), bkt_offs(nsys + 1), task_offs(nsys + 1);
+    int64_t M = 0, D = 0, T = 0;
+    for (int s = 0; s < nsys; ++s) {
+        const SketchJob& J = jobs[s];
+        SketchSys& S = hs[s];
+        S.A = J.A;
+        S.B = (J.B && J.nrhs == 1) ? J.B : nullptr;
+        S.At64 = J.At64;
+        S.Atlp = J.Atlp;
+        S.Bt = J.Bt;
+        S.nu2 = J.nu2;
+        S.lda = J.lda;
+        S.ldb = J.ldb;
+        S.ldat64 = J.ldat64;
+        S.ldatlp = J.ldatlp;
+        S.ldbt = J.ldbt;
+        S.m = J.m;
+        S.seed = J.seed;
+        S.n = static_cast<int32_t>(J.n);
+        S.d = static_cast<int32_t>(J.d);
+        S.nrhs = static_cast<int32_t>(J.nrhs);
+        S.nchunks = static_cast<int32_t>((J.n + cw - 1) / cw);
+        S.row_off = M;
+        S.bkt_off = D;
+        S.task_off = T;
+        row_offs[s] = M;
+        bkt_offs[s] = D;
+        task_offs[s] = T;
+        M += J.m;
+        D += J.d;
+        T += J.d * S.nchunks;
+    }
+    row_offs[nsys] = M;
+    bkt_offs[nsys] = D;
+    task_offs[nsys] = T;
+    if (M >= (int64_t)UINT32_MAX) {
+        set_error("total rows %lld exceed the 32-bit row index", (long long)M);
+        return CSK_ERR_UNSUPPORTED;
+    }
+
+    Carve c(ws);
+    Batch b;
+    SketchSys* d_sys = c.take<SketchSys>(nsys);
+    SketchSys* d_sys_b = c.take<SketchSys>(nsys);
+    int64_t* d_row = c.take<int64_t>(nsys + 1);
+    int64_t* d_bkt = c.take<int64_t>(nsys + 1);
+    int64_t* d_task = c.take<int64_t>(nsys + 1);
+    int64_t* d_task_b = c.take<int64_t>(nsys + 1);
+    b.cnt = c.take<uint32_t>(D);
+    b.ptr = c.take<uint32_t>(D + 1);
+    b.perm = c.take<uint32_t>(M);
+    b.nu2part = c.take<double>(T);
+    b.scan_part = c.take<uint32_t>(D / kScanTile + 2);
+    if (c.bytes() > ws_bytes) {
+        set_error("sketch workspace too small: need %zu bytes, got %zu", c.bytes(), ws_bytes);
+        return CSK_ERR_WORKSPACE;
+    }
+    b.sys = d_sys;
+    b.row_offs = d_row;
+    b.bkt_offs = d_bkt;
+    b.task_offs = d_task;
+    b.M = M;
+    b.D = D;
+    b.T = T;
+    b.nsys = nsys;
+
+    csk_status r;
+    if ((r = upload_descs(hs, d_sys, st)) != CSK_OK) return r;
+    if (nsys > 1) {
+        if ((r = upload_offs(row_offs, d_row, st)) != CSK_OK) return r;
+        if ((r = upload_offs(bkt_offs, d_bkt, st)) != CSK_OK) return r;
+        if ((r = upload_offs(task_offs, d_task, st)) != CSK_OK) return r;
+    }
+
+    if ((r = group_rows(b, st)) != CSK_OK) return r;
+    launch_segsum(b, a_dtype, g, lp_dtype, st);
+    CSK_LAUNCH_CHECK("k_segsum");
+    if (T > D) {
+        k_nu2_finalize<<<grid_for(D, 256, 4096), 256, 0, st>>>(b);
+        CSK_LAUNCH_CHECK("k_nu2_finalize");
+    }
+
+    // Multi-column right-hand sides: the same segmented sum over B.
+    if (nrhs_max > 1) {
+        const Geometry gb = pick_geometry(nrhs_max, CSK_F64, vec_ok_b);
+        const int64_t cwb = (int64_t)kWave * gb.vw * gb.vpl;
+        std::vector<SketchSys> hb(nsys);
+        std::vector<int64_t> toffs(nsys + 1);
+        int64_t TB = 0;
+        for (int s = 0; s < nsys; ++s) {
+            const SketchJob& J = jobs[s];
+            SketchSys S = hs[s];
+            S.A = J.B;
+            S.lda = J.ldb;
+            S.n = static_cast<int32_t>(J.B && J.nrhs > 1 ? J.nrhs : 0);
+            S.B = nullptr;
+            S.At64 = (J.B && J.nrhs > 1) ? J.Bt : nullptr;
+            S.ldat64 = J.ldbt;
+            S.Atlp = nullptr;
+            S.nu2 = nullptr;
+            S.nchunks = static_cast<int32_t>(std::max<int64_t>(1, (S.n + cwb - 1) / cwb));
+            S.task_off = TB;
+            toffs[s] = TB;
+            TB += J.d * S.nchunks;
+            hb[s] = S;
+        }
+        toffs[nsys] = TB;
+        if (TB > T) {
+            set_error("internal: right-hand-side task space exceeds workspace");
+            return CSK_ERR_UNSUPPORTED;
+        }
+        if ((r = upload_descs(hb, d_sys_b, st)) != CSK_OK) return r;
+        if (nsys > 1 && (r = upload_offs(toffs, d_task_b, st)) != CSK_OK) return r;
+        Batch bb = b;
+        bb.sys = d_sys_b;
+        bb.task_offs = d_task_b;
+        bb.T = TB;
+        launch_segsum(bb, CSK_F64, gb, (csk_dtype)0, st);
+        CSK_LAUNCH_CHECK("k_segsum(B)");
+    }
+
+    if (perm_out) CSK_HIP(hipMemcpyAsync(perm_out, b.perm, sizeof(uint32_t) * M, hipMemcpyDeviceToDevice, st));
+    if (ptr_out) CSK_HIP(hipMemcpyAsync(ptr_out, b.ptr, sizeof(uint32_t) * (D + 1), hipMemcpyDeviceToDevice, st));
+    return CSK_OK;
+}
+
+csk_status sketch_csr_run(const int64_t* row_ptr, const int32_t* col, const float* val, int64_t m, int64_t n,
+                          int64_t nnz, const double* b, int64_t d, uint64_t seed, double* At64, int64_t ldat64,
+                          void* At_lp, csk_dtype lp_dtype, int64_t ldat_lp, double* bt, double* nu2,
+                          void* ws, size_t ws_bytes, hipStream_t st)
+{
+    (void)nnz;
+    std::vector<SketchSys> hs(1);
+    SketchSys& S = hs[0];
+    S = SketchSys{};
+    S.B = b;
+    S.At64 = At64;
+    S.Atlp = At_lp;
+    S.Bt = bt;
+    S.nu2 = nu2;
+    S.ldat64 = ldat64;
+    S.ldatlp = ldat_lp;
+    S.m = m;
+    S.seed = seed;
+    S.n = static_cast<int32_t>(n);
+    S.d = static_cast<int32_t>(d);
+    S.nrhs = 1;
+    S.nchunks = 1;
+    Carve c(ws);
+    Batch bt_{};
+    SketchSys* d_sys = c.take<SketchSys>(1);
+    c.take<SketchSys>(1);
+    c.take<int64_t>(2);
+    c.take<int64_t>(2);
+    c.take<int64_t>(2);
+    c.take<int64_t>(2);
+    bt_.cnt = c.take<uint32_t>(d);
+    bt_.ptr = c.take<uint32_t>(d + 1);
+    bt_.perm = c.take<uint32_t>(m);
+    bt_.nu2part = c.take<double>(d);
+    bt_.scan_part = c.take<uint32_t>(d / kScanTile + 2);
+    if (c.bytes() > ws_bytes) {
+        set_error("sketch workspace too small: need %zu bytes, got %zu", c.bytes(), ws_bytes);
+        return CSK_ERR_WORKSPACE;
+    }
+    bt_.sys = d_sys;
+    bt_.M = m;
+    bt_.D = d;
+    bt_.T = d;
+    bt_.nsys = 1;
+    csk_status r;
+    if ((r = upload_descs(hs, d_sys, st)) != CSK_OK) return r;
+    if ((r = group_rows(bt_, st)) != CSK_OK) return r;
+    // accumulator chunk: up to 8192 columns (64 KB of LDS)
+    const int chunk = static_cast<int>(std::min<int64_t>(n, 8192));
+    const size_t shm = (size_t)chunk * 8;
+    const int grid = grid_for(d, 1, 1 << 20);
+    switch (lp_dtype) {
+    case CSK_F32:
+        CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_segsum_csr<CSK_F32>), hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+        k_segsum_csr<CSK_F32><<<grid, kCsrNT, shm, st>>>(bt_, row_ptr, col, val, chunk);
+        break;
+    case CSK_F16:
+        CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_segsum_csr<CSK_F16>), hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+        k_segsum_csr<CSK_F16><<<grid, kCsrNT, shm, st>>>(bt_, row_ptr, col, val, chunk);
+        break;
+    case CSK_BF16:
+        CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_segsum_csr<CSK_BF16>), hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+        k_segsum_csr<CSK_BF16><<<grid, kCsrNT, shm, st>>>(bt_, row_ptr, col, val, chunk);
+        break;
+    default:
+        CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_segsum_csr<0>), hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+        k_segsum_csr<0><<<grid, kCsrNT, shm, st>>>(bt_, row_ptr, col, val, chunk);
+        break;
+    }
+    CSK_LAUNCH_CHECK("k_segsum_csr");
+    return CSK_OK;
+}
+
+}  // namespace csk

@@ -1,0 +1,120 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry
+point declared in include/csk.h, and rejects bad arguments before touching a
+device.  No compute call is made here (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "csk.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+char\s*\*|csk_status|int32_t)\s+(csk_\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2004_02480_amd import _abi
+    return _abi.load()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("csk_hash", "csk_sketch", "csk_sketch_csr", "csk_solve", "csk_solve_batched",
+                     "csk_solve_mrhs", "csk_status_string"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_2004_02480_amd import _abi
+    names = declared_functions()
+    assert set(names) == set(_abi.EXPORTED)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    from paper_2004_02480_amd import _abi
+    for code, name in [(_abi.CSK_OK, "CSK_OK"), (_abi.CSK_ERR_NONFINITE, "CSK_ERR_NONFINITE"),
+                       (_abi.CSK_CANCELLED, "CSK_CANCELLED"), (_abi.CSK_ERR_DEGENERATE, "CSK_ERR_DEGENERATE")]:
+        assert lib.csk_status_string(code).decode() == name
+    assert lib.csk_version() >= 10000
+
+
+def test_invalid_arguments_rejected_on_host(lib):
+    from paper_2004_02480_amd import _abi
+    P = ctypes.c_void_p
+    assert lib.csk_hash(1, 0, 5, P(1), None, None) == _abi.CSK_ERR_INVALID_ARG
+    assert lib.csk_hash(1, 5, 0, P(1), None, None) == _abi.CSK_ERR_INVALID_ARG
+    assert lib.csk_hash(1, 5, 2**31, P(1), None, None) == _abi.CSK_ERR_INVALID_ARG
+    # sketch: null A, bad dtype, lda < n, no outputs
+    args = dict(A=None, at=_abi.CSK_F64, m=10, n=4, lda=4)
+    st = lib.csk_sketch(None, _abi.CSK_F64, 10, 4, 4, None, 0, 1, 5, 1, P(256), 4, None, 0, 4,
+                        None, 1, None, None, None, P(256), 1 << 20, None)
+    assert st == _abi.CSK_ERR_INVALID_ARG
+    st = lib.csk_sketch(P(256), _abi.CSK_F16, 10, 4, 4, None, 0, 1, 5, 1, P(256), 4, None, 0, 4,
+                        None, 1, None, None, None, P(256), 1 << 20, None)
+    assert st == _abi.CSK_ERR_UNSUPPORTED
+    st = lib.csk_sketch(P(256), _abi.CSK_F64, 10, 4, 3, None, 0, 1, 5, 1, P(256), 4, None, 0, 4,
+                        None, 1, None, None, None, P(256), 1 << 20, None)
+    assert st == _abi.CSK_ERR_INVALID_ARG
+    st = lib.csk_sketch(P(256), _abi.CSK_F64, 10, 4, 4, None, 0, 1, 5, 1, None, 4, None, 0, 4,
+                        None, 1, None, None, None, P(256), 1 << 20, None)
+    assert st == _abi.CSK_ERR_INVALID_ARG
+    # workspace too small is reported before any launch
+    st = lib.csk_sketch(P(256), _abi.CSK_F64, 10, 4, 4, None, 0, 1, 5, 1, P(256), 4, None, 0, 4,
+                        None, 1, None, None, None, P(256), 16, None)
+    assert st == _abi.CSK_ERR_WORKSPACE
+    # solve: missing opts, negative maxit, REL_ERR without x_ref, n too large
+    o = _abi.SolveOpts()
+    o.tol, o.maxit, o.stop_mode = 1e-10, 10, _abi.CSK_STOP_REL_ERR
+    assert lib.csk_solve(P(256), _abi.CSK_F64, 4, None, 4, 8, 4, P(256), None, None, P(256),
+                         None, P(256), P(256), 1 << 20, None) == _abi.CSK_ERR_INVALID_ARG
+    assert lib.csk_solve(P(256), _abi.CSK_F64, 4, None, 4, 8, 4, P(256), None, None, P(256),
+                         ctypes.byref(o), P(256), P(256), 1 << 20, None) == _abi.CSK_ERR_INVALID_ARG
+    o.maxit = -1
+    o.x_ref = 256
+    assert lib.csk_solve(P(256), _abi.CSK_F64, 4, None, 4, 8, 4, P(256), None, None, P(256),
+                         ctypes.byref(o), P(256), P(256), 1 << 20, None) == _abi.CSK_ERR_INVALID_ARG
+    o.maxit = 10
+    assert lib.csk_solve(P(256), _abi.CSK_F64, 9000, None, 9000, 8, 9000, P(256), None, None, P(256),
+                         ctypes.byref(o), P(256), P(256), 1 << 20, None) == _abi.CSK_ERR_UNSUPPORTED
+    # mixed precision without the FP64 sketch
+    assert lib.csk_solve(P(256), _abi.CSK_BF16, 4, None, 4, 8, 4, P(256), None, None, P(256),
+                         ctypes.byref(o), P(256), P(256), 1 << 20, None) == _abi.CSK_ERR_INVALID_ARG
+    msg = lib.csk_last_error().decode()
+    assert "At64" in msg
+
+
+def test_workspace_queries(lib):
+    sz = ctypes.c_size_t(0)
+    assert lib.csk_sketch_workspace_size(200000, 1000, 20000, 1, ctypes.byref(sz)) == 0
+    small = sz.value
+    assert lib.csk_sketch_workspace_size(400000, 1000, 20000, 1, ctypes.byref(sz)) == 0
+    assert sz.value > small >= 200000 * 4
+    assert lib.csk_solve_workspace_size(20000, 1000, 0, ctypes.byref(sz)) == 0
+    assert sz.value >= 20000 * 16
+    assert lib.csk_sketch_csr_workspace_size(1000000, 5000, 50000, ctypes.byref(sz)) == 0
+    assert lib.csk_solve_mrhs_workspace_size(10000, 500, 256, ctypes.byref(sz)) == 0
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    from paper_2004_02480_amd import _abi
+    with pytest.raises(ImportError):
+        _abi.load(str(tmp_path / "libcsk.so"))
+
+
+def test_product_does_not_reach_the_oracle():
+    # the product package never imports the checker
+    pkg = os.path.join(ROOT, "paper_2004_02480_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "csk_oracle" not in text, f

@@ -1,0 +1,167 @@
+"""GPU parity of the MWRK loop (Algorithm 1, loop; Section 3 stopping rule).
+
+Floating-point residuals are summed in a different order than the oracle's,
+so whole trajectories are compared through their results: the iterate after
+K steps agrees with the oracle's to ~1e-12 while no near-tie intervenes, and
+converged solutions agree with x* (and with the oracle's solution) to the
+requested tolerance.  Status paths, determinism and resume are checked
+directly."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2004_02480_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def relerr(x, xs):
+    x = x.cpu().numpy() if torch.is_tensor(x) else x
+    xs = xs.cpu().numpy() if torch.is_tensor(xs) else xs
+    return np.linalg.norm(x - xs) / np.linalg.norm(xs)
+
+
+def sketched(gpu, s, d, seed, lp=None):
+    out = gpu.csk_sketch(s.A, s.b, d, seed, lp_dtype=lp)
+    torch.cuda.synchronize()
+    return out
+
+
+@pytest.mark.parametrize("path", ["single", "grid"])
+def test_oracle_size_converges_and_matches_oracle(gpu, orc, path):
+    c = W.config("oracle_small")
+    s = W.gaussian(c["m"], c["n"], c["seed"], device=DEV)
+    sk = sketched(gpu, s, c["d"], c["sketch_seed"])
+    kw = dict(single_wg=1) if path == "single" else dict(single_wg=0, grid=8)
+    r = gpu.csk_solve(sk.At64, sk.bt, nu2=sk.nu2, x_ref=s.x_star, tol=1e-10, maxit=100000, **kw)
+    assert r.status == gpu.CSK_OK, r.status_name
+    assert relerr(r.x, s.x_star) <= 1e-10
+    o = orc.csk(s.A.cpu().numpy(), s.b.cpu().numpy(), c["d"], c["sketch_seed"], xref=s.x_star.cpu().numpy(),
+                tol=1e-10, maxit=100000)
+    assert relerr(r.x, o.x) <= 3e-10
+    assert abs(r.iters - o.iters) <= max(5, 0.1 * o.iters), (r.iters, o.iters)
+
+
+@pytest.mark.parametrize("path,K", [("single", 1), ("single", 7), ("single", 60), ("grid", 1), ("grid", 7),
+                                    ("grid", 60)])
+def test_iterates_match_oracle_step_by_step(gpu, orc, path, K):
+    s = W.gaussian(12000, 90, seed=21, device=DEV)
+    sk = sketched(gpu, s, 1100, 22)
+    kw = dict(single_wg=1) if path == "single" else dict(single_wg=0, grid=16)
+    r = gpu.csk_solve(sk.At64, sk.bt, nu2=sk.nu2, x_ref=s.x_star, tol=0.0, maxit=K, **kw)
+    assert r.status == gpu.CSK_NOT_CONVERGED and r.iters == K
+    o = orc.mwrk(sk.At64.cpu().numpy(), sk.bt.cpu().numpy(), xref=s.x_star.cpu().numpy(), tol=0.0, maxit=K)
+    assert np.linalg.norm(r.x.cpu().numpy() - o.x) <= 1e-12 * np.linalg.norm(o.x)
+
+
+def test_full_size_dense_coherent(gpu, orc):
+    # the benchmark workload end to end: every output checked against x*
+    # (any size) and the first iterates against the oracle
+    c = W.config("dense_coherent")
+    s = W.uniform01(c["m"], c["n"], c["seed"], device=DEV)
+    sk = sketched(gpu, s, c["d"], c["sketch_seed"])
+    r3 = gpu.csk_solve(sk.At64, sk.bt, nu2=sk.nu2, x_ref=s.x_star, tol=0.0, maxit=3)
+    o3 = orc.mwrk(sk.At64.cpu().numpy(), sk.bt.cpu().numpy(), xref=s.x_star.cpu().numpy(), tol=0.0, maxit=3)
+    assert np.linalg.norm(r3.x.cpu().numpy() - o3.x) <= 1e-12 * np.linalg.norm(o3.x)
+    r = gpu.csk_solve(sk.At64, sk.bt, nu2=sk.nu2, x_ref=s.x_star, tol=c["tol"], maxit=c["maxit"])
+    assert r.status == gpu.CSK_OK, r.status_name
+    assert relerr(r.x, s.x_star) <= 1e-10
+    print(f"dense_coherent iterations {r.iters}")
+
+
+@pytest.mark.parametrize("lp", [torch.bfloat16, torch.float16, torch.float32])
+def test_mixed_precision_reaches_1e10(gpu, lp):
+    s = W.row_scaled(60000, 200, seed=31, device=DEV)
+    sk = sketched(gpu, s, 2000, 32, lp=lp)
+    r64 = gpu.csk_solve(sk.At64, sk.bt, nu2=sk.nu2, x_ref=s.x_star, tol=1e-10, maxit=200000)
+    r = gpu.csk_solve(sk.At_lp, sk.bt, At64=sk.At64, nu2=sk.nu2, x_ref=s.x_star, tol=1e-10, maxit=200000)
+    assert r64.status == gpu.CSK_OK and r.status == gpu.CSK_OK, (r64.status_name, r.status_name)
+    assert relerr(r.x, s.x_star) <= 1e-10
+    assert r.iters <= 1.5 * r64.iters + 64, (r.iters, r64.iters)
+    assert r.refreshes >= r.iters // 64
+
+
+@pytest.mark.parametrize("path", ["single", "grid"])
+def test_residual_stopping_rule(gpu, path):
+    s = W.gaussian(20000, 60, seed=41, device=DEV)
+    sk = sketched(gpu, s, 1200, 42)
+    kw = dict(single_wg=1) if path == "single" else dict(single_wg=0, grid=12)
+    r = gpu.csk_solve(sk.At64, sk.bt, nu2=sk.nu2, tol=1e-9, maxit=100000, stop_mode=gpu.CSK_STOP_REL_RESID, **kw)
+    assert r.status == gpu.CSK_OK
+    res = (sk.bt - sk.At64 @ r.x).norm() / sk.bt.norm()
+    assert res.item() <= 1e-9 * (1 + 1e-6)
+    rb = gpu.csk_solve(sk.At_lp if sk.At_lp is not None else sk.At64.float(), sk.bt, At64=sk.At64, nu2=sk.nu2,
+                       tol=1e-9, maxit=100000, stop_mode=gpu.CSK_STOP_REL_RESID, **kw)
+    assert rb.status == gpu.CSK_OK
+    res = (sk.bt - sk.At64 @ rb.x).norm() / sk.bt.norm()
+    assert res.item() <= 1e-9 * (1 + 1e-6)
+
+
+@pytest.mark.parametrize("path", ["single", "grid"])
+def test_status_paths(gpu, path):
+    kw = dict(single_wg=1) if path == "single" else dict(single_wg=0, grid=4)
+    n = 8
+    z = torch.zeros((40, n), dtype=torch.float64, device=DEV)
+    xr = torch.ones(n, dtype=torch.float64, device=DEV)
+    r = gpu.csk_solve(z, torch.zeros(40, dtype=torch.float64, device=DEV), x_ref=xr, tol=1e-10, maxit=10, **kw)
+    assert r.status == gpu.CSK_ERR_DEGENERATE and r.iters == 0
+    A = torch.eye(n, dtype=torch.float64, device=DEV).repeat(5, 1)
+    bt = A @ xr
+    bt[3] = float("nan")
+    r = gpu.csk_solve(A, bt, x_ref=xr, tol=1e-10, maxit=10, **kw)
+    assert r.status == gpu.CSK_ERR_NONFINITE
+    s = W.gaussian(500, 10, seed=1, device=DEV)
+    r = gpu.csk_solve(s.A, s.b, x_ref=s.x_star, tol=1e-14, maxit=3, **kw)
+    assert r.status == gpu.CSK_NOT_CONVERGED and r.iters == 3
+    # a solve that starts at the solution stops before any projection
+    r = gpu.csk_solve(s.A, s.b, x0=s.x_star, x_ref=s.x_star, tol=1e-10, maxit=3, **kw)
+    assert r.status == gpu.CSK_OK and r.iters == 0
+
+
+def test_cancel_word(gpu):
+    # host-mapped pinned word set before the launch: the solve stops at its
+    # first poll with CSK_CANCELLED (no kernel waits on the host)
+    flag = torch.ones(1, dtype=torch.int32).pin_memory()
+    s = W.gaussian(4000, 30, seed=2, device=DEV)
+    for kw in (dict(single_wg=1), dict(single_wg=0, grid=4)):
+        r = gpu.csk_solve(s.A, s.b, x_ref=s.x_star, tol=1e-12, maxit=1000, cancel=flag.data_ptr(), **kw)
+        assert r.status == gpu.CSK_CANCELLED and r.iters == 0
+    flag.zero_()
+    r = gpu.csk_solve(s.A, s.b, x_ref=s.x_star, tol=1e-12, maxit=100000, cancel=flag.data_ptr())
+    assert r.status == gpu.CSK_OK
+
+
+@pytest.mark.parametrize("path", ["single", "grid"])
+def test_deterministic_and_resumable(gpu, path):
+    kw = dict(single_wg=1) if path == "single" else dict(single_wg=0, grid=32)
+    s = W.gaussian(40000, 150, seed=51, device=DEV)
+    sk = sketched(gpu, s, 3000, 52)
+    a = gpu.csk_solve(sk.At64, sk.bt, nu2=sk.nu2, x_ref=s.x_star, tol=0.0, maxit=300, **kw)
+    b = gpu.csk_solve(sk.At64, sk.bt, nu2=sk.nu2, x_ref=s.x_star, tol=0.0, maxit=300, **kw)
+    assert torch.equal(a.x, b.x)
+    h = gpu.csk_solve(sk.At64, sk.bt, nu2=sk.nu2, x_ref=s.x_star, tol=0.0, maxit=120, **kw)
+    c = gpu.csk_solve(sk.At64, sk.bt, nu2=sk.nu2, x0=h.x.clone(), x_ref=s.x_star, tol=0.0, maxit=180, **kw)
+    assert torch.equal(a.x, c.x)
+
+
+def test_nu2_computed_when_absent(gpu):
+    s = W.gaussian(8000, 64, seed=61, device=DEV)
+    sk = sketched(gpu, s, 700, 62)
+    a = gpu.csk_solve(sk.At64, sk.bt, nu2=sk.nu2, x_ref=s.x_star, tol=1e-10)
+    b = gpu.csk_solve(sk.At64, sk.bt, x_ref=s.x_star, tol=1e-10)
+    assert a.status == b.status == gpu.CSK_OK
+    assert relerr(b.x, s.x_star) <= 1e-10
+
+
+def test_mixed_full_size_row_scaled(gpu):
+    c = W.config("row_scaled")
+    s = W.row_scaled(c["m"], c["n"], c["seed"], device=DEV)
+    sk = sketched(gpu, s, c["d"], c["sketch_seed"], lp=torch.bfloat16)
+    r = gpu.csk_solve(sk.At_lp, sk.bt, At64=sk.At64, nu2=sk.nu2, x_ref=s.x_star, tol=1e-10, maxit=c["maxit"])
+    assert r.status == gpu.CSK_OK, r.status_name
+    assert relerr(r.x, s.x_star) <= 1e-10
+    print(f"row_scaled bf16 iterations {r.iters} refreshes {r.refreshes} fallback {r.fp64_fallback}")
