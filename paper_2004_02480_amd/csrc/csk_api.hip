@@ -146,7 +146,7 @@ csk_status check_batch(const csk_system_desc* sys, int32_t nsys, csk_dtype a_dty
     for (int s = 0; s < nsys; ++s) {
         const csk_system_desc& D = sys[s];
         if (!D.A || !D.b || !D.x) { set_error("system %d: A, b and x are required", s); return CSK_ERR_INVALID_ARG; }
-        if (D.m < 1 || D.n < 1 || D.d < 1 || D.lda < D.n || D.m >= INT32_MAX || D.d >= INT32_MAX) {
+        if (D.m < 1 || D.n < 1 || D.d < 1 || D.lda < D.n || D.m > INT32_MAX || D.d > INT32_MAX) {
             set_error("system %d: bad sizes (m=%lld n=%lld d=%lld lda=%lld)", s, (long long)D.m, (long long)D.n,
                       (long long)D.d, (long long)D.lda);
             return CSK_ERR_INVALID_ARG;
@@ -186,7 +186,7 @@ int32_t csk_version(void) { return 10000; }
 csk_status csk_hash(uint64_t seed, int64_t m, int64_t d, uint32_t* bucket, int8_t* sign, void* stream)
 {
     g_err[0] = 0;
-    if (m < 1 || d < 1 || d >= INT32_MAX) { set_error("need m >= 1 and 1 <= d < 2^31"); return CSK_ERR_INVALID_ARG; }
+    if (m < 1 || d < 1 || d > INT32_MAX) { set_error("need m >= 1 and 1 <= d < 2^31"); return CSK_ERR_INVALID_ARG; }
     if (!bucket && !sign) return CSK_OK;
     const int grid = (int)std::min<int64_t>((m + 255) / 256, 16384);
     k_hash_rows<<<grid, 256, 0, as_stream(stream)>>>(seed, m, (uint32_t)d, bucket, sign);
@@ -212,7 +212,7 @@ csk_status csk_sketch(const void* A, csk_dtype a_dtype, int64_t m, int64_t n, in
     g_err[0] = 0;
     if (!A) { set_error("A is NULL"); return CSK_ERR_INVALID_ARG; }
     if (a_dtype != CSK_F64 && a_dtype != CSK_F32) { set_error("A must be F64 or F32"); return CSK_ERR_UNSUPPORTED; }
-    if (m < 1 || n < 1 || d < 1 || m >= INT32_MAX || d >= INT32_MAX || n >= INT32_MAX) {
+    if (m < 1 || n < 1 || d < 1 || m > INT32_MAX || d > INT32_MAX || n > INT32_MAX) {
         set_error("need 1 <= m, d < 2^31 and n >= 1");
         return CSK_ERR_INVALID_ARG;
     }
@@ -264,7 +264,7 @@ csk_status csk_sketch_csr(const int64_t* row_ptr, const int32_t* col, const floa
 {
     g_err[0] = 0;
     if (!row_ptr || (nnz > 0 && (!col || !val))) { set_error("row_ptr / col / val required"); return CSK_ERR_INVALID_ARG; }
-    if (m < 1 || n < 1 || d < 1 || nnz < 0 || m >= INT32_MAX || d >= INT32_MAX || n >= INT32_MAX) {
+    if (m < 1 || n < 1 || d < 1 || nnz < 0 || m > INT32_MAX || d > INT32_MAX || n > INT32_MAX) {
         set_error("need 1 <= m, d < 2^31, n >= 1, nnz >= 0");
         return CSK_ERR_INVALID_ARG;
     }
@@ -295,7 +295,7 @@ csk_status csk_solve(const void* At, csk_dtype at_dtype, int64_t ldat, const dou
     g_err[0] = 0;
     csk_status st = check_opts(opts);
     if (st != CSK_OK) return st;
-    if (d < 1 || n < 1 || d >= INT32_MAX) { set_error("need 1 <= d < 2^31, n >= 1"); return CSK_ERR_INVALID_ARG; }
+    if (d < 1 || n < 1 || d > INT32_MAX) { set_error("need 1 <= d < 2^31, n >= 1"); return CSK_ERR_INVALID_ARG; }
     if (n > kMaxN) { set_error("n=%lld exceeds %lld", (long long)n, (long long)kMaxN); return CSK_ERR_UNSUPPORTED; }
     if (!bt || !x || !res) { set_error("bt, x and res are required"); return CSK_ERR_INVALID_ARG; }
     if (at_dtype == CSK_F64) {
@@ -482,7 +482,7 @@ csk_status csk_solve_mrhs(const void* At_lp, csk_dtype lp_dtype, int64_t ldat_lp
     if (st != CSK_OK) return st;
     if (lp_dtype != CSK_BF16 && lp_dtype != CSK_F16) { set_error("lp_dtype must be BF16 or F16"); return CSK_ERR_UNSUPPORTED; }
     if (!At_lp || !At64 || !Bt || !X || !res || !nu2) { set_error("At_lp, At64, Bt, nu2, X and res are required"); return CSK_ERR_INVALID_ARG; }
-    if (d < 1 || n < 1 || nrhs < 1 || d >= INT32_MAX || nrhs >= INT32_MAX) { set_error("bad sizes"); return CSK_ERR_INVALID_ARG; }
+    if (d < 1 || n < 1 || nrhs < 1 || d > INT32_MAX || nrhs > INT32_MAX) { set_error("bad sizes"); return CSK_ERR_INVALID_ARG; }
     if (n > 1024) { set_error("n=%lld exceeds 1024", (long long)n); return CSK_ERR_UNSUPPORTED; }
     if (ldat_lp < n || ldat64 < n || ldbt < nrhs || ldx < nrhs) { set_error("leading dimension too small"); return CSK_ERR_INVALID_ARG; }
     if (opts->stop_mode == CSK_STOP_REL_ERR && (!Xref || ldxref < nrhs)) { set_error("CSK_STOP_REL_ERR needs Xref"); return CSK_ERR_INVALID_ARG; }

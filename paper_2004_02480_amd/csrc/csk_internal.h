@@ -40,15 +40,26 @@ __device__ __forceinline__ double draw_sign(uint64_t w)
 // round-to-nearest-even steps (FP64 -> FP32 -> 16-bit); the conversions are
 // the compiler's IEEE conversions for __bf16 and _Float16.
 // ---------------------------------------------------------------------------
+// The FP32 intermediate is pinned in a register (empty asm) so the compiler
+// cannot fuse the two conversions into one direct FP64 -> 16-bit rounding,
+// which differs from the two-step result when the FP64 value lies within
+// one FP32 ulp of a 16-bit halfway point.
+__device__ __forceinline__ float f64_to_f32_pinned(double v)
+{
+    float f = static_cast<float>(v);
+    asm volatile("" : "+v"(f));
+    return f;
+}
+
 __device__ __forceinline__ uint16_t f64_to_bf16_bits(double v)
 {
-    __bf16 h = static_cast<__bf16>(static_cast<float>(v));
+    __bf16 h = static_cast<__bf16>(f64_to_f32_pinned(v));
     return __builtin_bit_cast(uint16_t, h);
 }
 
 __device__ __forceinline__ uint16_t f64_to_f16_bits(double v)
 {
-    _Float16 h = static_cast<_Float16>(static_cast<float>(v));
+    _Float16 h = static_cast<_Float16>(f64_to_f32_pinned(v));
     return __builtin_bit_cast(uint16_t, h);
 }
 

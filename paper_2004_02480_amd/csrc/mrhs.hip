@@ -1,21 +1,498 @@
-// mrhs.hip -- one sketch, many right-hand sides (placeholder until the
-// matrix-core solver lands).
+// mrhs.hip -- one sketch At, many right-hand sides: the loop of Algorithm 1
+// run independently for every column j of Bt, with all columns' residuals
+// formed together on the matrix cores.
+//
+// Per iteration (one persistent cooperative launch, two grid barriers):
+//   1. residual block R = R_ref - At_lp * Delta for the workgroup's rows and
+//      128 columns, with Delta = X - X_ref rounded to BF16/FP16 and the
+//      product on v_mfma_f32_16x16x32 (FP32 accumulation); every
+//      refresh_every iterations R_ref = Bt - At64 * X exactly, on the FP64
+//      matrix cores (v_mfma_f64_16x16x4), and Delta restarts from zero;
+//   2. per column, the best row of the block by r^2 / ||At^(i)||^2 (the
+//      squared weighted residual of the paper), published to global memory;
+//   3. barrier; the owner workgroup of column j reduces the row blocks' bests
+//      in fixed order, applies the stop test and the projection
+//      X[:, j] += (r / ||At^(i)||^2) At64^(i)^T, and writes Delta[:, j];
+//   4. barrier; the run ends when no column is active.
+// Scores and projections use the FP64 rows, as in the single-system solver.
+#include "csk_grid.h"
 #include "csk_mrhs.h"
 
+#include <algorithm>
+
 namespace csk {
+namespace {
+
+constexpr int kNT = 512;          // 8 wavefronts
+constexpr int kCols = 128;        // columns per workgroup (one 16-column tile per wavefront)
+constexpr int kMaxRT = 8;         // 16-row tiles per workgroup
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+struct CandRec {
+    double score, r, r2;
+    uint32_t idx, flags;
+};
+
+struct MCtl {
+    const uint16_t* Alp;      // rows_pad x npad, zero padded
+    const double* A64;        // d x n, lda64
+    const double* Bt;         // d x R, ldbt
+    const double* nu2;        // d
+    double* XT;               // Rpad x npad: column j of X is row j
+    double* XrT;              // Rpad x npad: X at the last refresh
+    const double* XuT;        // Rpad x npad: reference solution, or null
+    uint16_t* DT;             // Rpad x npad: Delta in 16-bit
+    CandRec* cand;            // RB x Rpad
+    const double* colref2;    // Rpad: ||Xref[:, j]||^2
+    const double* colbt2;     // Rpad: ||Bt[:, j]||^2
+    csk_solve_result* res;    // R
+    uint32_t* barrier;
+    uint32_t* active;
+    int32_t* cancel_seen;
+    const volatile int32_t* cancel;
+    double tol2;
+    int64_t maxit;
+    int64_t lda64, ldbt;
+    int32_t d, n, npad, R, Rpad, RB, CB, refresh_every, check_every, stop_mode;
+};
+
+template <class Tag> struct Mfma;
+template <> struct Mfma<tag_bf16> {
+    __device__ static f32x4 run(const uint16_t* a, const uint16_t* b, f32x4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const bf16x8*>(a),
+                                                       *reinterpret_cast<const bf16x8*>(b), c, 0, 0, 0);
+    }
+    __device__ static uint16_t round(double v) { return f64_to_bf16_bits(v); }
+};
+template <> struct Mfma<tag_f16> {
+    __device__ static f32x4 run(const uint16_t* a, const uint16_t* b, f32x4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(*reinterpret_cast<const f16x8*>(a),
+                                                      *reinterpret_cast<const f16x8*>(b), c, 0, 0, 0);
+    }
+    __device__ static uint16_t round(double v) { return f64_to_f16_bits(v); }
+};
+
+template <class Tag, int RT>
+__global__ __launch_bounds__(kNT) void k_mrhs(MCtl C)
+{
+    __shared__ GridRed slots[kNT / kWave];
+    __shared__ uint32_t s_ok;
+    __shared__ double s_nu2[RT * 16];
+    __shared__ int32_t s_done[8];
+
+    const int tid = threadIdx.x;
+    const int G = gridDim.x;
+    const int rb = blockIdx.x / C.CB;
+    const int cb = blockIdx.x % C.CB;
+    const int w = tid / kWave;
+    const int lane = tid & (kWave - 1);
+    const int lc = lane & 15;          // MFMA lane column / A-row
+    const int lg = lane >> 4;          // MFMA lane group
+    const int row0 = rb * RT * 16;
+    const int mycol = cb * kCols + w * 16 + lc;
+    const int n = C.n, d = C.d, R = C.R;
+
+    for (int i = tid; i < RT * 16; i += kNT) s_nu2[i] = (row0 + i < d) ? C.nu2[row0 + i] : 0.0;
+    if (tid < 8) s_done[tid] = 0;
+    __syncthreads();
+
+    double rref[RT][4];
+    uint32_t epoch = 0;
+    int64_t k_ref = 0, nref = 0;
+    for (int64_t k = 0;; ++k) {
+        const bool refresh = (k == 0) || (k - k_ref >= C.refresh_every);
+        // the current residual is rref - acc: acc = 0 right after a refresh
+        f32x4 acc[RT];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) acc[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        if (refresh) {
+            f64x4 acc64[RT];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) acc64[rt] = f64x4{0.0, 0.0, 0.0, 0.0};
+            for (int kk = 0; kk < n; kk += 4) {
+                const int kq = kk + lg;
+                const double bv = C.XT[(int64_t)mycol * C.npad + kq];
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) {
+                    const int row = row0 + rt * 16 + lc;
+                    const double av = (row < d && kq < n) ? C.A64[(int64_t)row * C.lda64 + kq] : 0.0;
+                    acc64[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc64[rt], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int row = row0 + rt * 16 + 4 * lg + q;
+                    rref[rt][q] = (row < d && mycol < R) ? C.Bt[(int64_t)row * C.ldbt + mycol] - acc64[rt][q] : 0.0;
+                }
+            k_ref = k;
+            ++nref;
+        } else {
+            const uint16_t* bcol = C.DT + (int64_t)mycol * C.npad + lg * 8;
+            for (int kk = 0; kk < C.npad; kk += 32) {
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) {
+                    const uint16_t* arow = C.Alp + (int64_t)(row0 + rt * 16 + lc) * C.npad + lg * 8 + kk;
+                    acc[rt] = Mfma<Tag>::run(arow, bcol + kk, acc[rt]);
+                }
+            }
+        }
+
+        // best row of this block for column mycol
+        GridRed cv = red_identity();
+        if (mycol < R) {
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int lr = rt * 16 + 4 * lg + q;
+                    const int row = row0 + lr;
+                    if (row < d) {
+                        const double r = rref[rt][q] - static_cast<double>(acc[rt][q]);
+                        cv.r2 += r * r;
+                        const double nn = s_nu2[lr];
+                        if (nn > 0.0) {
+                            const double score = (r * r) / nn;
+                            if (!isfinite(score)) cv.flags |= kFlagNonfinite;
+                            else if (cand_better(score, (uint32_t)row, cv.score, cv.idx)) {
+                                cv.score = score;
+                                cv.r = r;
+                                cv.idx = (uint32_t)row;
+                            }
+                        } else if (isnan(nn)) {
+                            cv.flags |= kFlagNonfinite;
+                        }
+                    }
+                }
+        }
+        // lanes lc, lc+16, lc+32, lc+48 share a column
+#pragma unroll
+        for (int off = 16; off < 64; off <<= 1) {
+            GridRed o;
+            o.score = __shfl_xor(cv.score, off, kWave);
+            o.r = __shfl_xor(cv.r, off, kWave);
+            o.r2 = __shfl_xor(cv.r2, off, kWave);
+            o.e2 = 0.0;
+            o.idx = __shfl_xor(cv.idx, off, kWave);
+            o.flags = __shfl_xor(cv.flags, off, kWave);
+            cv = red_combine(cv, o);
+        }
+        if (lg == 0 && mycol < R) {
+            CandRec c;
+            c.score = cv.score;
+            c.r = cv.r;
+            c.r2 = cv.r2;
+            c.idx = cv.idx;
+            c.flags = cv.flags;
+            C.cand[(int64_t)rb * C.Rpad + mycol] = c;
+        }
+        if (blockIdx.x == 0 && tid == 0 && C.cancel && (k % C.check_every) == 0 && *C.cancel != 0)
+            *C.cancel_seen = 1;
+        ++epoch;
+        bool ok = grid_barrier(C.barrier, epoch * (uint32_t)G, &s_ok);
+
+        // owner phase: column j belongs to workgroup j mod G
+        const int32_t cancelled = __hip_atomic_load(C.cancel_seen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int t = 0;
+        for (int j = blockIdx.x; j < R; j += G, ++t) {
+            if (s_done[t]) continue;
+            GridRed v = red_identity();
+            for (int b = tid; b < C.RB; b += kNT) {
+                const CandRec c = C.cand[(int64_t)b * C.Rpad + j];
+                GridRed o;
+                o.score = c.score;
+                o.r = c.r;
+                o.r2 = c.r2;
+                o.e2 = 0.0;
+                o.idx = c.idx;
+                o.flags = c.flags;
+                v = red_combine(v, o);
+            }
+            double* xj = C.XT + (int64_t)j * C.npad;
+            if (C.XuT)
+                for (int q = tid; q < n; q += kNT) {
+                    const double e = xj[q] - C.XuT[(int64_t)j * C.npad + q];
+                    v.e2 += e * e;
+                }
+            const GridRed tot = block_red<kNT>(v, slots);
+            int32_t status = -1;
+            double meas;
+            bool conv;
+            if (C.stop_mode == CSK_STOP_REL_ERR) {
+                const double ref2 = C.colref2[j];
+                meas = ref2 > 0.0 ? tot.e2 / ref2 : tot.e2;
+                conv = ref2 > 0.0 ? (tot.e2 / ref2 <= C.tol2) : (tot.e2 <= C.tol2);
+            } else {
+                const double bt2 = C.colbt2[j];
+                meas = bt2 > 0.0 ? tot.r2 / bt2 : tot.r2;
+                conv = refresh && tot.r2 <= C.tol2 * bt2;
+            }
+            if (conv) status = CSK_OK;
+            else if (k == C.maxit) status = CSK_NOT_CONVERGED;
+            else if (!ok) status = CSK_ERR_DEVICE;
+            else if (cancelled) status = CSK_CANCELLED;
+            else if (tot.flags & kFlagNonfinite) status = CSK_ERR_NONFINITE;
+            else if (tot.idx == kNoRow) status = CSK_ERR_DEGENERATE;
+            if (status >= 0) {
+                if (tid == 0) {
+                    C.res[j].iters = k;
+                    C.res[j].status = status;
+                    C.res[j].fp64_fallback = 0;
+                    C.res[j].final_measure = meas;
+                    C.res[j].refreshes = nref;
+                    s_done[t] = 1;
+                    __hip_atomic_fetch_sub(C.active, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                __syncthreads();
+                continue;
+            }
+            const double alpha = tot.r / C.nu2[tot.idx];
+            const double* arow = C.A64 + (int64_t)tot.idx * C.lda64;
+            double* xr = C.XrT + (int64_t)j * C.npad;
+            uint16_t* dj = C.DT + (int64_t)j * C.npad;
+            for (int q = tid; q < n; q += kNT) {
+                const double x = xj[q];
+                double base;
+                if (refresh) {
+                    xr[q] = x;
+                    base = x;
+                } else {
+                    base = xr[q];
+                }
+                const double xn = x + alpha * arow[q];
+                xj[q] = xn;
+                dj[q] = Mfma<Tag>::round(xn - base);
+            }
+        }
+        ++epoch;
+        ok = grid_barrier(C.barrier, epoch * (uint32_t)G, &s_ok) && ok;
+        const uint32_t left = __hip_atomic_load(C.active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (left == 0u || !ok) break;
+    }
+}
+
+// ---- set-up and tear-down kernels ------------------------------------------
+
+__global__ void k_pad_lp(const uint16_t* __restrict__ src, int64_t lds, int d, int n, uint16_t* __restrict__ dst,
+                         int rows_pad, int npad)
+{
+    const int64_t total = (int64_t)rows_pad * npad;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = e / npad;
+        const int c = (int)(e - r * npad);
+        dst[e] = (r < d && c < n) ? src[r * lds + c] : uint16_t(0);
+    }
+}
+
+__global__ void k_init_cols(const double* __restrict__ X0, int64_t ldx, const double* __restrict__ Xref,
+                            int64_t ldxref, int n, int R, int Rpad, int npad, double* XT, double* XrT, double* XuT,
+                            uint16_t* DT)
+{
+    const int64_t total = (int64_t)Rpad * npad;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(e / npad);
+        const int q = (int)(e - (int64_t)j * npad);
+        const bool in = j < R && q < n;
+        const double x = (in && X0) ? X0[(int64_t)q * ldx + j] : 0.0;
+        XT[e] = x;
+        XrT[e] = x;
+        DT[e] = 0;
+        if (XuT) XuT[e] = (in && Xref) ? Xref[(int64_t)q * ldxref + j] : 0.0;
+    }
+}
+
+// One workgroup per column: ||Xref[:, j]||^2 and ||Bt[:, j]||^2.
+__global__ __launch_bounds__(256) void k_col_norms(const double* __restrict__ XuT, int npad, int n,
+                                                   const double* __restrict__ Bt, int64_t ldbt, int d,
+                                                   double* colref2, double* colbt2)
+{
+    __shared__ double red[2][4];
+    const int j = blockIdx.x;
+    double a = 0.0, b = 0.0;
+    if (XuT)
+        for (int q = threadIdx.x; q < n; q += 256) a += XuT[(int64_t)j * npad + q] * XuT[(int64_t)j * npad + q];
+    for (int i = threadIdx.x; i < d; i += 256) b += Bt[(int64_t)i * ldbt + j] * Bt[(int64_t)i * ldbt + j];
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x / 64] = a;
+        red[1][threadIdx.x / 64] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        colref2[j] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+        colbt2[j] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    }
+}
+
+__global__ void k_init_counters(uint32_t* barrier, uint32_t* active, int32_t* cancel_seen, int R)
+{
+    if (threadIdx.x == 0) {
+        *barrier = 0u;
+        *active = (uint32_t)R;
+        *cancel_seen = 0;
+    }
+}
+
+__global__ void k_store_x(const double* __restrict__ XT, int npad, int n, int R, double* X, int64_t ldx)
+{
+    const int64_t total = (int64_t)n * R;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int q = (int)(e / R);
+        const int j = (int)(e - (int64_t)q * R);
+        X[(int64_t)q * ldx + j] = XT[(int64_t)j * npad + q];
+    }
+}
+
+struct Geom {
+    int CB, RB, RT, rows_pad, npad, Rpad;
+};
+
+Geom geom(int64_t d, int64_t n, int64_t R)
+{
+    Geom g;
+    const int cus = std::max(1, device_cu_count());
+    g.CB = (int)((R + kCols - 1) / kCols);
+    const int rb_max = std::max(1, cus / g.CB);
+    const int64_t rows_per = (d + rb_max - 1) / rb_max;
+    g.RT = (int)((rows_per + 15) / 16);
+    g.RB = (int)((d + 16 * g.RT - 1) / (16 * g.RT));
+    g.rows_pad = g.RB * 16 * g.RT;
+    g.npad = (int)((n + 31) / 32 * 32);
+    g.Rpad = g.CB * kCols;
+    return g;
+}
+
+int grid_for(int64_t items, int cap)
+{
+    return (int)std::max<int64_t>(1, std::min<int64_t>((items + 255) / 256, cap));
+}
+
+template <class Tag, int RT>
+csk_status launch_mrhs(const MCtl& C, int G, hipStream_t st)
+{
+    auto kern = k_mrhs<Tag, RT>;
+    int per_cu = 0;
+    CSK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern), kNT, 0));
+    if (G > per_cu * device_cu_count()) {
+        set_error("multi-RHS grid of %d workgroups exceeds the %d co-resident ones", G, per_cu * device_cu_count());
+        return CSK_ERR_UNSUPPORTED;
+    }
+    MCtl arg = C;
+    void* args[] = {&arg};
+    CSK_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(G), dim3(kNT), args, 0, st));
+    return CSK_OK;
+}
+
+template <class Tag>
+csk_status dispatch(const MCtl& C, int RT, int G, hipStream_t st)
+{
+    switch (RT) {
+    case 1: return launch_mrhs<Tag, 1>(C, G, st);
+    case 2: return launch_mrhs<Tag, 2>(C, G, st);
+    case 3: return launch_mrhs<Tag, 3>(C, G, st);
+    case 4: return launch_mrhs<Tag, 4>(C, G, st);
+    case 5: return launch_mrhs<Tag, 5>(C, G, st);
+    case 6: return launch_mrhs<Tag, 6>(C, G, st);
+    case 7: return launch_mrhs<Tag, 7>(C, G, st);
+    case 8: return launch_mrhs<Tag, 8>(C, G, st);
+    default: set_error("multi-RHS: %d row tiles per workgroup unsupported", RT); return CSK_ERR_UNSUPPORTED;
+    }
+}
+
+}  // namespace
 
 size_t mrhs_ws_bytes(int64_t d, int64_t n, int64_t nrhs)
 {
-    (void)d; (void)n; (void)nrhs;
-    return 256;
+    const Geom g = geom(d, n, nrhs);
+    Carve c(nullptr);
+    c.take<uint16_t>((size_t)g.rows_pad * g.npad);
+    c.take<double>((size_t)g.Rpad * g.npad);
+    c.take<double>((size_t)g.Rpad * g.npad);
+    c.take<double>((size_t)g.Rpad * g.npad);
+    c.take<uint16_t>((size_t)g.Rpad * g.npad);
+    c.take<CandRec>((size_t)g.RB * g.Rpad);
+    c.take<double>(g.Rpad);
+    c.take<double>(g.Rpad);
+    c.take<uint32_t>(64);
+    return c.bytes();
 }
 
-csk_status mrhs_run(const void*, csk_dtype, int64_t, const double*, int64_t, int64_t, int64_t, const double*,
-                    int64_t, int64_t, const double*, const double*, double*, int64_t, const double*, int64_t,
-                    const csk_solve_opts*, csk_solve_result*, void*, size_t, hipStream_t)
+csk_status mrhs_run(const void* At_lp, csk_dtype lp_dtype, int64_t ldat_lp, const double* At64, int64_t ldat64,
+                    int64_t d, int64_t n, const double* Bt, int64_t nrhs, int64_t ldbt, const double* nu2,
+                    const double* X0, double* X, int64_t ldx, const double* Xref, int64_t ldxref,
+                    const csk_solve_opts* o, csk_solve_result* res, void* ws, size_t ws_bytes, hipStream_t st)
 {
-    set_error("multi-right-hand-side solver not built");
-    return CSK_ERR_UNSUPPORTED;
+    const Geom g = geom(d, n, nrhs);
+    if (g.RT > kMaxRT) {
+        set_error("multi-RHS: d=%lld needs %d row tiles per workgroup (max %d)", (long long)d, g.RT, kMaxRT);
+        return CSK_ERR_UNSUPPORTED;
+    }
+    Carve c(ws);
+    MCtl C{};
+    uint16_t* alp = c.take<uint16_t>((size_t)g.rows_pad * g.npad);
+    C.XT = c.take<double>((size_t)g.Rpad * g.npad);
+    C.XrT = c.take<double>((size_t)g.Rpad * g.npad);
+    double* xut = c.take<double>((size_t)g.Rpad * g.npad);
+    C.DT = c.take<uint16_t>((size_t)g.Rpad * g.npad);
+    C.cand = c.take<CandRec>((size_t)g.RB * g.Rpad);
+    double* colref2 = c.take<double>(g.Rpad);
+    double* colbt2 = c.take<double>(g.Rpad);
+    uint32_t* ctr = c.take<uint32_t>(64);
+    if (c.bytes() > ws_bytes) {
+        set_error("multi-RHS workspace too small: need %zu bytes, got %zu", c.bytes(), ws_bytes);
+        return CSK_ERR_WORKSPACE;
+    }
+    C.Alp = alp;
+    C.A64 = At64;
+    C.lda64 = ldat64;
+    C.Bt = Bt;
+    C.ldbt = ldbt;
+    C.nu2 = nu2;
+    C.XuT = (o->stop_mode == CSK_STOP_REL_ERR) ? xut : nullptr;
+    C.colref2 = colref2;
+    C.colbt2 = colbt2;
+    C.res = res;
+    C.barrier = ctr;
+    C.active = ctr + 1;
+    C.cancel_seen = reinterpret_cast<int32_t*>(ctr + 2);
+    C.cancel = o->cancel;
+    C.tol2 = o->tol * o->tol;
+    C.maxit = o->maxit;
+    C.d = (int32_t)d;
+    C.n = (int32_t)n;
+    C.npad = g.npad;
+    C.R = (int32_t)nrhs;
+    C.Rpad = g.Rpad;
+    C.RB = g.RB;
+    C.CB = g.CB;
+    C.refresh_every = o->refresh_every > 0 ? o->refresh_every : 64;
+    C.check_every = o->check_every > 0 ? o->check_every : 256;
+    C.stop_mode = o->stop_mode;
+
+    k_pad_lp<<<grid_for((int64_t)g.rows_pad * g.npad, 8192), 256, 0, st>>>(
+        static_cast<const uint16_t*>(At_lp), ldat_lp, (int)d, (int)n, alp, g.rows_pad, g.npad);
+    CSK_LAUNCH_CHECK("k_pad_lp");
+    k_init_cols<<<grid_for((int64_t)g.Rpad * g.npad, 8192), 256, 0, st>>>(
+        X0, ldx, Xref, ldxref, (int)n, (int)nrhs, g.Rpad, g.npad, C.XT, C.XrT, C.XuT ? xut : nullptr, C.DT);
+    CSK_LAUNCH_CHECK("k_init_cols");
+    k_col_norms<<<(int)nrhs, 256, 0, st>>>(C.XuT, g.npad, (int)n, Bt, ldbt, (int)d, colref2, colbt2);
+    CSK_LAUNCH_CHECK("k_col_norms");
+    k_init_counters<<<1, 64, 0, st>>>(C.barrier, C.active, C.cancel_seen, (int)nrhs);
+    CSK_LAUNCH_CHECK("k_init_counters");
+    const int G = g.RB * g.CB;
+    csk_status r = (lp_dtype == CSK_BF16) ? dispatch<tag_bf16>(C, g.RT, G, st) : dispatch<tag_f16>(C, g.RT, G, st);
+    if (r != CSK_OK) return r;
+    k_store_x<<<grid_for(n * nrhs, 8192), 256, 0, st>>>(C.XT, g.npad, (int)n, (int)nrhs, X, ldx);
+    CSK_LAUNCH_CHECK("k_store_x");
+    return CSK_OK;
 }
 
 }  // namespace csk

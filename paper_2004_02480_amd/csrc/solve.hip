@@ -22,6 +22,7 @@
 // Small systems run the same loop in one workgroup (no grid barrier); the
 // batched kernel hands whole systems to workgroups from an atomic queue.
 #include "csk_solve.h"
+#include "csk_grid.h"
 
 #include <algorithm>
 #include <cmath>
@@ -31,19 +32,12 @@ namespace {
 
 constexpr int kNT = 512;        // threads per workgroup
 constexpr int kNW = kNT / kWave;
+using Red = GridRed;
 constexpr int kCPT = 16;        // owned columns per thread: n <= kNT * kCPT
 constexpr int kR = 2;           // rows in flight per lane group
-constexpr uint32_t kSpinLimit = 5u * 1000u * 1000u;  // several seconds
 
-enum : uint32_t { kFlagNonfinite = 1u, kFlagCancel = 2u, kFlagTimeout = 4u };
 
 struct tag_f64 { using storage = double; };
-
-// One workgroup's contribution to an iteration, and the reduction record.
-struct Red {
-    double score, r, r2, e2;
-    uint32_t idx, flags;
-};
 
 struct Ctl {
     double tol2;
@@ -57,60 +51,6 @@ struct Ctl {
     int32_t nsys;
     int32_t pad_;
 };
-
-__device__ __forceinline__ Red red_identity()
-{
-    Red v;
-    v.score = 0.0;
-    v.r = 0.0;
-    v.r2 = 0.0;
-    v.e2 = 0.0;
-    v.idx = kNoRow;
-    v.flags = 0u;
-    return v;
-}
-
-__device__ __forceinline__ Red red_combine(Red a, const Red& b)
-{
-    if (cand_better(b.score, b.idx, a.score, a.idx)) {
-        a.score = b.score;
-        a.r = b.r;
-        a.idx = b.idx;
-    }
-    a.r2 = a.r2 + b.r2;
-    a.e2 = a.e2 + b.e2;
-    a.flags |= b.flags;
-    return a;
-}
-
-__device__ __forceinline__ Red wave_red(Red v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        Red o;
-        o.score = __shfl_xor(v.score, off, kWave);
-        o.r = __shfl_xor(v.r, off, kWave);
-        o.r2 = __shfl_xor(v.r2, off, kWave);
-        o.e2 = __shfl_xor(v.e2, off, kWave);
-        o.idx = __shfl_xor(v.idx, off, kWave);
-        o.flags = __shfl_xor(v.flags, off, kWave);
-        v = red_combine(v, o);
-    }
-    return v;
-}
-
-// Fixed-shape reduction over the workgroup; every thread gets the result.
-__device__ __forceinline__ Red block_red(Red v, Red* slots)
-{
-    v = wave_red(v);
-    if ((threadIdx.x & (kWave - 1)) == 0) slots[threadIdx.x / kWave] = v;
-    __syncthreads();
-    Red t = slots[0];
-#pragma unroll
-    for (int w = 1; w < kNW; ++w) t = red_combine(t, slots[w]);
-    __syncthreads();
-    return t;
-}
 
 template <class T, int W>
 __device__ __forceinline__ T group_sum_t(T v)
@@ -229,25 +169,6 @@ __device__ __forceinline__ void residual_rows(const typename Elem<Tag>::S* __res
     }
 }
 
-// Grid barrier: arrival counter with release/acquire at device scope; the
-// spin is bounded so a kernel always terminates.
-__device__ __forceinline__ bool grid_barrier(uint32_t* ctr, uint32_t target, uint32_t* s_ok)
-{
-    if (threadIdx.x == 0) {
-        uint32_t ok = 1u;
-        __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        uint32_t spins = 0;
-        while (static_cast<int32_t>(__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
-            __builtin_amdgcn_s_sleep(1);
-            if (++spins > kSpinLimit) { ok = 0u; break; }
-        }
-        *s_ok = ok;
-    }
-    __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    return *s_ok != 0u;
-}
-
 template <class Tag, bool VEC, int LPR, bool GRID>
 __device__ void solve_loop(const SolveSys& S, const Ctl& C, int wg, int G, char* smem)
 {
@@ -286,7 +207,7 @@ __device__ void solve_loop(const SolveSys& S, const Ctl& C, int wg, int G, char*
     if (S.xref)
         for (int c = tid; c < n; c += kNT) q.e2 += S.xref[c] * S.xref[c];
     for (int i = tid; i < d; i += kNT) q.r2 += S.bt[i] * S.bt[i];
-    q = block_red(q, slots);
+    q = block_red<kNT>(q, slots);
     const double xref2 = q.e2;
     const double bt2 = q.r2;
     const double tol2 = C.tol2;
@@ -320,7 +241,7 @@ __device__ void solve_loop(const SolveSys& S, const Ctl& C, int wg, int G, char*
             }
         if (wg == 0 && tid == 0 && C.cancel && (k % C.check_every) == 0 && *C.cancel != 0)
             loc.flags |= kFlagCancel;
-        Red tot = block_red(loc, slots);
+        Red tot = block_red<kNT>(loc, slots);
         if constexpr (GRID) {
             Red* rec = C.exch + (size_t)(k & 1) * G;
             if (tid == 0) rec[wg] = tot;
@@ -328,7 +249,7 @@ __device__ void solve_loop(const SolveSys& S, const Ctl& C, int wg, int G, char*
             const bool ok = grid_barrier(C.barrier, epoch * (uint32_t)G, &s_ok);
             Red all = red_identity();
             for (int w = tid; w < G; w += kNT) all = red_combine(all, rec[w]);
-            tot = block_red(all, slots);
+            tot = block_red<kNT>(all, slots);
             if (!ok) tot.flags |= kFlagTimeout;
         }
 
