@@ -192,6 +192,36 @@ def batched_workload(P, W, torch):
                 total_iters=int(sum(r[0] for r in res)), a_bytes=a_bytes, redraws=redraws)
 
 
+def mrhs_workload(P, W, torch):
+    """A 200000 x 500 FP32 Gaussian, 256 right-hand sides, d = 10000: sketch of
+    A and B together, then all columns solved to 1e-8 with BF16 matrix-core
+    residual products and FP64 refresh."""
+    c = W.config("multi_rhs")
+    dev = "cuda:0"
+    log("[bench] generating multi_rhs A 200000x500 FP32, 256 right-hand sides")
+    s = W.multi_rhs(c["m"], c["n"], c["nrhs"], c["seed"], device=dev)
+    torch.cuda.synchronize()
+    sk_run = lambda: P.csk_sketch(s.A, s.B, c["d"], c["sketch_seed"], lp_dtype=torch.bfloat16)
+    sk_run()
+    t_sk, sk = timed(sk_run)
+    solve = lambda: P.csk_solve_mrhs(sk.At_lp, sk.At64, sk.bt, sk.nu2, Xref=s.X_star, tol=c["tol"],
+                                     maxit=c["maxit"], sync=False)
+    solve()
+    t_sv, (X, raw) = timed(solve)
+    res = P.parse_results(raw)
+    ok = sum(1 for r in res if r[1] == P.CSK_OK)
+    its = max(r[0] for r in res)
+    err = ((X - s.X_star).norm(dim=0) / s.X_star.norm(dim=0)).max().item()
+    flops = 2.0 * c["d"] * c["n"] * c["nrhs"] * its
+    log(f"[bench] multi_rhs: sketch {t_sk * 1e3:.2f} ms, solve {t_sv * 1e3:.1f} ms, {its} iterations, "
+        f"{ok}/{c['nrhs']} converged, worst rel {err:.2e}, {flops / t_sv / 1e12:.1f} TFLOP/s (BF16 MFMA)")
+    del s, sk
+    torch.cuda.empty_cache()
+    return dict(sketch_s=t_sk, solve_s=t_sv, time_s=t_sk + t_sv, iters=its, converged=ok, worst_relerr=err,
+                rhs_per_s=c["nrhs"] / (t_sk + t_sv), mfma_tflops=flops / t_sv / 1e12,
+                mfma_frac_bf16_peak=flops / t_sv / 2.5e15)
+
+
 def csr_workload(P, W, torch, solve=True):
     """CSR A 1e6 x 5000 at 0.1%, d = 50000: sketch bandwidth, and the mixed
     FP32 solve to 1e-8."""
@@ -254,6 +284,7 @@ def main():
         extra["row_scaled_mixed"] = mixed_workload(P, W, torch)
         extra["sparse_csr"] = csr_workload(P, W, torch)
         extra["batched_512"] = batched_workload(P, W, torch)
+        extra["multi_rhs_256"] = mrhs_workload(P, W, torch)
 
     line = {
         "metric": METRIC,

@@ -421,6 +421,7 @@ csk_status csk_solve_batched(const csk_system_desc* sys, int32_t nsys, csk_dtype
 
     // 2. solver descriptors, largest estimated work first
     std::vector<SolveSys> hs(nsys);
+    int64_t npad_max = 0;
     for (int s = 0; s < nsys; ++s) {
         SolveSys& S = hs[s];
         S = SolveSys{};
@@ -438,6 +439,8 @@ csk_status csk_solve_batched(const csk_system_desc* sys, int32_t nsys, csk_dtype
         S.d = (int32_t)sys[s].d;
         S.n = (int32_t)sys[s].n;
         S.stop_mode = sys[s].x_ref ? CSK_STOP_REL_ERR : CSK_STOP_REL_RESID;
+        S.npad = (int32_t)solve_npad(sys[s].n, lp_dtype, solve_batch_lpr(), true);
+        npad_max = std::max<int64_t>(npad_max, S.npad);
     }
     for (int k = 0; k < nsys; k += 24) {
         SysPack pack;
@@ -460,7 +463,8 @@ csk_status csk_solve_batched(const csk_system_desc* sys, int32_t nsys, csk_dtype
         k_store_order<<<1, 256, 0, stm>>>(pack, cnt, d_order + k);
         CSK_LAUNCH_CHECK("k_store_order");
     }
-    return solve_batched_run(d_sys, d_order, nsys, n_max, lp_dtype, opts, d_queue, stm);
+    (void)n_max;
+    return solve_batched_run(d_sys, d_order, nsys, npad_max, lp_dtype, opts, d_queue, stm);
 }
 
 csk_status csk_solve_mrhs_workspace_size(int64_t d, int64_t n, int64_t nrhs, size_t* bytes)

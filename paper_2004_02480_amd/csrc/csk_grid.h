@@ -79,8 +79,18 @@ __device__ __forceinline__ GridRed block_red(GridRed v, GridRed* slots)
 // Grid barrier: arrival counter (zeroed before launch) with release/acquire
 // at device scope; epoch e waits for e * G arrivals.  The spin is bounded,
 // so a kernel always terminates; false means the wait timed out.
+// Only thread 0 performs the device-scope release, and a workgroup barrier
+// by itself does not wait for other wavefronts' stores to complete.  When
+// wavefronts other than the one holding thread 0 wrote data that other
+// workgroups read after the barrier, ALL_WAVES makes every wavefront wait
+// for its stores before the workgroup barrier, so the release covers them.
+template <bool ALL_WAVES = false>
 __device__ __forceinline__ bool grid_barrier(uint32_t* ctr, uint32_t target, uint32_t* s_ok)
 {
+    if constexpr (ALL_WAVES) {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    }
     if (threadIdx.x == 0) {
         uint32_t ok = 1u;
         __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);

@@ -19,7 +19,7 @@ struct SolveSys {
     int64_t ldat, ldat64;
     int32_t d, n;
     int32_t stop_mode;
-    int32_t pad_;
+    int32_t npad;         // LDS length of the operand vectors (>= n, zero-padded)
 };
 
 struct SolvePlan {
@@ -32,14 +32,19 @@ struct SolvePlan {
 SolvePlan solve_plan(int64_t d, int64_t n, csk_dtype at_dtype, int64_t ldat, const void* At,
                      const csk_solve_opts* o);
 size_t solve_ws_bytes(int64_t d, int64_t n, int grid);
+// Operand length in LDS for a row of n columns with the given lanes per row.
+int64_t solve_npad(int64_t n, csk_dtype at_dtype, int lpr, bool vec);
+// Lanes per row used by the batched kernel.
+int solve_batch_lpr();
 
 csk_status solve_run(const SolveSys& sys, csk_dtype at_dtype, const csk_solve_opts* o,
                      void* ws, size_t ws_bytes, hipStream_t st);
 
-// Batched: `sys` is a device array of nsys systems; `order` (device, nsys)
-// lists them in the order the work queue hands them out.
+// Batched: `sys` is a device array of nsys systems (rows 16-byte aligned,
+// npad from solve_npad with solve_batch_lpr()); `order` (device, nsys) lists
+// them in the order the work queue hands them out.
 csk_status solve_batched_run(const SolveSys* sys_dev, const int32_t* order_dev, int32_t nsys,
-                             int64_t n_max, csk_dtype at_dtype, const csk_solve_opts* o,
+                             int64_t npad_max, csk_dtype at_dtype, const csk_solve_opts* o,
                              uint32_t* queue_dev, hipStream_t st);
 
 }  // namespace csk

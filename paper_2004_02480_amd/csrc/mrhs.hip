@@ -26,6 +26,7 @@ namespace {
 constexpr int kNT = 512;          // 8 wavefronts
 constexpr int kCols = 128;        // columns per workgroup (one 16-column tile per wavefront)
 constexpr int kMaxRT = 8;         // 16-row tiles per workgroup
+constexpr int kMaxOwned = 8;      // columns owned (reduced and projected) per workgroup
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
@@ -49,6 +50,7 @@ struct MCtl {
     CandRec* cand;            // RB x Rpad
     const double* colref2;    // Rpad: ||Xref[:, j]||^2
     const double* colbt2;     // Rpad: ||Bt[:, j]||^2
+    double* dinv;             // Rpad: 2^-e_j, Delta[:, j] is stored as Delta * 2^e_j
     csk_solve_result* res;    // R
     uint32_t* barrier;
     uint32_t* active;
@@ -84,7 +86,8 @@ __global__ __launch_bounds__(kNT) void k_mrhs(MCtl C)
     __shared__ GridRed slots[kNT / kWave];
     __shared__ uint32_t s_ok;
     __shared__ double s_nu2[RT * 16];
-    __shared__ int32_t s_done[8];
+    __shared__ int32_t s_done[kMaxOwned];
+    __shared__ double s_scale[kMaxOwned];
 
     const int tid = threadIdx.x;
     const int G = gridDim.x;
@@ -96,10 +99,17 @@ __global__ __launch_bounds__(kNT) void k_mrhs(MCtl C)
     const int lg = lane >> 4;          // MFMA lane group
     const int row0 = rb * RT * 16;
     const int mycol = cb * kCols + w * 16 + lc;
+    // v_mfma_f64_16x16x4 returns row 4q + lg of its A operand in register q
+    // of lane group lg, while the 16-bit products return row 4lg + q there.
+    // Loading A-operand row i from row 4(i%4) + i/4 makes both agree.
+    const int arow_perm = 4 * (lc & 3) + (lc >> 2);
     const int n = C.n, d = C.d, R = C.R;
 
     for (int i = tid; i < RT * 16; i += kNT) s_nu2[i] = (row0 + i < d) ? C.nu2[row0 + i] : 0.0;
-    if (tid < 8) s_done[tid] = 0;
+    if (tid < kMaxOwned) {
+        s_done[tid] = 0;
+        s_scale[tid] = 1.0;
+    }
     __syncthreads();
 
     double rref[RT][4];
@@ -120,7 +130,7 @@ __global__ __launch_bounds__(kNT) void k_mrhs(MCtl C)
                 const double bv = C.XT[(int64_t)mycol * C.npad + kq];
 #pragma unroll
                 for (int rt = 0; rt < RT; ++rt) {
-                    const int row = row0 + rt * 16 + lc;
+                    const int row = row0 + rt * 16 + arow_perm;
                     const double av = (row < d && kq < n) ? C.A64[(int64_t)row * C.lda64 + kq] : 0.0;
                     acc64[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc64[rt], 0, 0, 0);
                 }
@@ -145,6 +155,8 @@ __global__ __launch_bounds__(kNT) void k_mrhs(MCtl C)
             }
         }
 
+        // Delta of this column is stored scaled by an exact power of two
+        const double dinv = (mycol < R) ? C.dinv[mycol] : 1.0;
         // best row of this block for column mycol
         GridRed cv = red_identity();
         if (mycol < R) {
@@ -155,7 +167,7 @@ __global__ __launch_bounds__(kNT) void k_mrhs(MCtl C)
                     const int lr = rt * 16 + 4 * lg + q;
                     const int row = row0 + lr;
                     if (row < d) {
-                        const double r = rref[rt][q] - static_cast<double>(acc[rt][q]);
+                        const double r = rref[rt][q] - static_cast<double>(acc[rt][q]) * dinv;
                         cv.r2 += r * r;
                         const double nn = s_nu2[lr];
                         if (nn > 0.0) {
@@ -196,7 +208,7 @@ __global__ __launch_bounds__(kNT) void k_mrhs(MCtl C)
         if (blockIdx.x == 0 && tid == 0 && C.cancel && (k % C.check_every) == 0 && *C.cancel != 0)
             *C.cancel_seen = 1;
         ++epoch;
-        bool ok = grid_barrier(C.barrier, epoch * (uint32_t)G, &s_ok);
+        bool ok = grid_barrier<true>(C.barrier, epoch * (uint32_t)G, &s_ok);
 
         // owner phase: column j belongs to workgroup j mod G
         const int32_t cancelled = __hip_atomic_load(C.cancel_seen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -240,6 +252,7 @@ __global__ __launch_bounds__(kNT) void k_mrhs(MCtl C)
             else if (cancelled) status = CSK_CANCELLED;
             else if (tot.flags & kFlagNonfinite) status = CSK_ERR_NONFINITE;
             else if (tot.idx == kNoRow) status = CSK_ERR_DEGENERATE;
+            else if (tot.idx >= (uint32_t)d) status = CSK_ERR_DEVICE;  // never dereference a bad row
             if (status >= 0) {
                 if (tid == 0) {
                     C.res[j].iters = k;
@@ -255,6 +268,19 @@ __global__ __launch_bounds__(kNT) void k_mrhs(MCtl C)
             }
             const double alpha = tot.r / C.nu2[tot.idx];
             const double* arow = C.A64 + (int64_t)tot.idx * C.lda64;
+            // At a refresh Delta restarts at alpha * a; scale it by 2^e with
+            // ||alpha a|| * 2^e in [16, 32) so the 16-bit operand keeps its
+            // precision (FP16's exponent range is narrow) as x converges.
+            if (refresh) {
+                const double v = fabs(alpha) * sqrt(C.nu2[tot.idx]);
+                int e = 0;
+                if (v > 0.0 && isfinite(v)) e = 4 - ilogb(v);
+                e = e < -960 ? -960 : (e > 960 ? 960 : e);
+                if (tid == 0) C.dinv[j] = ldexp(1.0, -e);
+                s_scale[t] = ldexp(1.0, e);
+            }
+            __syncthreads();
+            const double dscale = s_scale[t];
             double* xr = C.XrT + (int64_t)j * C.npad;
             uint16_t* dj = C.DT + (int64_t)j * C.npad;
             for (int q = tid; q < n; q += kNT) {
@@ -268,11 +294,11 @@ __global__ __launch_bounds__(kNT) void k_mrhs(MCtl C)
                 }
                 const double xn = x + alpha * arow[q];
                 xj[q] = xn;
-                dj[q] = Mfma<Tag>::round(xn - base);
+                dj[q] = Mfma<Tag>::round((xn - base) * dscale);
             }
         }
         ++epoch;
-        ok = grid_barrier(C.barrier, epoch * (uint32_t)G, &s_ok) && ok;
+        ok = grid_barrier<true>(C.barrier, epoch * (uint32_t)G, &s_ok) && ok;
         const uint32_t left = __hip_atomic_load(C.active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (left == 0u || !ok) break;
     }
@@ -332,12 +358,24 @@ __global__ __launch_bounds__(256) void k_col_norms(const double* __restrict__ Xu
     }
 }
 
-__global__ void k_init_counters(uint32_t* barrier, uint32_t* active, int32_t* cancel_seen, int R)
+__global__ void k_init_counters(uint32_t* barrier, uint32_t* active, int32_t* cancel_seen, int R,
+                                CandRec* cand, int64_t ncand, double* dinv, int Rpad)
 {
-    if (threadIdx.x == 0) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < Rpad; e += (int64_t)gridDim.x * blockDim.x)
+        dinv[e] = 1.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         *barrier = 0u;
         *active = (uint32_t)R;
         *cancel_seen = 0;
+    }
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ncand; e += (int64_t)gridDim.x * blockDim.x) {
+        CandRec c;
+        c.score = 0.0;
+        c.r = 0.0;
+        c.r2 = 0.0;
+        c.idx = kNoRow;
+        c.flags = 0u;
+        cand[e] = c;
     }
 }
 
@@ -421,6 +459,7 @@ size_t mrhs_ws_bytes(int64_t d, int64_t n, int64_t nrhs)
     c.take<CandRec>((size_t)g.RB * g.Rpad);
     c.take<double>(g.Rpad);
     c.take<double>(g.Rpad);
+    c.take<double>(g.Rpad);
     c.take<uint32_t>(64);
     return c.bytes();
 }
@@ -431,6 +470,11 @@ csk_status mrhs_run(const void* At_lp, csk_dtype lp_dtype, int64_t ldat_lp, cons
                     const csk_solve_opts* o, csk_solve_result* res, void* ws, size_t ws_bytes, hipStream_t st)
 {
     const Geom g = geom(d, n, nrhs);
+    if ((nrhs + (int64_t)g.RB * g.CB - 1) / ((int64_t)g.RB * g.CB) > kMaxOwned) {
+        set_error("multi-RHS: %lld right-hand sides on %d workgroups exceed %d per workgroup", (long long)nrhs,
+                  g.RB * g.CB, kMaxOwned);
+        return CSK_ERR_UNSUPPORTED;
+    }
     if (g.RT > kMaxRT) {
         set_error("multi-RHS: d=%lld needs %d row tiles per workgroup (max %d)", (long long)d, g.RT, kMaxRT);
         return CSK_ERR_UNSUPPORTED;
@@ -445,6 +489,7 @@ csk_status mrhs_run(const void* At_lp, csk_dtype lp_dtype, int64_t ldat_lp, cons
     C.cand = c.take<CandRec>((size_t)g.RB * g.Rpad);
     double* colref2 = c.take<double>(g.Rpad);
     double* colbt2 = c.take<double>(g.Rpad);
+    C.dinv = c.take<double>(g.Rpad);
     uint32_t* ctr = c.take<uint32_t>(64);
     if (c.bytes() > ws_bytes) {
         set_error("multi-RHS workspace too small: need %zu bytes, got %zu", c.bytes(), ws_bytes);
@@ -485,7 +530,10 @@ csk_status mrhs_run(const void* At_lp, csk_dtype lp_dtype, int64_t ldat_lp, cons
     CSK_LAUNCH_CHECK("k_init_cols");
     k_col_norms<<<(int)nrhs, 256, 0, st>>>(C.XuT, g.npad, (int)n, Bt, ldbt, (int)d, colref2, colbt2);
     CSK_LAUNCH_CHECK("k_col_norms");
-    k_init_counters<<<1, 64, 0, st>>>(C.barrier, C.active, C.cancel_seen, (int)nrhs);
+    k_init_counters<<<grid_for((int64_t)g.RB * g.Rpad, 1024), 256, 0, st>>>(C.barrier, C.active, C.cancel_seen,
+                                                                              (int)nrhs, C.cand,
+                                                                              (int64_t)g.RB * g.Rpad, C.dinv,
+                                                                              g.Rpad);
     CSK_LAUNCH_CHECK("k_init_counters");
     const int G = g.RB * g.CB;
     csk_status r = (lp_dtype == CSK_BF16) ? dispatch<tag_bf16>(C, g.RT, G, st) : dispatch<tag_f16>(C, g.RT, G, st);

@@ -237,29 +237,6 @@ template <class T> struct VecOf;
 template <> struct VecOf<double> { static constexpr int kW = 2; using type = double2; };
 template <> struct VecOf<float> { static constexpr int kW = 4; using type = float4; };
 
-template <class T, int VW> struct Loader;
-template <class T> struct Loader<T, 1> {
-    __device__ static void load(const T* p, double* out) { out[0] = static_cast<double>(*p); }
-};
-template <> struct Loader<double, 2> {
-    __device__ static void load(const double* p, double* out)
-    {
-        const double2 v = *reinterpret_cast<const double2*>(p);
-        out[0] = v.x;
-        out[1] = v.y;
-    }
-};
-template <> struct Loader<float, 4> {
-    __device__ static void load(const float* p, double* out)
-    {
-        const float4 v = *reinterpret_cast<const float4*>(p);
-        out[0] = v.x;
-        out[1] = v.y;
-        out[2] = v.z;
-        out[3] = v.w;
-    }
-};
-
 // LP: 0 none, 1 f32, 2 f16, 3 bf16 (matches csk_dtype values for 1..3).
 template <int LP>
 __device__ __forceinline__ void store_lp(void* base, int64_t off, double v)
@@ -269,11 +246,38 @@ __device__ __forceinline__ void store_lp(void* base, int64_t off, double v)
     if constexpr (LP == CSK_BF16) static_cast<uint16_t*>(base)[off] = round_store<tag_bf16>(v);
 }
 
+// Raw element loads of one lane's part of a row chunk: VPL vectors of VW
+// elements (16 bytes each when VW > 1); columns at or past n read as zero.
+template <class TA, int VW, int VPL>
+__device__ __forceinline__ void load_row_chunk(TA (&v)[VPL][VW], const TA* __restrict__ rowp, int col0, int lane, int n,
+                                               bool on)
+{
+#pragma unroll
+    for (int q = 0; q < VPL; ++q) {
+        const int col = col0 + (q * kWave + lane) * VW;
+        if (on && col + VW <= n) {
+            if constexpr (VW == 1) {
+                v[q][0] = rowp[col];
+            } else {
+                using V = typename VecOf<TA>::type;
+                const V x = *reinterpret_cast<const V*>(rowp + col);
+                static_assert(sizeof(V) == sizeof(TA) * VW, "vector width");
+                __builtin_memcpy(&v[q][0], &x, sizeof(V));
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < VW; ++e) v[q][e] = (on && col + e < n) ? rowp[col + e] : TA(0);
+        }
+    }
+}
+
 // One wavefront per (bucket, column chunk).  A chunk is VPL vectors of VW
-// elements per lane, i.e. 64*VW*VPL columns.  Rows of the bucket are taken
-// in ascending order (perm is sorted), U at a time for memory-level
-// parallelism; every accumulation stays in the order of the rows.
-template <class TA, int VW, int VPL, int U, int LP>
+// elements per lane, i.e. 64*VW*VPL columns.  The bucket's row indices are
+// read 64 at a time (one per lane, with their signs and b values); the rows
+// then stream through a ring of D row slots whose indices are broadcast from
+// those lanes, so D rows are always in flight.  Every accumulation stays in
+// ascending row order, sequential per output element (one lane each).
+template <class TA, int VW, int VPL, int D, int LP>
 __global__ __launch_bounds__(256) void k_segsum(Batch b)
 {
     constexpr int CW = kWave * VW * VPL;
@@ -288,61 +292,59 @@ __global__ __launch_bounds__(256) void k_segsum(Batch b)
         const int n = S.n;
         const int col0 = c * CW;
         const TA* __restrict__ A = static_cast<const TA*>(S.A);
+        const int64_t lda = S.lda;
         const uint32_t beg = b.ptr[S.bkt_off + j];
         const uint32_t end = b.ptr[S.bkt_off + j + 1];
         const bool with_b = (S.B != nullptr) && c == 0;
 
         double acc[VPL][VW];
 #pragma unroll
-        for (int v = 0; v < VPL; ++v)
+        for (int q = 0; q < VPL; ++q)
 #pragma unroll
-            for (int e = 0; e < VW; ++e) acc[v][e] = 0.0;
+            for (int e = 0; e < VW; ++e) acc[q][e] = 0.0;
         double bacc = 0.0;
 
-        for (uint32_t p = beg; p < end; p += U) {
-            uint32_t row[U];
-            double sg[U];
-            double val[U][VPL][VW];
+        for (uint32_t base = beg; base < end; base += kWave) {
+            const int cnt = static_cast<int>(min((uint32_t)kWave, end - base));
+            const uint32_t my_row = lane < cnt ? b.perm[base + lane] : 0u;
+            const double my_sg = draw_sign(draw_word(S.seed, my_row));
+            const double my_b = (with_b && lane < cnt) ? S.B[(int64_t)my_row * S.ldb] : 0.0;
+            TA val[D][VPL][VW];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const bool ok = p + u < end;
-                row[u] = ok ? b.perm[p + u] : 0u;
-                sg[u] = draw_sign(draw_word(S.seed, row[u]));
-#pragma unroll
-                for (int v = 0; v < VPL; ++v) {
-                    const int col = col0 + (v * kWave + lane) * VW;
-                    const TA* src = A + (int64_t)row[u] * S.lda + col;
-                    if (ok && col + VW <= n) {
-                        Loader<TA, VW>::load(src, val[u][v]);
-                    } else {
-#pragma unroll
-                        for (int e = 0; e < VW; ++e)
-                            val[u][v][e] = (ok && col + e < n) ? static_cast<double>(src[e]) : 0.0;
-                    }
-                }
+            for (int u = 0; u < D; ++u) {
+                const uint32_t row = __builtin_amdgcn_readlane(my_row, u < cnt ? u : 0);
+                load_row_chunk<TA, VW, VPL>(val[u], A + (int64_t)row * lda, col0, lane, n, u < cnt);
             }
+            for (int p = 0; p < cnt; p += D) {
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (p + u < end) {
+                for (int u = 0; u < D; ++u) {
+                    const int qi = p + u;
+                    if (qi < cnt) {
+                        const double sg = __shfl(my_sg, qi, kWave);
 #pragma unroll
-                    for (int v = 0; v < VPL; ++v)
+                        for (int q = 0; q < VPL; ++q)
 #pragma unroll
-                        for (int e = 0; e < VW; ++e) acc[v][e] = acc[v][e] + sg[u] * val[u][v][e];
-                    if (with_b) bacc = bacc + sg[u] * S.B[(int64_t)row[u] * S.ldb];
+                            for (int e = 0; e < VW; ++e)
+                                acc[q][e] = acc[q][e] + sg * static_cast<double>(val[u][q][e]);
+                        if (with_b) bacc = bacc + sg * __shfl(my_b, qi, kWave);
+                        const int nq = qi + D;
+                        const uint32_t row = __builtin_amdgcn_readlane(my_row, nq < cnt ? nq : 0);
+                        load_row_chunk<TA, VW, VPL>(val[u], A + (int64_t)row * lda, col0, lane, n, nq < cnt);
+                    }
                 }
             }
         }
 
         double nrm = 0.0;
 #pragma unroll
-        for (int v = 0; v < VPL; ++v) {
-            const int col = col0 + (v * kWave + lane) * VW;
+        for (int q = 0; q < VPL; ++q) {
+            const int col = col0 + (q * kWave + lane) * VW;
 #pragma unroll
             for (int e = 0; e < VW; ++e) {
                 if (col + e < n) {
-                    nrm += acc[v][e] * acc[v][e];
-                    if (S.At64) S.At64[j * S.ldat64 + col + e] = acc[v][e];
-                    if constexpr (LP != 0) store_lp<LP>(S.Atlp, j * S.ldatlp + col + e, acc[v][e]);
+                    nrm += acc[q][e] * acc[q][e];
+                    if (S.At64) S.At64[j * S.ldat64 + col + e] = acc[q][e];
+                    if constexpr (LP != 0) store_lp<LP>(S.Atlp, j * S.ldatlp + col + e, acc[q][e]);
                 }
             }
         }
@@ -549,8 +551,8 @@ Geometry pick_geometry(int64_t n_max, csk_dtype a_dtype, bool vec_ok)
 template <class TA, int VW, int VPL, int LP>
 void launch_segsum_lp(const Batch& b, hipStream_t st)
 {
-    constexpr int U = (VPL >= 4) ? 4 : 8;
-    k_segsum<TA, VW, VPL, U, LP><<<grid_for(b.T, 4, 1 << 20), 256, 0, st>>>(b);
+    constexpr int D = (VPL >= 4) ? 4 : 8;  // rows in flight per wavefront
+    k_segsum<TA, VW, VPL, D, LP><<<grid_for(b.T, 4, 1 << 20), 256, 0, st>>>(b);
 }
 
 template <class TA, int VW, int VPL>

@@ -2,55 +2,117 @@
 // on the sketched system (At, bt), as one persistent kernel.
 //
 // Every iteration k, with no host round trip:
-//   1. residual r_i = bt_i - At^(i) x_k for the workgroup's own block of rows
-//      (bandwidth-bound: At is streamed once per iteration; x sits in LDS);
+//   1. residual r_i = bt_i - At^(i) x_k for the workgroup's own block of rows.
+//      The product is bandwidth-bound: At streams through a ring of kD chunks
+//      per lane (kK 16-byte vectors each) so enough loads are in flight to
+//      cover HBM latency; x sits in LDS.
 //   2. weighted score r_i^2 / ||At^(i)||^2 (the square of the paper's
 //      |r_i| / ||At^(i)||, same argmax), best row of the workgroup through
 //      wavefront butterflies and LDS;
-//   3. (grid path) one grid-wide barrier: each workgroup publishes its best
-//      row, partial ||r||^2 and partial ||x - x_ref||^2, then every workgroup
-//      reduces all records in the same fixed order, so all agree on i_k and
-//      on the stop decision without a second barrier;
+//   3. (grid path) each workgroup publishes its best row (score, step length
+//      alpha = r / ||At^(i)||^2, index), partial ||r||^2 and partial
+//      ||x - x_ref||^2 in its own record, release-stored with the iteration
+//      as tag; every workgroup polls all tags in parallel and reduces the
+//      records in the same fixed order, so all agree on i_k and on the stop
+//      decision.  No shared read-modify-write counter is contended.
 //   4. stop test (Section 3's RES, or the sketched residual), then the
-//      projection x += (r_{i_k} / ||At^(i_k)||^2) At^(i_k)^T, applied by every
-//      workgroup to its own copy of x (each thread owns fixed columns).
+//      projection x += alpha At^(i_k)^T, applied by every workgroup to its
+//      own copy of x (each thread owns fixed columns).
 // Mixed precision: At is held in FP32/FP16/BF16 and the FP64 sketch At64 is
 // kept beside it.  Every `refresh_every` iterations the exact FP64 residual
 // r_ref = bt - At64 x is formed and x_ref = x saved; in between the residual
 // is r_ref - At (x - x_ref) with FP32 accumulation, so each inner iteration
 // streams 2-4x fewer bytes.  Scores and projections use the FP64 rows.
-// Small systems run the same loop in one workgroup (no grid barrier); the
+// Small systems run the same loop in one workgroup (no exchange); the
 // batched kernel hands whole systems to workgroups from an atomic queue.
-#include "csk_solve.h"
 #include "csk_grid.h"
+#include "csk_solve.h"
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 namespace csk {
 namespace {
 
 constexpr int kNT = 512;        // threads per workgroup
 constexpr int kNW = kNT / kWave;
-using Red = GridRed;
 constexpr int kCPT = 16;        // owned columns per thread: n <= kNT * kCPT
-constexpr int kR = 2;           // rows in flight per lane group
+constexpr int kK = 8;           // 16-byte vectors per lane per chunk (FP64, FP32)
+constexpr int kK16 = 4;         // ... for the 16-bit types (8 elements per vector)
 
+using Red = GridRed;            // Red.r carries the step length alpha
 
 struct tag_f64 { using storage = double; };
+
+// Chunks in flight per lane (each chunk holds KK 16-byte vectors): 3 for
+// FP64 (8 vectors), 2 for FP32 (8 vectors), 3 for the 16-bit types (4).
+template <class Tag> constexpr int ring_depth() { return std::is_same<Tag, tag_f64>::value ? 3 : std::is_same<Tag, tag_f32>::value ? 2 : 3; }
+template <class Tag> constexpr int chunk_k() { return sizeof(typename Tag::storage) == 2 ? kK16 : kK; }
+
+// One workgroup's published contribution to an iteration.
+struct alignas(64) XRec {
+    double score, alpha, r2, e2;
+    uint32_t idx, flags;
+    uint64_t tag;
+};
 
 struct Ctl {
     double tol2;
     int64_t maxit;
     const volatile int32_t* cancel;
-    Red* exch;             // [2][grid]
-    uint32_t* barrier;     // arrival counter, zero at launch
+    XRec* exch;            // [2][grid], tags zero at launch
     uint32_t* queue;       // batched work queue, zero at launch
     const int32_t* order;  // batched: queue position -> system
     int32_t refresh_every, check_every;
     int32_t nsys;
     int32_t pad_;
 };
+
+// Element access.  A chunk slot holds one 16-byte vector per k (VW elements)
+// or, on the scalar path, one element in its low bits.
+template <class Tag> struct Elem;
+template <> struct Elem<tag_f64> {
+    using S = double;
+    using Acc = double;
+    static constexpr int kVec = 2;
+    __device__ static double dot(const uint4& v, const double* x, int vw)
+    {
+        if (vw == 1) return __builtin_bit_cast(double, make_uint2(v.x, v.y)) * x[0];
+        const double2 a = __builtin_bit_cast(double2, v);
+        return a.x * x[0] + a.y * x[1];
+    }
+};
+template <> struct Elem<tag_f32> {
+    using S = float;
+    using Acc = float;
+    static constexpr int kVec = 4;
+    __device__ static float dot(const uint4& v, const float* x, int vw)
+    {
+        if (vw == 1) return __uint_as_float(v.x) * x[0];
+        return __uint_as_float(v.x) * x[0] + __uint_as_float(v.y) * x[1] + __uint_as_float(v.z) * x[2] +
+               __uint_as_float(v.w) * x[3];
+    }
+};
+template <class Tag> struct Elem16 {
+    using S = uint16_t;
+    using Acc = float;
+    static constexpr int kVec = 8;
+    __device__ static float dot(const uint4& v, const float* x, int vw)
+    {
+        if (vw == 1) return widen<Tag>(static_cast<uint16_t>(v.x & 0xFFFFu)) * x[0];
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+        float s = 0.f;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            s += widen<Tag>(static_cast<uint16_t>(w[k] & 0xFFFFu)) * x[2 * k];
+            s += widen<Tag>(static_cast<uint16_t>(w[k] >> 16)) * x[2 * k + 1];
+        }
+        return s;
+    }
+};
+template <> struct Elem<tag_f16> : Elem16<tag_f16> {};
+template <> struct Elem<tag_bf16> : Elem16<tag_bf16> {};
 
 template <class T, int W>
 __device__ __forceinline__ T group_sum_t(T v)
@@ -60,113 +122,185 @@ __device__ __forceinline__ T group_sum_t(T v)
     return v;
 }
 
-// 16-byte vector loads of At, widened to the accumulation type.
-template <class Tag> struct Elem;
-template <> struct Elem<tag_f64> {
-    using S = double; using Acc = double; static constexpr int kVec = 2;
-    __device__ static Acc one(const S* p) { return *p; }
-    __device__ static void vec(const S* p, Acc* o) { const double2 v = *reinterpret_cast<const double2*>(p); o[0] = v.x; o[1] = v.y; }
-};
-template <> struct Elem<tag_f32> {
-    using S = float; using Acc = float; static constexpr int kVec = 4;
-    __device__ static Acc one(const S* p) { return *p; }
-    __device__ static void vec(const S* p, Acc* o) { const float4 v = *reinterpret_cast<const float4*>(p); o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w; }
-};
-template <class Tag> struct Elem16 {
-    using S = uint16_t; using Acc = float; static constexpr int kVec = 8;
-    __device__ static Acc one(const S* p) { return widen<Tag>(*p); }
-    __device__ static void vec(const S* p, Acc* o)
-    {
-        const uint4 v = *reinterpret_cast<const uint4*>(p);
-        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+// The first `cnt` elements at p (cnt <= W) in a 16-byte vector, rest zero;
+// element indices are compile-time constants, so nothing leaves registers.
+template <class S, int W>
+__device__ __forceinline__ uint4 load_partial(const S* p, int cnt)
+{
+    struct alignas(16) Pack {
+        S e[16 / sizeof(S)];
+    } t;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            o[2 * k] = widen<Tag>(static_cast<uint16_t>(w[k] & 0xFFFFu));
-            o[2 * k + 1] = widen<Tag>(static_cast<uint16_t>(w[k] >> 16));
+    for (int e = 0; e < (int)(16 / sizeof(S)); ++e) t.e[e] = (e < W && e < cnt) ? p[e] : S(0);
+    return __builtin_bit_cast(uint4, t);
+}
+
+// Loads chunk slot `b` (KK vectors of one lane) for (row, seg); `on` false
+// (or columns past n) leaves zeros and touches no memory.  For the last
+// segment of a row it also fetches that row's right-hand side and squared
+// norm, so every load a consumer waits on was issued with its chunk (waits
+// on the in-order vector-memory counter then never drain later chunks).
+template <class Tag, int VW, int LPR, int KK>
+__device__ __forceinline__ void load_chunk(uint4 (&b)[KK], double& rhs_v, double& nu2_v,
+                                           const typename Elem<Tag>::S* __restrict__ A, int64_t lda, int n, int row,
+                                           int seg, int nseg, int q, bool on, const double* __restrict__ rhs,
+                                           const double* __restrict__ nu2)
+{
+    using S = typename Elem<Tag>::S;
+    constexpr int SW = LPR * VW * KK;
+    const S* base = A + (int64_t)row * lda;
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk) {
+        const int col = seg * SW + (kk * LPR + q) * VW;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (on && col < n) {
+            if (col + VW <= n && VW > 1) v = *reinterpret_cast<const uint4*>(base + col);
+            else v = load_partial<S, VW>(base + col, n - col);
         }
+        b[kk] = v;
     }
-};
-template <> struct Elem<tag_f16> : Elem16<tag_f16> {};
-template <> struct Elem<tag_bf16> : Elem16<tag_bf16> {};
+    rhs_v = 0.0;
+    nu2_v = 0.0;
+    if (on && seg == nseg - 1) {
+        rhs_v = rhs[row];
+        nu2_v = nu2[row];
+    }
+}
 
 // Residuals, candidates and partial ||r||^2 for rows [r0, r1) of the
-// workgroup.  Lane groups of LPR lanes share a row; kR rows are in flight
-// per group.  xs is the operand vector in LDS (x for FP64, x - x_ref in FP32
-// for the low-precision product); rhs is bt (exact) or r_ref (inner).  When
-// rout is non-null the residuals are stored there (a refresh).
-template <class Tag, bool VEC, int LPR>
-__device__ __forceinline__ void residual_rows(const typename Elem<Tag>::S* __restrict__ A, int64_t lda,
-                                              int n, int r0, int r1,
-                                              const typename Elem<Tag>::Acc* __restrict__ xs,
-                                              const double* __restrict__ rhs, double* __restrict__ rout,
-                                              const double* __restrict__ nu2, Red& loc)
+// workgroup.  Lane groups of LPR lanes share a row; a row is split into
+// nseg segments of LPR*VW*kK columns; the group walks its (row, segment)
+// chunks in order with kD chunks in flight.  xs is the operand vector in LDS
+// (x for FP64, x - x_ref in FP32 for the low-precision product), zero beyond
+// n up to nseg*SW; rhs is bt (exact) or r_ref (inner).  When rout is
+// non-null the residuals are stored there (a refresh).
+template <class Tag, bool VEC, int LPR, int kD>
+__device__ __forceinline__ void stream_rows(const typename Elem<Tag>::S* __restrict__ A, int64_t lda, int n,
+                                            int nseg, int r0, int r1, const typename Elem<Tag>::Acc* __restrict__ xs,
+                                            const double* __restrict__ rhs, double* __restrict__ rout,
+                                            const double* __restrict__ nu2, Red& loc)
 {
     using E = Elem<Tag>;
     using Acc = typename E::Acc;
     constexpr int VW = VEC ? E::kVec : 1;
     constexpr int NG = kNT / LPR;
+    constexpr int KK = chunk_k<Tag>();
+    constexpr int SW = LPR * VW * KK;
     const int q = threadIdx.x % LPR;
     const int g = threadIdx.x / LPR;
-    constexpr int step = LPR * VW;
-    const int K = (n + step - 1) / step;
-    for (int base = r0 + g; base < r1; base += NG * kR) {
-        Acc acc[kR];
+    const int span = r1 - r0;
+    const int nrows = span > g ? (span - g + NG - 1) / NG : 0;
+    const int nchunk = nrows * nseg;
+    const int nchunk_max = (span > 0 ? (span + NG - 1) / NG : 0) * nseg;  // group 0 has the most
+
+    uint4 buf[kD][KK];
+    double pr[kD], pn[kD];  // right-hand side and squared norm of the slot's row
+    int irow = 0, iseg = 0;  // next chunk to load
 #pragma unroll
-        for (int u = 0; u < kR; ++u) acc[u] = Acc(0);
-#pragma unroll 4
-        for (int k = 0; k < K; ++k) {
-            const int col = k * step + q * VW;
-            if (col + VW <= n) {
-                Acc xv[VW];
+    for (int u = 0; u < kD; ++u) {
+        load_chunk<Tag, VW, LPR, KK>(buf[u], pr[u], pn[u], A, lda, n, r0 + g + NG * irow, iseg, nseg, q,
+                                     u < nchunk, rhs, nu2);
+        if (++iseg == nseg) { iseg = 0; ++irow; }
+    }
+    int crow = 0, cseg = 0;  // next chunk to consume
+    Acc acc = Acc(0);
+    for (int c0 = 0; c0 < nchunk_max; c0 += kD) {
 #pragma unroll
-                for (int e = 0; e < VW; ++e) xv[e] = xs[col + e];
+        for (int u = 0; u < kD; ++u) {
+            const int c = c0 + u;
+            if (c < nchunk_max) {
+                const int cbase = cseg * SW + q * VW;
 #pragma unroll
-                for (int u = 0; u < kR; ++u) {
-                    const int row = base + u * NG;
-                    if (row < r1) {
-                        Acc a[VW];
-                        const typename E::S* p = A + (int64_t)row * lda + col;
-                        if constexpr (VW == 1) a[0] = E::one(p); else E::vec(p, a);
-#pragma unroll
-                        for (int e = 0; e < VW; ++e) acc[u] += a[e] * xv[e];
+                for (int kk = 0; kk < KK; ++kk) acc += E::dot(buf[u][kk], xs + cbase + kk * LPR * VW, VW);
+                if (cseg == nseg - 1) {
+                    const Acc s = group_sum_t<Acc, LPR>(acc);
+                    acc = Acc(0);
+                    if (c < nchunk) {
+                        const int row = r0 + g + NG * crow;
+                        const double r = pr[u] - static_cast<double>(s);
+                        if (rout) rout[row] = r;
+                        if (q == 0) loc.r2 += r * r;
+                        const double nn = pn[u];
+                        if (nn > 0.0) {
+                            const double score = (r * r) / nn;
+                            if (!isfinite(score)) {
+                                loc.flags |= kFlagNonfinite;
+                            } else if (cand_better(score, (uint32_t)row, loc.score, loc.idx)) {
+                                loc.score = score;
+                                loc.r = r / nn;
+                                loc.idx = (uint32_t)row;
+                            }
+                        } else if (isnan(nn)) {
+                            loc.flags |= kFlagNonfinite;
+                        }
                     }
                 }
-            } else if (col < n) {
-                // ragged end of the row: element loads only
-                for (int e = 0; e < n - col; ++e) {
-                    const Acc xe = xs[col + e];
-#pragma unroll
-                    for (int u = 0; u < kR; ++u) {
-                        const int row = base + u * NG;
-                        if (row < r1) acc[u] += E::one(A + (int64_t)row * lda + col + e) * xe;
-                    }
-                }
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kR; ++u) acc[u] = group_sum_t<Acc, LPR>(acc[u]);
-#pragma unroll
-        for (int u = 0; u < kR; ++u) {
-            const int row = base + u * NG;
-            if (row < r1) {
-                const double r = rhs[row] - static_cast<double>(acc[u]);
-                if (rout) rout[row] = r;
-                if (q == 0) loc.r2 += r * r;
-                const double nn = nu2[row];
-                if (nn > 0.0) {
-                    const double score = (r * r) / nn;
-                    if (!isfinite(score)) loc.flags |= kFlagNonfinite;
-                    else if (cand_better(score, (uint32_t)row, loc.score, loc.idx)) {
-                        loc.score = score;
-                        loc.r = r;
-                        loc.idx = (uint32_t)row;
-                    }
-                } else if (isnan(nn)) {
-                    loc.flags |= kFlagNonfinite;
-                }
+                if (++cseg == nseg) { cseg = 0; ++crow; }
+                load_chunk<Tag, VW, LPR, KK>(buf[u], pr[u], pn[u], A, lda, n, r0 + g + NG * irow, iseg, nseg, q,
+                                             c + kD < nchunk, rhs, nu2);
+                if (++iseg == nseg) { iseg = 0; ++irow; }
             }
         }
     }
+}
+
+// Publish this workgroup's record for iteration k and reduce all G records
+// (grid path).  Tags start at zero and iteration k writes k + 1, so a stale
+// record is never mistaken for a fresh one; two slots alternate by parity.
+// All record accesses are device-coherent (write-through stores and loads at
+// the coherence point, "sc1"): the writer's field stores are acknowledged
+// (explicit wait) before its tag store is issued, and a reader loads the
+// fields only after it has seen the tag.  No cache write-back or
+// invalidation is needed, so the exchange does not touch L2 contents (where
+// the workgroup's rows of At may be resident).
+template <class T> __device__ __forceinline__ void coh_store(T* p, T v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T> __device__ __forceinline__ T coh_load(const T* p)
+{
+    return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ Red exchange(const Red& mine, XRec* exch, int wg, int G, int64_t k, Red* slots)
+{
+    XRec* slot = exch + (size_t)(k & 1) * G;
+    const uint64_t tagv = static_cast<uint64_t>(k) + 1u;
+    if (threadIdx.x == 0) {
+        XRec& w = slot[wg];
+        coh_store(&w.score, mine.score);
+        coh_store(&w.alpha, mine.r);
+        coh_store(&w.r2, mine.r2);
+        coh_store(&w.e2, mine.e2);
+        coh_store(&w.idx, mine.idx);
+        coh_store(&w.flags, mine.flags);
+        // fields acknowledged at the coherence point before the tag goes out
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        coh_store(&w.tag, tagv);
+    }
+    bool ok = true;
+    Red all = red_identity();
+    for (int w = threadIdx.x; w < G; w += kNT) {
+        uint32_t spins = 0;
+        while (coh_load(&slot[w].tag) != tagv) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > kSpinLimit) {
+                ok = false;
+                break;
+            }
+        }
+        asm volatile("" ::: "memory");
+        Red o;
+        o.score = coh_load(&slot[w].score);
+        o.r = coh_load(&slot[w].alpha);
+        o.r2 = coh_load(&slot[w].r2);
+        o.e2 = coh_load(&slot[w].e2);
+        o.idx = coh_load(&slot[w].idx);
+        o.flags = coh_load(&slot[w].flags);
+        all = red_combine(all, o);
+    }
+    if (!ok) all.flags |= kFlagTimeout;
+    return block_red<kNT>(all, slots);
 }
 
 template <class Tag, bool VEC, int LPR, bool GRID>
@@ -174,14 +308,19 @@ __device__ void solve_loop(const SolveSys& S, const Ctl& C, int wg, int G, char*
 {
     constexpr bool MIXED = !std::is_same<Tag, tag_f64>::value;
     using LPS = typename Elem<Tag>::S;
+    using LAcc = typename Elem<Tag>::Acc;
+    constexpr int SW64 = LPR * (VEC ? 2 : 1) * kK;
+    constexpr int SWLP = LPR * (VEC ? Elem<Tag>::kVec : 1) * chunk_k<Tag>();
     __shared__ Red slots[kNW];
-    __shared__ uint32_t s_ok;
 
     const int tid = threadIdx.x;
     const int n = S.n;
     const int d = S.d;
-    double* sx = reinterpret_cast<double*>(smem);            // x, FP64
-    float* sd = reinterpret_cast<float*>(sx + ((n + 1) & ~1)); // x - x_ref, FP32 (mixed)
+    const int npad = S.npad;
+    const int nseg64 = (n + SW64 - 1) / SW64;
+    const int nseglp = (n + SWLP - 1) / SWLP;
+    double* sx = reinterpret_cast<double*>(smem);           // x, FP64, zero past n
+    LAcc* sd = reinterpret_cast<LAcc*>(sx + npad);          // x - x_ref (mixed), zero past n
 
     const int rows_per = (d + G - 1) / G;
     const int r0 = min(d, wg * rows_per);
@@ -190,17 +329,15 @@ __device__ void solve_loop(const SolveSys& S, const Ctl& C, int wg, int G, char*
     const int e0 = min(n, wg * cols_per);
     const int e1 = min(n, e0 + cols_per);
 
-    double xo[kCPT], dl[kCPT];
+    // x lives in LDS (sx); each thread owns columns tid + j*kNT and is the
+    // only writer of them.  Mixed precision keeps x - x_ref for the owned
+    // columns in FP64 registers (dl) and its FP32 rounding in LDS (sd).
+    double dl[kCPT];
 #pragma unroll
-    for (int j = 0; j < kCPT; ++j) {
-        const int c = tid + j * kNT;
-        xo[j] = 0.0;
-        dl[j] = 0.0;
-        if (c < n) {
-            xo[j] = S.x0 ? S.x0[c] : 0.0;
-            sx[c] = xo[j];
-            if (MIXED) sd[c] = 0.0f;
-        }
+    for (int j = 0; j < kCPT; ++j) dl[j] = 0.0;
+    for (int c = tid; c < npad; c += kNT) {
+        sx[c] = (c < n && S.x0) ? S.x0[c] : 0.0;
+        if (MIXED) sd[c] = LAcc(0);
     }
     // ||x_ref||^2 and ||bt||^2, reduced identically by every workgroup.
     Red q = red_identity();
@@ -220,19 +357,19 @@ __device__ void solve_loop(const SolveSys& S, const Ctl& C, int wg, int G, char*
     double hist0 = INFINITY, hist1 = INFINITY;
     int32_t status = CSK_NOT_CONVERGED;
     double meas = NAN;
-    uint32_t epoch = 0;
     int64_t k = 0;
     for (;; ++k) {
         const bool refresh = MIXED && !fp64 && (need_refresh || (k - k_ref) >= C.refresh_every);
         const bool exact = !MIXED || fp64 || refresh;
         Red loc = red_identity();
         if (exact) {
-            residual_rows<tag_f64, VEC, LPR>(S.At64, S.ldat64, n, r0, r1, sx, S.bt,
-                                             refresh ? S.rref : nullptr, S.nu2, loc);
+            // the refresh product of the mixed mode runs once per window: a
+            // shallower ring leaves the registers to the working-precision one
+            stream_rows<tag_f64, VEC, LPR, MIXED ? 2 : ring_depth<tag_f64>()>(
+                S.At64, S.ldat64, n, nseg64, r0, r1, sx, S.bt, refresh ? S.rref : nullptr, S.nu2, loc);
         } else {
-            residual_rows<Tag, VEC, LPR>(static_cast<const LPS*>(S.At), S.ldat, n, r0, r1,
-                                         reinterpret_cast<const typename Elem<Tag>::Acc*>(sd),
-                                         S.rref, nullptr, S.nu2, loc);
+            stream_rows<Tag, VEC, LPR, ring_depth<Tag>()>(static_cast<const LPS*>(S.At), S.ldat, n, nseglp, r0, r1,
+                                                          sd, S.rref, nullptr, S.nu2, loc);
         }
         if (S.xref)
             for (int c = e0 + tid; c < e1; c += kNT) {
@@ -242,16 +379,7 @@ __device__ void solve_loop(const SolveSys& S, const Ctl& C, int wg, int G, char*
         if (wg == 0 && tid == 0 && C.cancel && (k % C.check_every) == 0 && *C.cancel != 0)
             loc.flags |= kFlagCancel;
         Red tot = block_red<kNT>(loc, slots);
-        if constexpr (GRID) {
-            Red* rec = C.exch + (size_t)(k & 1) * G;
-            if (tid == 0) rec[wg] = tot;
-            ++epoch;
-            const bool ok = grid_barrier(C.barrier, epoch * (uint32_t)G, &s_ok);
-            Red all = red_identity();
-            for (int w = tid; w < G; w += kNT) all = red_combine(all, rec[w]);
-            tot = block_red<kNT>(all, slots);
-            if (!ok) tot.flags |= kFlagTimeout;
-        }
+        if constexpr (GRID) tot = exchange(tot, C.exch, wg, G, k, slots);
 
         // Stop test on x_k (top of iteration k).
         bool conv;
@@ -270,6 +398,7 @@ __device__ void solve_loop(const SolveSys& S, const Ctl& C, int wg, int G, char*
         if (tot.flags & kFlagCancel) { status = CSK_CANCELLED; break; }
         if (tot.flags & kFlagNonfinite) { status = CSK_ERR_NONFINITE; break; }
         if (tot.idx == kNoRow) { status = CSK_ERR_DEGENERATE; break; }
+        if (tot.idx >= (uint32_t)d) { status = CSK_ERR_DEVICE; break; }  // never dereference a bad row
         if (refresh) {
             ++nref;
             k_ref = k;
@@ -281,19 +410,17 @@ __device__ void solve_loop(const SolveSys& S, const Ctl& C, int wg, int G, char*
         }
 
         // Projection onto row i_k, on this workgroup's copy of x.
-        const int64_t ik = tot.idx;
-        const double alpha = tot.r / S.nu2[ik];
-        const double* __restrict__ arow = S.At64 + ik * S.ldat64;
+        const double alpha = tot.r;
+        const double* __restrict__ arow = S.At64 + (int64_t)tot.idx * S.ldat64;
 #pragma unroll
         for (int j = 0; j < kCPT; ++j) {
             const int c = tid + j * kNT;
             if (c < n) {
                 const double a = arow[c];
-                xo[j] = xo[j] + alpha * a;
-                sx[c] = xo[j];
+                sx[c] = sx[c] + alpha * a;
                 if (MIXED) {
                     dl[j] = (refresh ? 0.0 : dl[j]) + alpha * a;
-                    sd[c] = static_cast<float>(dl[j]);
+                    sd[c] = static_cast<LAcc>(dl[j]);
                 }
             }
         }
@@ -301,11 +428,7 @@ __device__ void solve_loop(const SolveSys& S, const Ctl& C, int wg, int G, char*
     }
 
     if (wg == 0) {
-#pragma unroll
-        for (int j = 0; j < kCPT; ++j) {
-            const int c = tid + j * kNT;
-            if (c < n) S.x[c] = xo[j];
-        }
+        for (int c = tid; c < n; c += kNT) S.x[c] = sx[c];
         if (tid == 0 && S.res) {
             S.res->iters = k;
             S.res->status = status;
@@ -347,9 +470,10 @@ __global__ __launch_bounds__(kNT) void k_solve_batched(const SolveSys* __restric
     }
 }
 
-__global__ void k_zero_u32(uint32_t* p, int count)
+__global__ void k_zero_words(uint32_t* p, int64_t words)
 {
-    if ((int)threadIdx.x < count) p[threadIdx.x] = 0u;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < words; e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = 0u;
 }
 
 __global__ __launch_bounds__(256) void k_row_norms2(const double* __restrict__ A, int64_t lda, int d, int n,
@@ -364,16 +488,16 @@ __global__ __launch_bounds__(256) void k_row_norms2(const double* __restrict__ A
     }
 }
 
-size_t smem_bytes(int64_t n, bool mixed)
+size_t smem_bytes(int64_t npad, bool mixed)
 {
-    return (size_t)((n + 1) & ~1) * 8 + (mixed ? (size_t)n * 4 : 0) + 16;
+    return (size_t)npad * 8 + (mixed ? (size_t)npad * 4 : 0) + 16;
 }
 
 template <class Tag, bool VEC, int LPR>
 csk_status launch_solve(const SolveSys& S, const Ctl& C, int grid, hipStream_t st)
 {
     const bool mixed = !std::is_same<Tag, tag_f64>::value;
-    const size_t shm = smem_bytes(S.n, mixed);
+    const size_t shm = smem_bytes(S.npad, mixed);
     if (grid <= 1) {
         auto kern = k_solve_single<Tag, VEC, LPR>;
         CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
@@ -400,12 +524,31 @@ csk_status launch_solve(const SolveSys& S, const Ctl& C, int grid, hipStream_t s
     return CSK_OK;
 }
 
-template <class Tag, bool VEC, int LPR>
-csk_status launch_batched(const SolveSys* sys, const Ctl& C, int64_t n_max, hipStream_t st)
+template <class Tag, bool VEC>
+csk_status dispatch_lpr(const SolveSys& S, const Ctl& C, const SolvePlan& p, hipStream_t st)
+{
+    switch (p.lpr) {
+    case 4: return launch_solve<Tag, VEC, 4>(S, C, p.grid, st);
+    case 16: return launch_solve<Tag, VEC, 16>(S, C, p.grid, st);
+    default: return launch_solve<Tag, VEC, 64>(S, C, p.grid, st);
+    }
+}
+
+template <class Tag>
+csk_status dispatch_solve(const SolveSys& S, const Ctl& C, const SolvePlan& p, hipStream_t st)
+{
+    if (p.vw > 1) return dispatch_lpr<Tag, true>(S, C, p, st);
+    return dispatch_lpr<Tag, false>(S, C, p, st);
+}
+
+constexpr int kBatchLPR = 16;
+
+template <class Tag>
+csk_status launch_batched(const SolveSys* sys, const Ctl& C, int64_t npad_max, hipStream_t st)
 {
     const bool mixed = !std::is_same<Tag, tag_f64>::value;
-    const size_t shm = smem_bytes(n_max, mixed);
-    auto kern = k_solve_batched<Tag, VEC, LPR>;
+    const size_t shm = smem_bytes(npad_max, mixed);
+    auto kern = k_solve_batched<Tag, true, kBatchLPR>;
     CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
     int per_cu = 0;
@@ -414,24 +557,6 @@ csk_status launch_batched(const SolveSys* sys, const Ctl& C, int64_t n_max, hipS
     kern<<<grid, kNT, shm, st>>>(sys, C);
     CSK_LAUNCH_CHECK("k_solve_batched");
     return CSK_OK;
-}
-
-template <class Tag>
-csk_status dispatch_solve(const SolveSys& S, const Ctl& C, const SolvePlan& p, hipStream_t st)
-{
-    if (p.vw > 1) {
-        if (p.lpr == 16) return launch_solve<Tag, true, 16>(S, C, p.grid, st);
-        return launch_solve<Tag, true, 64>(S, C, p.grid, st);
-    }
-    if (p.lpr == 16) return launch_solve<Tag, false, 16>(S, C, p.grid, st);
-    return launch_solve<Tag, false, 64>(S, C, p.grid, st);
-}
-
-template <class Tag>
-csk_status dispatch_batched(const SolveSys* sys, const Ctl& C, int64_t n_max, bool vec, hipStream_t st)
-{
-    if (vec) return launch_batched<Tag, true, 16>(sys, C, n_max, st);
-    return launch_batched<Tag, false, 16>(sys, C, n_max, st);
 }
 
 bool al16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
@@ -447,18 +572,33 @@ Ctl make_ctl(const csk_solve_opts* o)
     return C;
 }
 
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
 }  // namespace
+
+int64_t chunk_k_of(csk_dtype t) { return dtype_size(t) == 2 ? kK16 : kK; }
+
+int64_t solve_npad(int64_t n, csk_dtype at_dtype, int lpr, bool vec)
+{
+    const int64_t vwlp = vec ? 16 / (int64_t)dtype_size(at_dtype) : 1;
+    const int64_t sw64 = (int64_t)lpr * (vec ? 2 : 1) * kK;
+    const int64_t swlp = (int64_t)lpr * vwlp * chunk_k_of(at_dtype);
+    return std::max(round_up(n, sw64), round_up(n, swlp));
+}
+
+int solve_batch_lpr() { return kBatchLPR; }
 
 SolvePlan solve_plan(int64_t d, int64_t n, csk_dtype at_dtype, int64_t ldat, const void* At,
                      const csk_solve_opts* o)
 {
     SolvePlan p;
     p.block = kNT;
-    // Lanes per row: 64 when a row spans at least two full wavefront vectors.
     const int64_t vec = 16 / (int64_t)dtype_size(at_dtype);
-    p.lpr = (n >= 2 * 64 * std::min<int64_t>(vec, 2)) ? 64 : 16;
     const bool vec_ok = al16(At) && ((ldat * (int64_t)dtype_size(at_dtype)) % 16 == 0);
     p.vw = vec_ok ? (int)vec : 1;
+    // Lanes per row: the fewest of {4, 16, 64} whose chunk covers the row.
+    const int64_t per_lane = (int64_t)p.vw * chunk_k_of(at_dtype);
+    p.lpr = (4 * per_lane >= n) ? 4 : (16 * per_lane >= n) ? 16 : 64;
     int grid;
     if (o && o->single_wg == 1) grid = 1;
     else if (o && o->grid > 0) grid = o->grid;
@@ -469,7 +609,7 @@ SolvePlan solve_plan(int64_t d, int64_t n, csk_dtype at_dtype, int64_t ldat, con
         const int64_t bytes = d * n * (int64_t)dtype_size(at_dtype);
         grid = (bytes <= (int64_t)(1 << 20)) ? 1 : std::max(2, std::min<int>(device_cu_count(), (int)((d + 15) / 16)));
     }
-    p.grid = std::min<int64_t>(grid, d) < 1 ? 1 : (int)std::min<int64_t>(grid, d);
+    p.grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, d));
     return p;
 }
 
@@ -477,8 +617,7 @@ size_t solve_ws_bytes(int64_t d, int64_t n, int grid)
 {
     (void)n;
     Carve c(nullptr);
-    c.take<Red>(2 * (size_t)std::max(grid, 1));
-    c.take<uint32_t>(64);
+    c.take<XRec>(2 * (size_t)std::max(grid, 1));
     c.take<double>(d);   // r_ref
     c.take<double>(d);   // nu2 when not supplied
     return c.bytes();
@@ -490,12 +629,16 @@ csk_status solve_run(const SolveSys& sys_in, csk_dtype at_dtype, const csk_solve
     SolveSys S = sys_in;
     SolvePlan plan = solve_plan(S.d, S.n, at_dtype, S.ldat, S.At, o);
     // The exact FP64 product shares the vector path, so At64 must qualify too.
-    if (plan.vw > 1 && (!al16(S.At64) || (S.ldat64 * 8) % 16 != 0)) plan.vw = 1;
+    if (plan.vw > 1 && (!al16(S.At64) || (S.ldat64 * 8) % 16 != 0)) {
+        plan.vw = 1;
+        const int64_t per_lane = chunk_k_of(at_dtype);
+        plan.lpr = (4 * per_lane >= S.n) ? 4 : (16 * per_lane >= S.n) ? 16 : 64;
+    }
+    S.npad = (int32_t)solve_npad(S.n, at_dtype, plan.lpr, plan.vw > 1);
 
     Carve c(ws);
     Ctl C = make_ctl(o);
-    C.exch = c.take<Red>(2 * (size_t)std::max(plan.grid, 1));
-    C.barrier = c.take<uint32_t>(64);
+    C.exch = c.take<XRec>(2 * (size_t)std::max(plan.grid, 1));
     S.rref = c.take<double>(S.d);
     double* nu2_ws = c.take<double>(S.d);
     if (c.bytes() > ws_bytes) {
@@ -507,8 +650,12 @@ csk_status solve_run(const SolveSys& sys_in, csk_dtype at_dtype, const csk_solve
         CSK_LAUNCH_CHECK("k_row_norms2");
         S.nu2 = nu2_ws;
     }
-    k_zero_u32<<<1, 64, 0, st>>>(C.barrier, 64);
-    CSK_LAUNCH_CHECK("k_zero_u32");
+    if (plan.grid > 1) {
+        const int64_t words = (int64_t)2 * plan.grid * (int64_t)sizeof(XRec) / 4;
+        k_zero_words<<<(int)std::min<int64_t>(64, (words + 255) / 256), 256, 0, st>>>(
+            reinterpret_cast<uint32_t*>(C.exch), words);
+        CSK_LAUNCH_CHECK("k_zero_words");
+    }
     switch (at_dtype) {
     case CSK_F64: return dispatch_solve<tag_f64>(S, C, plan, st);
     case CSK_F32: return dispatch_solve<tag_f32>(S, C, plan, st);
@@ -519,22 +666,20 @@ csk_status solve_run(const SolveSys& sys_in, csk_dtype at_dtype, const csk_solve
 }
 
 csk_status solve_batched_run(const SolveSys* sys_dev, const int32_t* order_dev, int32_t nsys,
-                             int64_t n_max, csk_dtype at_dtype, const csk_solve_opts* o,
+                             int64_t npad_max, csk_dtype at_dtype, const csk_solve_opts* o,
                              uint32_t* queue_dev, hipStream_t st)
 {
     Ctl C = make_ctl(o);
     C.queue = queue_dev;
     C.order = order_dev;
     C.nsys = nsys;
-    k_zero_u32<<<1, 64, 0, st>>>(queue_dev, 1);
-    CSK_LAUNCH_CHECK("k_zero_u32");
-    // Descriptors are laid out by the caller with 16-byte aligned rows.
-    const bool vec = true;
+    k_zero_words<<<1, 64, 0, st>>>(queue_dev, 1);
+    CSK_LAUNCH_CHECK("k_zero_words");
     switch (at_dtype) {
-    case CSK_F64: return dispatch_batched<tag_f64>(sys_dev, C, n_max, vec, st);
-    case CSK_F32: return dispatch_batched<tag_f32>(sys_dev, C, n_max, vec, st);
-    case CSK_F16: return dispatch_batched<tag_f16>(sys_dev, C, n_max, vec, st);
-    case CSK_BF16: return dispatch_batched<tag_bf16>(sys_dev, C, n_max, vec, st);
+    case CSK_F64: return launch_batched<tag_f64>(sys_dev, C, npad_max, st);
+    case CSK_F32: return launch_batched<tag_f32>(sys_dev, C, npad_max, st);
+    case CSK_F16: return launch_batched<tag_f16>(sys_dev, C, npad_max, st);
+    case CSK_BF16: return launch_batched<tag_bf16>(sys_dev, C, npad_max, st);
     default: return CSK_ERR_UNSUPPORTED;
     }
 }
