@@ -113,7 +113,7 @@ def main_workload(args, P, W, torch):
     return out, s, c
 
 
-def cpu_baseline(s, c, iters_gpu, budget_iters=200):
+def cpu_baseline(s, c, iters_gpu, budget_iters=2000):
     """The oracle as it stands (single thread) on the same workload: the full
     sketch, then `budget_iters` MWRK iterations, extrapolated to the GPU's
     iteration count."""
@@ -222,6 +222,71 @@ def mrhs_workload(P, W, torch):
                 mfma_frac_bf16_peak=flops / t_sv / 2.5e15)
 
 
+# Section 3, Table 1: the paper's means over 50 trials (MATLAB, unstated
+# CPU): (m, n) -> (CSK iterations, MWRK iterations, CSK s, MWRK s).
+TABLE1_PAPER = {
+    (300000, 50): (54.90, 31.0, 0.2209, 1.6878), (300000, 100): (94.86, 63.0, 0.4569, 5.1097),
+    (300000, 150): (132.76, 96.0, 1.4894, 10.3728), (400000, 50): (54.36, 29.0, 0.2597, 1.9737),
+    (400000, 100): (95.14, 60.0, 0.5778, 6.0903), (400000, 150): (132.56, 94.0, 1.8509, 13.1016),
+    (500000, 50): (55.10, 29.0, 0.3312, 2.5878), (500000, 100): (94.96, 60.0, 0.7366, 8.2903),
+    (500000, 150): (132.54, 91.0, 2.0513, 17.3091), (600000, 50): (54.88, 28.0, 0.4053, 3.1672),
+    (600000, 100): (95.16, 58.0, 0.8566, 10.2019), (600000, 150): (132.58, 92.0, 2.3828, 22.0388),
+    (700000, 50): (54.70, 29.0, 0.4550, 3.9312), (700000, 100): (95.42, 58.0, 1.0025, 12.2144),
+    (700000, 150): (132.36, 89.0, 2.7194, 25.7228),
+}
+
+
+def table1_workload(P, W, torch, trials=5):
+    """Section 3's experiment on this GPU: CSK (sketch with d = n^2, then
+    MWRK on the sketch) against MWRK on the full (A, b), mean iterations
+    and times over `trials` seeded draws per shape."""
+    c = W.config("table1")
+    dev = "cuda:0"
+    rows = []
+    for m in c["ms"]:
+        for n in c["ns"]:
+            d = n * n
+            it_c, it_m, t_c, t_m = [], [], [], []
+            for t in range(trials):
+                s = W.gaussian(m, n, c["seed"] + t, device=dev)
+                torch.cuda.synchronize()
+
+                def csk():
+                    sk = P.csk_sketch(s.A, s.b, d, c["sketch_seed"] + t)
+                    return P.csk_solve(sk.At64, sk.bt, nu2=sk.nu2, x_ref=s.x_star, tol=c["tol"], maxit=c["maxit"],
+                                       sync=False)
+
+                def mwrk():
+                    return P.csk_solve(s.A, s.b, x_ref=s.x_star, tol=c["tol"], maxit=c["maxit"], sync=False)
+
+                if t == 0:
+                    csk()
+                    mwrk()
+                tc, (_, rc) = timed(csk)
+                tm, (_, rm) = timed(mwrk)
+                ic, sc = P.parse_results(rc)[0][:2]
+                im, sm = P.parse_results(rm)[0][:2]
+                if sc != P.CSK_OK or sm != P.CSK_OK:
+                    raise SystemExit(f"table1 {m}x{n} trial {t}: CSK {P.csk_status_string(sc)}, "
+                                     f"MWRK {P.csk_status_string(sm)}")
+                it_c.append(ic)
+                it_m.append(im)
+                t_c.append(tc)
+                t_m.append(tm)
+                del s
+            mean = lambda v: sum(v) / len(v)
+            pc, pm, pct, pmt = TABLE1_PAPER[(m, n)]
+            row = dict(m=m, n=n, d=d, csk_it=mean(it_c), mwrk_it=mean(it_m), csk_s=mean(t_c), mwrk_s=mean(t_m),
+                       it_speedup=mean(it_m) / mean(it_c), time_speedup=mean(t_m) / mean(t_c),
+                       paper_csk_it=pc, paper_mwrk_it=pm, paper_time_speedup=pmt / pct)
+            rows.append(row)
+            log(f"[bench] table1 {m}x{n}: CSK {row['csk_it']:.1f} it {row['csk_s'] * 1e3:.2f} ms, "
+                f"MWRK {row['mwrk_it']:.1f} it {row['mwrk_s'] * 1e3:.2f} ms, time speedup "
+                f"{row['time_speedup']:.1f} (paper: CSK {pc} it, MWRK {pm} it, speedup {pmt / pct:.1f})")
+    torch.cuda.empty_cache()
+    return dict(trials=trials, rows=rows)
+
+
 def csr_workload(P, W, torch, solve=True):
     """CSR A 1e6 x 5000 at 0.1%, d = 50000: sketch bandwidth, and the mixed
     FP32 solve to 1e-8."""
@@ -254,6 +319,34 @@ def csr_workload(P, W, torch, solve=True):
     return out
 
 
+def memory_rates(torch):
+    """Measured read rates of this GPU's memory system (context for the
+    roofline): a 160 MB buffer read repeatedly (it fits the 256 MB Infinity
+    Cache) and a 2 GB buffer (it does not)."""
+    out = {}
+    for name, nbytes in (("read_160MB", 160 << 20), ("read_2GB", 2 << 30)):
+        t = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda:0").fill_(1.0)
+        t.sum()
+        sec, _ = timed(lambda: t.sum(), 20)
+        out[name + "_gbs"] = nbytes / sec / 1e9
+        del t
+    torch.cuda.empty_cache()
+    log(f"[bench] memory read rates: {out}")
+    return out
+
+
+def calib_copy(torch, nbytes=1 << 30, reps=3):
+    """A plain device copy of known size (reads and writes nbytes each), the
+    reference for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calib_copy_bytes": nbytes, "reps": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -261,12 +354,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--quick", action="store_true", help="main workload only (for profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a design note, "
               "not a measured path", file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.calib_copy:
+        calib_copy(torch)
+        return
     import paper_2004_02480_amd as P
     from paper_2004_02480_amd import workloads as W
 
@@ -285,6 +383,8 @@ def main():
         extra["sparse_csr"] = csr_workload(P, W, torch)
         extra["batched_512"] = batched_workload(P, W, torch)
         extra["multi_rhs_256"] = mrhs_workload(P, W, torch)
+        extra["table1"] = table1_workload(P, W, torch)
+        extra["memory_rates"] = memory_rates(torch)
 
     line = {
         "metric": METRIC,

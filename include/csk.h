@@ -186,7 +186,14 @@ csk_status csk_sketch_csr(const int64_t* row_ptr, const int32_t* col, const floa
  * nu2: d FP64 squared row norms of At64 (nullable: computed into ws).
  * x0: n FP64 start (nullable: zero, as in Section 3).  x: n FP64 output.
  * Rows of zero norm are never selected; ties go to the lowest row index.
- * Requires d >= 1, 1 <= n <= 8192, ldat >= n, d < 2^31.                      */
+ * Requires d >= 1, 1 <= n <= 8192, ldat >= n, d < 2^31.
+ * Memory: when At (and At64) start on 16 bytes and ldat * element size is a
+ * multiple of 16, rows are read in whole 16-byte vectors, so the bytes of
+ * the last row up to the end of the vector holding column n - 1 are read
+ * (their values are ignored); a buffer of d * ldat elements always
+ * suffices.  Otherwise rows are read element by element.
+ * The solve keeps part of At in LDS for its whole duration (as much as fits
+ * beside x); nothing of it is written back.                                 */
 csk_status csk_solve_workspace_size(int64_t d, int64_t n, csk_dtype at_dtype, size_t* bytes /*host*/);
 csk_status csk_solve(const void* At, csk_dtype at_dtype, int64_t ldat,
                      const double* At64, int64_t ldat64,

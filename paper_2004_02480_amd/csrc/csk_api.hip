@@ -50,6 +50,23 @@ int device_cu_count()
     return cache[dev];
 }
 
+int device_max_lds()
+{
+    static std::mutex mu;
+    static std::vector<int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 65536;
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)cache.size() <= dev) cache.resize(dev + 1, 0);
+    if (cache[dev] == 0) {
+        int b = 0;
+        if (hipDeviceGetAttribute(&b, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || b < 65536)
+            b = 65536;
+        cache[dev] = b;
+    }
+    return cache[dev];
+}
+
 // ---- kernels local to the boundary --------------------------------------
 namespace {
 
@@ -81,6 +98,22 @@ __global__ void k_store_order(OrderPack pack, int count, int32_t* dst)
 }
 
 hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+}  // namespace
+
+csk_status upload_i32(const int32_t* host, int64_t count, int32_t* dev, hipStream_t st)
+{
+    for (int64_t k = 0; k < count; k += 512) {
+        OrderPack pack;
+        const int cnt = (int)std::min<int64_t>(512, count - k);
+        for (int q = 0; q < cnt; ++q) pack.v[q] = host[k + q];
+        k_store_order<<<1, 256, 0, st>>>(pack, cnt, dev + k);
+        CSK_LAUNCH_CHECK("k_store_order");
+    }
+    return CSK_OK;
+}
+
+namespace {
 
 bool lp_ok(csk_dtype t) { return t == CSK_F32 || t == CSK_F16 || t == CSK_BF16; }
 
@@ -357,6 +390,9 @@ csk_status csk_solve_batched_workspace_size(const csk_system_desc* sys, int32_t 
     c.take<SolveSys>(nsys);
     c.take<int32_t>(nsys);
     c.take<uint32_t>(64);
+    c.take<int32_t>(nsys + 1);
+    c.take<int32_t>(nsys);
+    c.take<char>(kBatchExchRecords * solve_exch_record_bytes());
     *bytes = c.bytes();
     return CSK_OK;
 }
@@ -392,6 +428,9 @@ csk_status csk_solve_batched(const csk_system_desc* sys, int32_t nsys, csk_dtype
     SolveSys* d_sys = c.take<SolveSys>(nsys);
     int32_t* d_order = c.take<int32_t>(nsys);
     uint32_t* d_queue = c.take<uint32_t>(64);
+    int32_t* d_item_off = c.take<int32_t>(nsys + 1);
+    int32_t* d_exch_off = c.take<int32_t>(nsys);
+    void* d_exch = c.take<char>(kBatchExchRecords * solve_exch_record_bytes());
 
     // 1. sketch every system in one pipeline
     std::vector<SketchJob> jobs(nsys);
@@ -421,7 +460,7 @@ csk_status csk_solve_batched(const csk_system_desc* sys, int32_t nsys, csk_dtype
 
     // 2. solver descriptors, largest estimated work first
     std::vector<SolveSys> hs(nsys);
-    int64_t npad_max = 0;
+    int64_t npad_max = 0, d_max = 0, n_max_s = 0;
     for (int s = 0; s < nsys; ++s) {
         SolveSys& S = hs[s];
         S = SolveSys{};
@@ -441,6 +480,8 @@ csk_status csk_solve_batched(const csk_system_desc* sys, int32_t nsys, csk_dtype
         S.stop_mode = sys[s].x_ref ? CSK_STOP_REL_ERR : CSK_STOP_REL_RESID;
         S.npad = (int32_t)solve_npad(sys[s].n, lp_dtype, solve_batch_lpr(), true);
         npad_max = std::max<int64_t>(npad_max, S.npad);
+        d_max = std::max<int64_t>(d_max, S.d);
+        n_max_s = std::max<int64_t>(n_max_s, S.n);
     }
     for (int k = 0; k < nsys; k += 24) {
         SysPack pack;
@@ -456,15 +497,19 @@ csk_status csk_solve_batched(const csk_system_desc* sys, int32_t nsys, csk_dtype
         const double cb = (double)sys[b].d * (double)sys[b].n * (double)sys[b].n;
         return ca > cb;
     });
-    for (int k = 0; k < nsys; k += 512) {
-        OrderPack pack;
-        const int cnt = std::min(512, nsys - k);
-        for (int q = 0; q < cnt; ++q) pack.v[q] = order[k + q];
-        k_store_order<<<1, 256, 0, stm>>>(pack, cnt, d_order + k);
-        CSK_LAUNCH_CHECK("k_store_order");
-    }
-    (void)n_max;
-    return solve_batched_run(d_sys, d_order, nsys, npad_max, lp_dtype, opts, d_queue, stm);
+    BatchedPlan bp;
+    bp.order = order.data();
+    bp.sys = hs.data();
+    bp.npad_max = npad_max;
+    bp.d_max = d_max;
+    bp.n_max = n_max_s;
+    bp.order_dev = d_order;
+    bp.item_off_dev = d_item_off;
+    bp.exch_off_dev = d_exch_off;
+    bp.exch_dev = d_exch;
+    bp.exch_records = kBatchExchRecords;
+    bp.queue_dev = d_queue;
+    return solve_batched_run(d_sys, nsys, bp, lp_dtype, opts, stm);
 }
 
 csk_status csk_solve_mrhs_workspace_size(int64_t d, int64_t n, int64_t nrhs, size_t* bytes)

@@ -193,5 +193,10 @@ inline size_t dtype_size(csk_dtype t)
 }
 
 int device_cu_count();
+// Copies count host int32 values to device memory, stream-ordered, through
+// kernel arguments (no staging allocation).
+csk_status upload_i32(const int32_t* host, int64_t count, int32_t* dev, hipStream_t st);
+// Largest LDS allocation of one workgroup on the current device, in bytes.
+int device_max_lds();
 
 }  // namespace csk

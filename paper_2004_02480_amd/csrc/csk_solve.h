@@ -40,11 +40,28 @@ int solve_batch_lpr();
 csk_status solve_run(const SolveSys& sys, csk_dtype at_dtype, const csk_solve_opts* o,
                      void* ws, size_t ws_bytes, hipStream_t st);
 
-// Batched: `sys` is a device array of nsys systems (rows 16-byte aligned,
-// npad from solve_npad with solve_batch_lpr()); `order` (device, nsys) lists
-// them in the order the work queue hands them out.
-csk_status solve_batched_run(const SolveSys* sys_dev, const int32_t* order_dev, int32_t nsys,
-                             int64_t npad_max, csk_dtype at_dtype, const csk_solve_opts* o,
-                             uint32_t* queue_dev, hipStream_t st);
+// Batched.  Systems are handed out from an atomic queue in `order` (host,
+// largest estimated work first); a system whose work is well above the
+// average share of one workgroup is split over several workgroups that run
+// the grid loop on it with their own exchange records.
+constexpr size_t kBatchExchRecords = 4096;  // exchange records for split systems
+size_t solve_exch_record_bytes();
+
+struct BatchedPlan {
+    const int32_t* order;      // host, nsys: queue position -> system
+    const SolveSys* sys;       // host copy of the descriptors
+    int64_t npad_max, d_max, n_max;
+    int32_t* order_dev;        // nsys
+    int32_t* item_off_dev;     // nsys + 1: first work item of each queue position
+    int32_t* exch_off_dev;     // nsys: first exchange record of each queue position
+    void* exch_dev;            // exch_records records
+    size_t exch_records;
+    uint32_t* queue_dev;
+};
+
+// `sys_dev` is the device array of nsys descriptors (rows 16-byte aligned,
+// npad from solve_npad with solve_batch_lpr()).
+csk_status solve_batched_run(const SolveSys* sys_dev, int32_t nsys, const BatchedPlan& bp, csk_dtype at_dtype,
+                             const csk_solve_opts* o, hipStream_t st);
 
 }  // namespace csk

@@ -234,8 +234,8 @@ __global__ __launch_bounds__(256) void k_long_segments(Batch b)
 }
 
 template <class T> struct VecOf;
-template <> struct VecOf<double> { static constexpr int kW = 2; using type = double2; };
-template <> struct VecOf<float> { static constexpr int kW = 4; using type = float4; };
+template <> struct VecOf<double> { using type = double2; };
+template <> struct VecOf<float> { using type = float4; };
 
 // LP: 0 none, 1 f32, 2 f16, 3 bf16 (matches csk_dtype values for 1..3).
 template <int LP>

@@ -3,9 +3,10 @@
 //
 // Every iteration k, with no host round trip:
 //   1. residual r_i = bt_i - At^(i) x_k for the workgroup's own block of rows.
-//      The product is bandwidth-bound: At streams through a ring of kD chunks
-//      per lane (kK 16-byte vectors each) so enough loads are in flight to
-//      cover HBM latency; x sits in LDS.
+//      The product is bandwidth-bound.  As much of the workgroup's block as
+//      LDS holds beside x stays resident there for the whole solve; the rest
+//      streams through a ring of kD chunks per lane (kK 16-byte vectors each)
+//      so enough loads are in flight to cover HBM latency; x sits in LDS.
 //   2. weighted score r_i^2 / ||At^(i)||^2 (the square of the paper's
 //      |r_i| / ||At^(i)||, same argmax), best row of the workgroup through
 //      wavefront butterflies and LDS;
@@ -31,13 +32,13 @@
 #include <algorithm>
 #include <cmath>
 #include <type_traits>
+#include <vector>
 
 namespace csk {
 namespace {
 
 constexpr int kNT = 512;        // threads per workgroup
 constexpr int kNW = kNT / kWave;
-constexpr int kCPT = 16;        // owned columns per thread: n <= kNT * kCPT
 constexpr int kK = 8;           // 16-byte vectors per lane per chunk (FP64, FP32)
 constexpr int kK16 = 4;         // ... for the 16-bit types (8 elements per vector)
 
@@ -50,11 +51,10 @@ struct tag_f64 { using storage = double; };
 template <class Tag> constexpr int ring_depth() { return std::is_same<Tag, tag_f64>::value ? 3 : std::is_same<Tag, tag_f32>::value ? 2 : 3; }
 template <class Tag> constexpr int chunk_k() { return sizeof(typename Tag::storage) == 2 ? kK16 : kK; }
 
-// One workgroup's published contribution to an iteration.
+// One workgroup's published contribution to an iteration (tagged words, see
+// exchange()).
 struct alignas(64) XRec {
-    double score, alpha, r2, e2;
-    uint32_t idx, flags;
-    uint64_t tag;
+    uint64_t w[8];
 };
 
 struct Ctl {
@@ -64,49 +64,60 @@ struct Ctl {
     XRec* exch;            // [2][grid], tags zero at launch
     uint32_t* queue;       // batched work queue, zero at launch
     const int32_t* order;  // batched: queue position -> system
+    const int32_t* item_off;  // batched: first work item of each queue position (nsys + 1)
+    const int32_t* exch_off;  // batched: first exchange record of each queue position
     int32_t refresh_every, check_every;
     int32_t nsys;
+    int32_t res_layers;    // LDS-resident chunks per lane group (capacity)
+    int32_t xslice;        // LDS doubles for the workgroup's slice of x_ref
     int32_t pad_;
 };
 
 // Element access.  A chunk slot holds one 16-byte vector per k (VW elements)
-// or, on the scalar path, one element in its low bits.
+// or, on the scalar path, one element in its low bits.  `lim` is the number
+// of leading elements of the vector that lie inside the row (columns < n of
+// a row this lane group owns); the others are treated as zero whatever the
+// loaded bits are.
 template <class Tag> struct Elem;
 template <> struct Elem<tag_f64> {
     using S = double;
     using Acc = double;
     static constexpr int kVec = 2;
-    __device__ static double dot(const uint4& v, const double* x, int vw)
+    template <int VW> __device__ static double dot(const uint4& v, const double* x, int lim)
     {
-        if (vw == 1) return __builtin_bit_cast(double, make_uint2(v.x, v.y)) * x[0];
-        const double2 a = __builtin_bit_cast(double2, v);
-        return a.x * x[0] + a.y * x[1];
+        if constexpr (VW == 1) {
+            const double a = __builtin_bit_cast(double, make_uint2(v.x, v.y));
+            return (lim > 0 ? a : 0.0) * x[0];
+        } else {
+            const double2 a = __builtin_bit_cast(double2, v);
+            return (lim > 0 ? a.x : 0.0) * x[0] + (lim > 1 ? a.y : 0.0) * x[1];
+        }
     }
 };
 template <> struct Elem<tag_f32> {
     using S = float;
     using Acc = float;
     static constexpr int kVec = 4;
-    __device__ static float dot(const uint4& v, const float* x, int vw)
+    template <int VW> __device__ static float dot(const uint4& v, const float* x, int lim)
     {
-        if (vw == 1) return __uint_as_float(v.x) * x[0];
-        return __uint_as_float(v.x) * x[0] + __uint_as_float(v.y) * x[1] + __uint_as_float(v.z) * x[2] +
-               __uint_as_float(v.w) * x[3];
+        if constexpr (VW == 1) return (lim > 0 ? __uint_as_float(v.x) : 0.f) * x[0];
+        return (lim > 0 ? __uint_as_float(v.x) : 0.f) * x[0] + (lim > 1 ? __uint_as_float(v.y) : 0.f) * x[1] +
+               (lim > 2 ? __uint_as_float(v.z) : 0.f) * x[2] + (lim > 3 ? __uint_as_float(v.w) : 0.f) * x[3];
     }
 };
 template <class Tag> struct Elem16 {
     using S = uint16_t;
     using Acc = float;
     static constexpr int kVec = 8;
-    __device__ static float dot(const uint4& v, const float* x, int vw)
+    template <int VW> __device__ static float dot(const uint4& v, const float* x, int lim)
     {
-        if (vw == 1) return widen<Tag>(static_cast<uint16_t>(v.x & 0xFFFFu)) * x[0];
+        if constexpr (VW == 1) return (lim > 0 ? widen<Tag>(static_cast<uint16_t>(v.x & 0xFFFFu)) : 0.f) * x[0];
         const uint32_t w[4] = {v.x, v.y, v.z, v.w};
         float s = 0.f;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            s += widen<Tag>(static_cast<uint16_t>(w[k] & 0xFFFFu)) * x[2 * k];
-            s += widen<Tag>(static_cast<uint16_t>(w[k] >> 16)) * x[2 * k + 1];
+            s += (lim > 2 * k ? widen<Tag>(static_cast<uint16_t>(w[k] & 0xFFFFu)) : 0.f) * x[2 * k];
+            s += (lim > 2 * k + 1 ? widen<Tag>(static_cast<uint16_t>(w[k] >> 16)) : 0.f) * x[2 * k + 1];
         }
         return s;
     }
@@ -122,63 +133,78 @@ __device__ __forceinline__ T group_sum_t(T v)
     return v;
 }
 
-// The first `cnt` elements at p (cnt <= W) in a 16-byte vector, rest zero;
-// element indices are compile-time constants, so nothing leaves registers.
-template <class S, int W>
-__device__ __forceinline__ uint4 load_partial(const S* p, int cnt)
-{
-    struct alignas(16) Pack {
-        S e[16 / sizeof(S)];
-    } t;
-#pragma unroll
-    for (int e = 0; e < (int)(16 / sizeof(S)); ++e) t.e[e] = (e < W && e < cnt) ? p[e] : S(0);
-    return __builtin_bit_cast(uint4, t);
-}
-
-// Loads chunk slot `b` (KK vectors of one lane) for (row, seg); `on` false
-// (or columns past n) leaves zeros and touches no memory.  For the last
-// segment of a row it also fetches that row's right-hand side and squared
-// norm, so every load a consumer waits on was issued with its chunk (waits
-// on the in-order vector-memory counter then never drain later chunks).
+// Loads chunk slot `b` (KK vectors of one lane) of (row, seg), with the
+// row's right-hand side and squared norm.  Every load is issued, from a
+// valid address, whatever `on` says: a lane that is off reads the first
+// vector of row `rsafe` (all such lanes read the same 16 bytes, one cache
+// line), and a vector starting at or past column n reads column 0; the
+// caller masks such elements with `lim` (returned: the count of valid
+// elements from this lane's first column of the chunk, 0 when off).
+// A vector that starts before n may end past it, inside the row's 16-byte
+// padded length (the vector path requires 16-byte rows), so it stays inside
+// the matrix.  Without branches the compiler never has to merge different
+// loads, so waits on the in-order vector-memory counter only ever wait for
+// the slot that is consumed.
 template <class Tag, int VW, int LPR, int KK>
-__device__ __forceinline__ void load_chunk(uint4 (&b)[KK], double& rhs_v, double& nu2_v,
-                                           const typename Elem<Tag>::S* __restrict__ A, int64_t lda, int n, int row,
-                                           int seg, int nseg, int q, bool on, const double* __restrict__ rhs,
-                                           const double* __restrict__ nu2)
+__device__ __forceinline__ int load_chunk(uint4 (&b)[KK], double& rhs_v, double& nu2_v,
+                                          const typename Elem<Tag>::S* __restrict__ A, int64_t lda, int n, int row,
+                                          int rsafe, int seg, int q, bool on, const double* __restrict__ rhs,
+                                          const double* __restrict__ nu2)
 {
     using S = typename Elem<Tag>::S;
     constexpr int SW = LPR * VW * KK;
-    const S* base = A + (int64_t)row * lda;
+    const int r = on ? row : rsafe;
+    const S* base = A + (int64_t)r * lda;
 #pragma unroll
     for (int kk = 0; kk < KK; ++kk) {
         const int col = seg * SW + (kk * LPR + q) * VW;
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (on && col < n) {
-            if (col + VW <= n && VW > 1) v = *reinterpret_cast<const uint4*>(base + col);
-            else v = load_partial<S, VW>(base + col, n - col);
+        const int cc = (on && col < n) ? col : 0;
+        if constexpr (VW > 1) {
+            b[kk] = *reinterpret_cast<const uint4*>(base + cc);
+        } else if constexpr (sizeof(S) == 8) {
+            const uint64_t w = *reinterpret_cast<const uint64_t*>(base + cc);
+            b[kk] = make_uint4(static_cast<uint32_t>(w), static_cast<uint32_t>(w >> 32), 0u, 0u);
+        } else if constexpr (sizeof(S) == 4) {
+            b[kk] = make_uint4(*reinterpret_cast<const uint32_t*>(base + cc), 0u, 0u, 0u);
+        } else {
+            b[kk] = make_uint4(static_cast<uint32_t>(*reinterpret_cast<const uint16_t*>(base + cc)), 0u, 0u, 0u);
         }
-        b[kk] = v;
     }
-    rhs_v = 0.0;
-    nu2_v = 0.0;
-    if (on && seg == nseg - 1) {
-        rhs_v = rhs[row];
-        nu2_v = nu2[row];
-    }
+    rhs_v = rhs[r];
+    nu2_v = nu2[r];
+    return on ? n - (seg * SW + q * VW) : 0;
 }
+
+// LDS-resident part of the working matrix.  The first L chunks of every
+// lane group's (row, segment) sequence stay in LDS for the whole solve: slot
+// (l, kk, tid) holds the thread's own vector kk of chunk l, so the thread
+// that fills a slot is the only one that reads it.  Rows whose last segment
+// is resident keep their right-hand side and squared norm in LDS as well
+// (rhs, nn at group row * NG + group); every lane of the group writes the
+// same value there and reads back its own write.
+struct ResLds {
+    const uint4* chunks;
+    const double* rhs;
+    const double* nn;
+    int L;
+};
 
 // Residuals, candidates and partial ||r||^2 for rows [r0, r1) of the
 // workgroup.  Lane groups of LPR lanes share a row; a row is split into
 // nseg segments of LPR*VW*kK columns; the group walks its (row, segment)
-// chunks in order with kD chunks in flight.  xs is the operand vector in LDS
-// (x for FP64, x - x_ref in FP32 for the low-precision product), zero beyond
-// n up to nseg*SW; rhs is bt (exact) or r_ref (inner).  When rout is
-// non-null the residuals are stored there (a refresh).
-template <class Tag, bool VEC, int LPR, int kD>
+// chunks in order: first the LDS-resident ones, then the rest from memory
+// with kD chunks in flight (their loads are issued before the resident
+// chunks are consumed).  xs is the operand vector in LDS (x for FP64,
+// x - x_ref in FP32 for the low-precision product), zero beyond n up to
+// nseg*SW; rhs is bt (exact) or r_ref (inner).  When rout is non-null the
+// residuals are stored there (a refresh), and for the first nrow_out group
+// rows also in the LDS array lrout.
+template <class Tag, bool VEC, int LPR, int kD, bool ROUT>
 __device__ __forceinline__ void stream_rows(const typename Elem<Tag>::S* __restrict__ A, int64_t lda, int n,
                                             int nseg, int r0, int r1, const typename Elem<Tag>::Acc* __restrict__ xs,
                                             const double* __restrict__ rhs, double* __restrict__ rout,
-                                            const double* __restrict__ nu2, Red& loc)
+                                            const double* __restrict__ nu2, Red& loc, const ResLds& res,
+                                            double* lrout, int nrow_out)
 {
     using E = Elem<Tag>;
     using Acc = typename E::Acc;
@@ -192,67 +218,132 @@ __device__ __forceinline__ void stream_rows(const typename Elem<Tag>::S* __restr
     const int nrows = span > g ? (span - g + NG - 1) / NG : 0;
     const int nchunk = nrows * nseg;
     const int nchunk_max = (span > 0 ? (span + NG - 1) / NG : 0) * nseg;  // group 0 has the most
+    const int Lg = min(res.L, nchunk_max);
+    // The streamed part is padded to whole rounds of the ring so that every
+    // slot is consumed and refilled unconditionally (the extra chunks are
+    // off: one shared cache line, masked); the compiler then tracks the
+    // in-order load counter exactly and waits only for the slot in use.
+    const int nstream = nchunk_max - Lg;
+    const int nround = (nstream + kD - 1) / kD;
+
+    auto finish = [&](int crow, Acc s, double pr, double nn) {
+        const int row = r0 + g + NG * crow;
+        const double r = pr - static_cast<double>(s);
+        if constexpr (ROUT) {
+            rout[row] = r;
+            if (crow < nrow_out) lrout[crow * NG + g] = r;
+        }
+        if (q == 0) loc.r2 += r * r;
+        if (nn > 0.0) {
+            const double score = (r * r) / nn;
+            if (!isfinite(score)) {
+                loc.flags |= kFlagNonfinite;
+            } else if (cand_better(score, (uint32_t)row, loc.score, loc.idx)) {
+                loc.score = score;
+                loc.r = r / nn;
+                loc.idx = (uint32_t)row;
+            }
+        } else if (isnan(nn)) {
+            loc.flags |= kFlagNonfinite;
+        }
+    };
 
     uint4 buf[kD][KK];
     double pr[kD], pn[kD];  // right-hand side and squared norm of the slot's row
-    int irow = 0, iseg = 0;  // next chunk to load
+    int lim[kD];            // valid elements of the slot from this lane's first column
+    int irow = Lg / nseg, iseg = Lg - (Lg / nseg) * nseg;  // next chunk to load
+    int iload = Lg;
+    if (nround > 0) {
 #pragma unroll
-    for (int u = 0; u < kD; ++u) {
-        load_chunk<Tag, VW, LPR, KK>(buf[u], pr[u], pn[u], A, lda, n, r0 + g + NG * irow, iseg, nseg, q,
-                                     u < nchunk, rhs, nu2);
-        if (++iseg == nseg) { iseg = 0; ++irow; }
+        for (int u = 0; u < kD; ++u) {
+            lim[u] = load_chunk<Tag, VW, LPR, KK>(buf[u], pr[u], pn[u], A, lda, n, r0 + g + NG * irow, r0, iseg, q,
+                                                  iload < nchunk, rhs, nu2);
+            ++iload;
+            if (++iseg == nseg) { iseg = 0; ++irow; }
+        }
     }
     int crow = 0, cseg = 0;  // next chunk to consume
     Acc acc = Acc(0);
-    for (int c0 = 0; c0 < nchunk_max; c0 += kD) {
+    for (int c = 0; c < Lg; ++c) {
+        const uint4* slot = res.chunks + (size_t)c * KK * kNT + threadIdx.x;
+        const int cbase = cseg * SW + q * VW;
+        const int l0 = c < nchunk ? n - cbase : 0;
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk)
+            acc += E::template dot<VW>(slot[kk * kNT], xs + cbase + kk * LPR * VW, l0 - kk * LPR * VW);
+        if (cseg == nseg - 1) {
+            const Acc s = group_sum_t<Acc, LPR>(acc);
+            acc = Acc(0);
+            if (c < nchunk) finish(crow, s, res.rhs[crow * NG + g], res.nn[crow * NG + g]);
+        }
+        if (++cseg == nseg) { cseg = 0; ++crow; }
+    }
+    int c = Lg;
+    for (int rd = 0; rd < nround; ++rd) {
+        const bool last = rd == nround - 1;
 #pragma unroll
         for (int u = 0; u < kD; ++u) {
-            const int c = c0 + u;
-            if (c < nchunk_max) {
-                const int cbase = cseg * SW + q * VW;
+            const int cbase = cseg * SW + q * VW;
 #pragma unroll
-                for (int kk = 0; kk < KK; ++kk) acc += E::dot(buf[u][kk], xs + cbase + kk * LPR * VW, VW);
-                if (cseg == nseg - 1) {
-                    const Acc s = group_sum_t<Acc, LPR>(acc);
-                    acc = Acc(0);
-                    if (c < nchunk) {
-                        const int row = r0 + g + NG * crow;
-                        const double r = pr[u] - static_cast<double>(s);
-                        if (rout) rout[row] = r;
-                        if (q == 0) loc.r2 += r * r;
-                        const double nn = pn[u];
-                        if (nn > 0.0) {
-                            const double score = (r * r) / nn;
-                            if (!isfinite(score)) {
-                                loc.flags |= kFlagNonfinite;
-                            } else if (cand_better(score, (uint32_t)row, loc.score, loc.idx)) {
-                                loc.score = score;
-                                loc.r = r / nn;
-                                loc.idx = (uint32_t)row;
-                            }
-                        } else if (isnan(nn)) {
-                            loc.flags |= kFlagNonfinite;
-                        }
-                    }
-                }
-                if (++cseg == nseg) { cseg = 0; ++crow; }
-                load_chunk<Tag, VW, LPR, KK>(buf[u], pr[u], pn[u], A, lda, n, r0 + g + NG * irow, iseg, nseg, q,
-                                             c + kD < nchunk, rhs, nu2);
-                if (++iseg == nseg) { iseg = 0; ++irow; }
+            for (int kk = 0; kk < KK; ++kk)
+                acc += E::template dot<VW>(buf[u][kk], xs + cbase + kk * LPR * VW, lim[u] - kk * LPR * VW);
+            if (cseg == nseg - 1) {
+                const Acc s = group_sum_t<Acc, LPR>(acc);
+                acc = Acc(0);
+                if (c < nchunk) finish(crow, s, pr[u], pn[u]);
             }
+            if (++cseg == nseg) { cseg = 0; ++crow; }
+            ++c;
+            lim[u] = load_chunk<Tag, VW, LPR, KK>(buf[u], pr[u], pn[u], A, lda, n, r0 + g + NG * irow, r0, iseg, q,
+                                                  !last && iload < nchunk, rhs, nu2);
+            ++iload;
+            if (++iseg == nseg) { iseg = 0; ++irow; }
+        }
+    }
+}
+
+// Fills the LDS-resident chunks (the first L of each group's sequence) and,
+// for rows whose last segment is resident, their right-hand side and norm.
+// Elements past n (or of rows the group does not own) are masked when the
+// chunks are consumed, so their loaded bits do not matter.
+template <class Tag, bool VEC, int LPR>
+__device__ void fill_resident(const typename Elem<Tag>::S* __restrict__ A, int64_t lda, int n, int nseg, int r0,
+                              int r1, const double* __restrict__ rhs, const double* __restrict__ nu2, uint4* chunks,
+                              double* lrhs, double* lnn, int L)
+{
+    using E = Elem<Tag>;
+    constexpr int VW = VEC ? E::kVec : 1;
+    constexpr int NG = kNT / LPR;
+    constexpr int KK = chunk_k<Tag>();
+    const int q = threadIdx.x % LPR;
+    const int g = threadIdx.x / LPR;
+    const int span = r1 - r0;
+    const int nrows = span > g ? (span - g + NG - 1) / NG : 0;
+    const int nchunk = nrows * nseg;
+    for (int c = 0; c < L; ++c) {
+        const int crow = c / nseg, seg = c - (c / nseg) * nseg;
+        uint4 v[KK];
+        double pr, pn;
+        load_chunk<Tag, VW, LPR, KK>(v, pr, pn, A, lda, n, r0 + g + NG * crow, r0, seg, q, c < nchunk, rhs, nu2);
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) chunks[((size_t)c * KK + kk) * kNT + threadIdx.x] = v[kk];
+        if (seg == nseg - 1) {
+            lrhs[crow * NG + g] = pr;
+            lnn[crow * NG + g] = pn;
         }
     }
 }
 
 // Publish this workgroup's record for iteration k and reduce all G records
-// (grid path).  Tags start at zero and iteration k writes k + 1, so a stale
-// record is never mistaken for a fresh one; two slots alternate by parity.
-// All record accesses are device-coherent (write-through stores and loads at
-// the coherence point, "sc1"): the writer's field stores are acknowledged
-// (explicit wait) before its tag store is issued, and a reader loads the
-// fields only after it has seen the tag.  No cache write-back or
-// invalidation is needed, so the exchange does not touch L2 contents (where
-// the workgroup's rows of At may be resident).
+// (grid path).  A record is one 64-byte line of eight 64-bit words, each
+// carrying 32 bits of payload and, in its upper half, the iteration tag
+// k + 1 (tags start at zero; two slots alternate by parity, so a stale word
+// is never mistaken for a fresh one).  Words are written and read with
+// device-coherent 64-bit accesses, so a reader accepts the record once all
+// eight tags match: no acknowledgement wait on the writer, no second read,
+// and no cache write-back or invalidation (the workgroup's rows of At stay
+// in L2).  Payload: score, alpha, the stop measure (||x - x_ref||^2 part or
+// ||r||^2 part), row index, flags.
 template <class T> __device__ __forceinline__ void coh_store(T* p, T v)
 {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -262,55 +353,98 @@ template <class T> __device__ __forceinline__ T coh_load(const T* p)
     return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ Red exchange(const Red& mine, XRec* exch, int wg, int G, int64_t k, Red* slots)
+__device__ __forceinline__ double join_f64(uint64_t lo, uint64_t hi)
+{
+    return __longlong_as_double((long long)((hi << 32) | (lo & 0xFFFFFFFFull)));
+}
+
+__device__ __forceinline__ Red exchange(const Red& mine, XRec* exch, int wg, int G, int64_t k, Red* slots,
+                                        bool rel_err)
 {
     XRec* slot = exch + (size_t)(k & 1) * G;
-    const uint64_t tagv = static_cast<uint64_t>(k) + 1u;
-    if (threadIdx.x == 0) {
-        XRec& w = slot[wg];
-        coh_store(&w.score, mine.score);
-        coh_store(&w.alpha, mine.r);
-        coh_store(&w.r2, mine.r2);
-        coh_store(&w.e2, mine.e2);
-        coh_store(&w.idx, mine.idx);
-        coh_store(&w.flags, mine.flags);
-        // fields acknowledged at the coherence point before the tag goes out
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        coh_store(&w.tag, tagv);
+    const uint64_t tag = static_cast<uint64_t>(static_cast<uint32_t>(k + 1)) << 32;
+    if (threadIdx.x < 8) {
+        const int f = threadIdx.x;
+        const double dv = f < 2 ? mine.score : f < 4 ? mine.r : (rel_err ? mine.e2 : mine.r2);
+        const uint64_t bits = static_cast<uint64_t>(__double_as_longlong(dv));
+        const uint32_t p = f < 6 ? static_cast<uint32_t>((f & 1) ? (bits >> 32) : bits)
+                                 : (f == 6 ? mine.idx : mine.flags);
+        coh_store(&slot[wg].w[f], tag | p);
     }
     bool ok = true;
     Red all = red_identity();
     for (int w = threadIdx.x; w < G; w += kNT) {
+        uint64_t v[8];
         uint32_t spins = 0;
-        while (coh_load(&slot[w].tag) != tagv) {
+        for (;;) {
+#pragma unroll
+            for (int f = 0; f < 8; ++f) v[f] = coh_load(&slot[w].w[f]);
+            bool fresh = true;
+#pragma unroll
+            for (int f = 0; f < 8; ++f) fresh = fresh && ((v[f] & 0xFFFFFFFF00000000ull) == tag);
+            if (fresh) break;
             __builtin_amdgcn_s_sleep(1);
             if (++spins > kSpinLimit) {
                 ok = false;
                 break;
             }
         }
-        asm volatile("" ::: "memory");
+        if (!ok) break;
         Red o;
-        o.score = coh_load(&slot[w].score);
-        o.r = coh_load(&slot[w].alpha);
-        o.r2 = coh_load(&slot[w].r2);
-        o.e2 = coh_load(&slot[w].e2);
-        o.idx = coh_load(&slot[w].idx);
-        o.flags = coh_load(&slot[w].flags);
+        o.score = join_f64(v[0], v[1]);
+        o.r = join_f64(v[2], v[3]);
+        const double meas = join_f64(v[4], v[5]);
+        o.r2 = rel_err ? 0.0 : meas;
+        o.e2 = rel_err ? meas : 0.0;
+        o.idx = static_cast<uint32_t>(v[6]);
+        o.flags = static_cast<uint32_t>(v[7]);
         all = red_combine(all, o);
     }
     if (!ok) all.flags |= kFlagTimeout;
     return block_red<kNT>(all, slots);
 }
 
+// LDS carve of the solve: x (FP64), x - x_ref in the accumulation type
+// (mixed), this workgroup's slice of x_ref, then the resident right-hand
+// sides and norms and the resident chunks (16-byte aligned).
+struct SolveLds {
+    size_t sx, sd, sxr, lrhs, lnn, chunks, total;
+};
+
+__host__ __device__ inline size_t al_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+__host__ __device__ inline SolveLds solve_lds(int npad, bool mixed, int xslice, int L, int ng, int layer_bytes)
+{
+    SolveLds o;
+    size_t at = 0;
+    o.sx = at;
+    at += (size_t)npad * 8;
+    o.sd = at;
+    at += mixed ? (size_t)npad * 4 : 0;
+    at = al_up(at, 8);
+    o.sxr = at;
+    at += (size_t)xslice * 8;
+    o.lrhs = at;
+    at += (size_t)L * ng * 8;
+    o.lnn = at;
+    at += (size_t)L * ng * 8;
+    at = al_up(at, 16);
+    o.chunks = at;
+    at += (size_t)L * layer_bytes;
+    o.total = at;
+    return o;
+}
+
 template <class Tag, bool VEC, int LPR, bool GRID>
-__device__ void solve_loop(const SolveSys& S, const Ctl& C, int wg, int G, char* smem)
+__device__ __forceinline__ void solve_loop(const SolveSys& S, const Ctl& C, XRec* exch, int wg, int G, char* smem)
 {
     constexpr bool MIXED = !std::is_same<Tag, tag_f64>::value;
     using LPS = typename Elem<Tag>::S;
     using LAcc = typename Elem<Tag>::Acc;
     constexpr int SW64 = LPR * (VEC ? 2 : 1) * kK;
     constexpr int SWLP = LPR * (VEC ? Elem<Tag>::kVec : 1) * chunk_k<Tag>();
+    constexpr int NG = kNT / LPR;
+    constexpr int LAYER = kNT * chunk_k<Tag>() * 16;
     __shared__ Red slots[kNW];
 
     const int tid = threadIdx.x;
@@ -319,8 +453,7 @@ __device__ void solve_loop(const SolveSys& S, const Ctl& C, int wg, int G, char*
     const int npad = S.npad;
     const int nseg64 = (n + SW64 - 1) / SW64;
     const int nseglp = (n + SWLP - 1) / SWLP;
-    double* sx = reinterpret_cast<double*>(smem);           // x, FP64, zero past n
-    LAcc* sd = reinterpret_cast<LAcc*>(sx + npad);          // x - x_ref (mixed), zero past n
+    const int nseg_res = MIXED ? nseglp : nseg64;  // the stream that uses the resident chunks
 
     const int rows_per = (d + G - 1) / G;
     const int r0 = min(d, wg * rows_per);
@@ -328,17 +461,37 @@ __device__ void solve_loop(const SolveSys& S, const Ctl& C, int wg, int G, char*
     const int cols_per = (n + G - 1) / G;
     const int e0 = min(n, wg * cols_per);
     const int e1 = min(n, e0 + cols_per);
+    // resident chunks: at most what LDS was sized for, and no more than the
+    // longest group sequence of this workgroup
+    const int gmax_rows = rows_per > 0 ? (rows_per + NG - 1) / NG : 0;
+    const int L = min(C.res_layers, gmax_rows * nseg_res);
+
+    const SolveLds lay = solve_lds(npad, MIXED, C.xslice, C.res_layers, NG, LAYER);
+    double* sx = reinterpret_cast<double*>(smem + lay.sx);   // x, FP64, zero past n
+    LAcc* sd = reinterpret_cast<LAcc*>(smem + lay.sd);       // x - x_ref (mixed), zero past n
+    double* sxr = reinterpret_cast<double*>(smem + lay.sxr); // x_ref[e0 .. e1)
+    double* lrhs = reinterpret_cast<double*>(smem + lay.lrhs);
+    double* lnn = reinterpret_cast<double*>(smem + lay.lnn);
+    uint4* lchunks = reinterpret_cast<uint4*>(smem + lay.chunks);
+    const ResLds res{lchunks, lrhs, lnn, L};
+    const ResLds none{nullptr, nullptr, nullptr, 0};
 
     // x lives in LDS (sx); each thread owns columns tid + j*kNT and is the
-    // only writer of them.  Mixed precision keeps x - x_ref for the owned
-    // columns in FP64 registers (dl) and its FP32 rounding in LDS (sd).
-    double dl[kCPT];
-#pragma unroll
-    for (int j = 0; j < kCPT; ++j) dl[j] = 0.0;
+    // only writer of them.  Mixed precision also keeps x - x_ref in the
+    // accumulation type (sd): the projections since the last refresh summed
+    // in FP32, whose rounding is far below that of the low-precision rows.
     for (int c = tid; c < npad; c += kNT) {
         sx[c] = (c < n && S.x0) ? S.x0[c] : 0.0;
         if (MIXED) sd[c] = LAcc(0);
     }
+    if (S.xref && C.xslice > 0)
+        for (int c = e0 + tid; c < e1; c += kNT) sxr[c - e0] = S.xref[c];
+    if (MIXED)
+        fill_resident<Tag, VEC, LPR>(static_cast<const LPS*>(S.At), S.ldat, n, nseglp, r0, r1, S.bt, S.nu2, lchunks,
+                                     lrhs, lnn, L);
+    else
+        fill_resident<tag_f64, VEC, LPR>(S.At64, S.ldat64, n, nseg64, r0, r1, S.bt, S.nu2, lchunks, lrhs, lnn, L);
+    const int nrow_res = L / nseg_res;  // group rows whose last segment is resident
     // ||x_ref||^2 and ||bt||^2, reduced identically by every workgroup.
     Red q = red_identity();
     if (S.xref)
@@ -362,24 +515,29 @@ __device__ void solve_loop(const SolveSys& S, const Ctl& C, int wg, int G, char*
         const bool refresh = MIXED && !fp64 && (need_refresh || (k - k_ref) >= C.refresh_every);
         const bool exact = !MIXED || fp64 || refresh;
         Red loc = red_identity();
-        if (exact) {
+        if (MIXED && refresh) {
             // the refresh product of the mixed mode runs once per window: a
             // shallower ring leaves the registers to the working-precision one
-            stream_rows<tag_f64, VEC, LPR, MIXED ? 2 : ring_depth<tag_f64>()>(
-                S.At64, S.ldat64, n, nseg64, r0, r1, sx, S.bt, refresh ? S.rref : nullptr, S.nu2, loc);
+            // (it streams every chunk: the resident ones are low precision)
+            stream_rows<tag_f64, VEC, LPR, 2, true>(S.At64, S.ldat64, n, nseg64, r0, r1, sx, S.bt, S.rref, S.nu2,
+                                                    loc, none, lrhs, nrow_res);
+        } else if (exact) {
+            stream_rows<tag_f64, VEC, LPR, MIXED ? 2 : ring_depth<tag_f64>(), false>(
+                S.At64, S.ldat64, n, nseg64, r0, r1, sx, S.bt, nullptr, S.nu2, loc, MIXED ? none : res, nullptr, 0);
         } else {
-            stream_rows<Tag, VEC, LPR, ring_depth<Tag>()>(static_cast<const LPS*>(S.At), S.ldat, n, nseglp, r0, r1,
-                                                          sd, S.rref, nullptr, S.nu2, loc);
+            stream_rows<Tag, VEC, LPR, ring_depth<Tag>(), false>(static_cast<const LPS*>(S.At), S.ldat, n, nseglp,
+                                                                 r0, r1, sd, S.rref, nullptr, S.nu2, loc, res,
+                                                                 nullptr, 0);
         }
         if (S.xref)
             for (int c = e0 + tid; c < e1; c += kNT) {
-                const double e = sx[c] - S.xref[c];
+                const double e = sx[c] - (C.xslice > 0 ? sxr[c - e0] : S.xref[c]);
                 loc.e2 += e * e;
             }
         if (wg == 0 && tid == 0 && C.cancel && (k % C.check_every) == 0 && *C.cancel != 0)
             loc.flags |= kFlagCancel;
         Red tot = block_red<kNT>(loc, slots);
-        if constexpr (GRID) tot = exchange(tot, C.exch, wg, G, k, slots);
+        if constexpr (GRID) tot = exchange(tot, exch, wg, G, k, slots, rel_err);
 
         // Stop test on x_k (top of iteration k).
         bool conv;
@@ -412,17 +570,11 @@ __device__ void solve_loop(const SolveSys& S, const Ctl& C, int wg, int G, char*
         // Projection onto row i_k, on this workgroup's copy of x.
         const double alpha = tot.r;
         const double* __restrict__ arow = S.At64 + (int64_t)tot.idx * S.ldat64;
-#pragma unroll
-        for (int j = 0; j < kCPT; ++j) {
-            const int c = tid + j * kNT;
-            if (c < n) {
-                const double a = arow[c];
-                sx[c] = sx[c] + alpha * a;
-                if (MIXED) {
-                    dl[j] = (refresh ? 0.0 : dl[j]) + alpha * a;
-                    sd[c] = static_cast<LAcc>(dl[j]);
-                }
-            }
+#pragma unroll 2
+        for (int c = tid; c < n; c += kNT) {
+            const double a = arow[c];
+            sx[c] = sx[c] + alpha * a;
+            if (MIXED) sd[c] = (refresh ? LAcc(0) : sd[c]) + static_cast<LAcc>(alpha * a);
         }
         __syncthreads();
     }
@@ -443,29 +595,47 @@ template <class Tag, bool VEC, int LPR>
 __global__ __launch_bounds__(kNT) void k_solve_grid(SolveSys S, Ctl C)
 {
     extern __shared__ __align__(16) char smem[];
-    solve_loop<Tag, VEC, LPR, true>(S, C, blockIdx.x, gridDim.x, smem);
+    solve_loop<Tag, VEC, LPR, true>(S, C, C.exch, blockIdx.x, gridDim.x, smem);
 }
 
 template <class Tag, bool VEC, int LPR>
 __global__ __launch_bounds__(kNT) void k_solve_single(SolveSys S, Ctl C)
 {
     extern __shared__ __align__(16) char smem[];
-    solve_loop<Tag, VEC, LPR, false>(S, C, 0, 1, smem);
+    solve_loop<Tag, VEC, LPR, false>(S, C, nullptr, 0, 1, smem);
 }
 
+// Work items in queue order: queue position p owns items
+// [item_off[p], item_off[p+1]); a system with one item runs the
+// single-workgroup loop, a split one the grid loop over its P items with its
+// own exchange records.  The launch is cooperative (every workgroup
+// resident) and items are claimed in order, so the parts of a split system
+// are always all claimed: only the most recently claimed system can be
+// incomplete, and a free workgroup claims its next part.
 template <class Tag, bool VEC, int LPR>
 __global__ __launch_bounds__(kNT) void k_solve_batched(const SolveSys* __restrict__ sys, Ctl C)
 {
     extern __shared__ __align__(16) char smem[];
     __shared__ int32_t s_next;
+    const int32_t nitems = C.item_off[C.nsys];
     for (;;) {
         if (threadIdx.x == 0) s_next = static_cast<int32_t>(atomicAdd(C.queue, 1u));
         __syncthreads();
-        const int32_t qpos = s_next;
+        const int32_t item = s_next;
         __syncthreads();
-        if (qpos >= C.nsys) break;
-        const SolveSys S = sys[C.order[qpos]];
-        solve_loop<Tag, VEC, LPR, false>(S, C, 0, 1, smem);
+        if (item >= nitems) break;
+        int lo = 0, hi = C.nsys;  // item_off[lo] <= item < item_off[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (C.item_off[mid] <= item) lo = mid;
+            else hi = mid;
+        }
+        const int parts = C.item_off[lo + 1] - C.item_off[lo];
+        const SolveSys S = sys[C.order[lo]];
+        if (parts == 1)
+            solve_loop<Tag, VEC, LPR, false>(S, C, nullptr, 0, 1, smem);
+        else
+            solve_loop<Tag, VEC, LPR, true>(S, C, C.exch + C.exch_off[lo], item - C.item_off[lo], parts, smem);
         __syncthreads();
     }
 }
@@ -488,16 +658,43 @@ __global__ __launch_bounds__(256) void k_row_norms2(const double* __restrict__ A
     }
 }
 
-size_t smem_bytes(int64_t npad, bool mixed)
+constexpr int kMaxResLayers = 16;
+constexpr size_t kLdsReserve = 2048;  // static LDS of the kernels, rounded up
+
+// Sizes the LDS of a solve launch: the operand vectors, the x_ref slice,
+// then as many resident chunk layers as fit (never more than `want`).
+template <class Tag, int LPR>
+SolveLds plan_lds(int npad, int& xslice, int want, int& layers)
 {
-    return (size_t)npad * 8 + (mixed ? (size_t)npad * 4 : 0) + 16;
+    const bool mixed = !std::is_same<Tag, tag_f64>::value;
+    constexpr int NG = kNT / LPR;
+    constexpr int LAYER = kNT * chunk_k<Tag>() * 16;
+    const size_t cap = (size_t)device_max_lds() - kLdsReserve;
+    // the x_ref slice is a convenience: without room it is read from memory
+    if (xslice > 0 && solve_lds(npad, mixed, xslice, 0, NG, LAYER).total > cap) xslice = 0;
+    int L = std::max(0, std::min(want, kMaxResLayers));
+    while (L > 0 && solve_lds(npad, mixed, xslice, L, NG, LAYER).total > cap) --L;
+    layers = L;
+    return solve_lds(npad, mixed, xslice, L, NG, LAYER);
 }
 
 template <class Tag, bool VEC, int LPR>
-csk_status launch_solve(const SolveSys& S, const Ctl& C, int grid, hipStream_t st)
+csk_status launch_solve(const SolveSys& S, Ctl C, int grid, hipStream_t st)
 {
-    const bool mixed = !std::is_same<Tag, tag_f64>::value;
-    const size_t shm = smem_bytes(S.npad, mixed);
+    constexpr bool mixed = !std::is_same<Tag, tag_f64>::value;
+    constexpr int NG = kNT / LPR;
+    const int sw = LPR * (VEC ? (mixed ? Elem<Tag>::kVec : 2) : 1) * chunk_k<Tag>();
+    const int nseg = (S.n + sw - 1) / sw;
+    const int g = std::max(grid, 1);
+    const int rows_per = (S.d + g - 1) / g;
+    const int want = ((rows_per + NG - 1) / NG) * nseg;
+    C.xslice = S.xref ? (S.n + g - 1) / g : 0;
+    const SolveLds lay = plan_lds<Tag, LPR>(S.npad, C.xslice, want, C.res_layers);
+    const size_t shm = lay.total;
+    if (shm > (size_t)device_max_lds() - kLdsReserve) {
+        set_error("the solve needs %zu bytes of LDS per workgroup (n = %d too large)", shm, S.n);
+        return CSK_ERR_UNSUPPORTED;
+    }
     if (grid <= 1) {
         auto kern = k_solve_single<Tag, VEC, LPR>;
         CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
@@ -544,18 +741,75 @@ csk_status dispatch_solve(const SolveSys& S, const Ctl& C, const SolvePlan& p, h
 constexpr int kBatchLPR = 16;
 
 template <class Tag>
-csk_status launch_batched(const SolveSys* sys, const Ctl& C, int64_t npad_max, hipStream_t st)
+csk_status launch_batched(const SolveSys* sys_dev, int32_t nsys, const BatchedPlan& bp, Ctl C, hipStream_t st)
 {
-    const bool mixed = !std::is_same<Tag, tag_f64>::value;
-    const size_t shm = smem_bytes(npad_max, mixed);
+    constexpr bool mixed = !std::is_same<Tag, tag_f64>::value;
+    constexpr int NG = kNT / kBatchLPR;
+    const int sw = kBatchLPR * (mixed ? Elem<Tag>::kVec : 2) * chunk_k<Tag>();
+    const int64_t nseg = (bp.n_max + sw - 1) / sw;
+    const int want = (int)std::min<int64_t>(kMaxResLayers, ((bp.d_max + NG - 1) / NG) * nseg);
+    C.xslice = (int)bp.n_max;
+    const SolveLds lay = plan_lds<Tag, kBatchLPR>((int)bp.npad_max, C.xslice, want, C.res_layers);
+    const size_t shm = lay.total;
+    if (shm > (size_t)device_max_lds() - kLdsReserve) {
+        set_error("the batched solve needs %zu bytes of LDS per workgroup (n = %lld too large)", shm,
+                  (long long)bp.n_max);
+        return CSK_ERR_UNSUPPORTED;
+    }
     auto kern = k_solve_batched<Tag, true, kBatchLPR>;
     CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
     int per_cu = 0;
     CSK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern), kNT, shm));
-    const int grid = std::max(1, std::min(C.nsys, std::max(1, per_cu) * device_cu_count()));
-    kern<<<grid, kNT, shm, st>>>(sys, C);
-    CSK_LAUNCH_CHECK("k_solve_batched");
+    const int cap = std::max(1, per_cu) * device_cu_count();
+
+    // Split plan: the estimated work of a system is d n^2 (bytes per
+    // iteration times an iteration count that grows with n).  A system above
+    // twice the average share of one workgroup gets about work / share
+    // workgroups, at least 32 rows each, at most half the grid.
+    double W = 0.0;
+    for (int32_t p = 0; p < nsys; ++p) {
+        const SolveSys& S = bp.sys[bp.order[p]];
+        W += (double)S.d * (double)S.n * (double)S.n;
+    }
+    const double share = W / cap;
+    std::vector<int32_t> item_off(nsys + 1), exch_off(nsys, 0);
+    size_t rec = 0;
+    int32_t items = 0;
+    for (int32_t p = 0; p < nsys; ++p) {
+        const SolveSys& S = bp.sys[bp.order[p]];
+        const double w = (double)S.d * (double)S.n * (double)S.n;
+        int parts = 1;
+        if (w > 2.0 * share) {
+            const double want_parts = std::ceil(w / share);
+            parts = (int)std::min<double>(want_parts, (double)std::max(1, S.d / 32));
+            parts = std::max(1, std::min(parts, cap / 2));
+            if (parts > 1 && rec + 2 * (size_t)parts > bp.exch_records) parts = 1;
+        }
+        item_off[p] = items;
+        exch_off[p] = (int32_t)rec;
+        items += parts;
+        if (parts > 1) rec += 2 * (size_t)parts;
+    }
+    item_off[nsys] = items;
+    csk_status e = upload_i32(item_off.data(), nsys + 1, bp.item_off_dev, st);
+    if (e == CSK_OK) e = upload_i32(exch_off.data(), nsys, bp.exch_off_dev, st);
+    if (e != CSK_OK) return e;
+    C.item_off = bp.item_off_dev;
+    C.exch_off = bp.exch_off_dev;
+    C.exch = static_cast<XRec*>(bp.exch_dev);
+    if (rec > 0) {
+        const int64_t words = (int64_t)rec * (int64_t)sizeof(XRec) / 4;
+        k_zero_words<<<(int)std::min<int64_t>(256, (words + 255) / 256), 256, 0, st>>>(
+            reinterpret_cast<uint32_t*>(bp.exch_dev), words);
+        CSK_LAUNCH_CHECK("k_zero_words");
+    }
+    const int grid = std::max(1, std::min(items, cap));
+    const SolveSys* s_arg = sys_dev;
+    Ctl c_arg = C;
+    void* args[] = {&s_arg, &c_arg};
+    CSK_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(grid), dim3(kNT), args,
+                                       (unsigned)shm, st));
     return CSK_OK;
 }
 
@@ -665,21 +919,24 @@ csk_status solve_run(const SolveSys& sys_in, csk_dtype at_dtype, const csk_solve
     }
 }
 
-csk_status solve_batched_run(const SolveSys* sys_dev, const int32_t* order_dev, int32_t nsys,
-                             int64_t npad_max, csk_dtype at_dtype, const csk_solve_opts* o,
-                             uint32_t* queue_dev, hipStream_t st)
+size_t solve_exch_record_bytes() { return sizeof(XRec); }
+
+csk_status solve_batched_run(const SolveSys* sys_dev, int32_t nsys, const BatchedPlan& bp, csk_dtype at_dtype,
+                             const csk_solve_opts* o, hipStream_t st)
 {
     Ctl C = make_ctl(o);
-    C.queue = queue_dev;
-    C.order = order_dev;
+    C.queue = bp.queue_dev;
+    C.order = bp.order_dev;
     C.nsys = nsys;
-    k_zero_words<<<1, 64, 0, st>>>(queue_dev, 1);
+    csk_status e = upload_i32(bp.order, nsys, bp.order_dev, st);
+    if (e != CSK_OK) return e;
+    k_zero_words<<<1, 64, 0, st>>>(bp.queue_dev, 1);
     CSK_LAUNCH_CHECK("k_zero_words");
     switch (at_dtype) {
-    case CSK_F64: return launch_batched<tag_f64>(sys_dev, C, npad_max, st);
-    case CSK_F32: return launch_batched<tag_f32>(sys_dev, C, npad_max, st);
-    case CSK_F16: return launch_batched<tag_f16>(sys_dev, C, npad_max, st);
-    case CSK_BF16: return launch_batched<tag_bf16>(sys_dev, C, npad_max, st);
+    case CSK_F64: return launch_batched<tag_f64>(sys_dev, nsys, bp, C, st);
+    case CSK_F32: return launch_batched<tag_f32>(sys_dev, nsys, bp, C, st);
+    case CSK_F16: return launch_batched<tag_f16>(sys_dev, nsys, bp, C, st);
+    case CSK_BF16: return launch_batched<tag_bf16>(sys_dev, nsys, bp, C, st);
     default: return CSK_ERR_UNSUPPORTED;
     }
 }

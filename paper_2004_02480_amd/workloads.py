@@ -40,6 +40,11 @@ CONFIGS = {
                        maxit=2000000),
     "batched": dict(nsys=512, seed=5000, sketch_seed=15000, tol=1e-8, maxit=400000),
     "multi_rhs": dict(m=200000, n=500, nrhs=256, d=10000, seed=6, sketch_seed=106, tol=1e-8, maxit=400000),
+    # Section 3's experiment: N(0,1) A and x*, d = n^2, x0 = 0, stop at
+    # RES = ||x - x*||^2 / ||x*||^2 <= 1e-6 (tol 1e-3 on the plain relative
+    # error) or 20000 iterations; trial t uses seeds seed + t, sketch_seed + t
+    "table1": dict(ms=(300000, 400000, 500000, 600000, 700000), ns=(50, 100, 150), seed=10000,
+                   sketch_seed=20000, tol=1e-3, maxit=20000),
 }
 
 
