@@ -147,7 +147,12 @@ csk_status csk_hash(uint64_t seed, int64_t m, int64_t d, uint32_t* bucket, int8_
  *   perm   m u32: rows grouped by bucket, ascending within a bucket;
  *   ptr    d+1 u32: bucket j owns perm[ptr[j] .. ptr[j+1]), ptr[d] = m.
  * Requires 1 <= m < 2^31, n >= 1, 1 <= d < 2^31, lda >= n.  The paper asks
- * for d < m; that is recommended, not enforced (the sketch stays defined).  */
+ * for d < m; that is recommended, not enforced (the sketch stays defined).
+ * Memory: when A (or B) starts on 16 bytes and its leading dimension times
+ * the element size is a multiple of 16, rows are read in whole 16-byte
+ * vectors, so the bytes of the last row up to the end of the vector holding
+ * its last column are read (their values are ignored); a buffer of m * lda
+ * elements always suffices.  Otherwise rows are read element by element.   */
 csk_status csk_sketch_workspace_size(int64_t m, int64_t n, int64_t d, int64_t nrhs, size_t* bytes /*host*/);
 csk_status csk_sketch(const void* A, csk_dtype a_dtype, int64_t m, int64_t n, int64_t lda,
                       const double* B, int64_t nrhs, int64_t ldb,

@@ -61,6 +61,79 @@ __device__ __forceinline__ GridRed wave_red(GridRed v)
     return v;
 }
 
+// The same reduction with DPP lane moves inside each row of 16 lanes
+// (quad permutations, then the half-row and row mirrors: each step pairs
+// lanes whose partial results cover disjoint lane sets, so after four steps
+// every lane holds its row's reduction) and the four rows combined in a
+// fixed order from lanes 0, 16, 32, 48.  The result is uniform.
+template <int CTRL> __device__ __forceinline__ uint32_t dpp_u32(uint32_t v)
+{
+    return static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(static_cast<int>(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL> __device__ __forceinline__ double dpp_f64(double v)
+{
+    const uint64_t b = static_cast<uint64_t>(__double_as_longlong(v));
+    const uint64_t lo = dpp_u32<CTRL>(static_cast<uint32_t>(b));
+    const uint64_t hi = dpp_u32<CTRL>(static_cast<uint32_t>(b >> 32));
+    return __longlong_as_double(static_cast<long long>((hi << 32) | lo));
+}
+template <int CTRL> __device__ __forceinline__ GridRed dpp_step(const GridRed& v)
+{
+    GridRed o;
+    o.score = dpp_f64<CTRL>(v.score);
+    o.r = dpp_f64<CTRL>(v.r);
+    o.r2 = dpp_f64<CTRL>(v.r2);
+    o.e2 = dpp_f64<CTRL>(v.e2);
+    o.idx = dpp_u32<CTRL>(v.idx);
+    o.flags = dpp_u32<CTRL>(v.flags);
+    return red_combine(v, o);
+}
+__device__ __forceinline__ double readlane_f64(double v, int lane)
+{
+    const uint64_t b = static_cast<uint64_t>(__double_as_longlong(v));
+    const uint64_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(b), lane));
+    const uint64_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(b >> 32), lane));
+    return __longlong_as_double(static_cast<long long>((hi << 32) | lo));
+}
+__device__ __forceinline__ GridRed readlane_red(const GridRed& v, int lane)
+{
+    GridRed o;
+    o.score = readlane_f64(v.score, lane);
+    o.r = readlane_f64(v.r, lane);
+    o.r2 = readlane_f64(v.r2, lane);
+    o.e2 = readlane_f64(v.e2, lane);
+    o.idx = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v.idx), lane));
+    o.flags = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v.flags), lane));
+    return o;
+}
+__device__ __forceinline__ GridRed wave_red_dpp(GridRed v)
+{
+    v = dpp_step<0xB1>(v);   // quad_perm [1,0,3,2]
+    v = dpp_step<0x4E>(v);   // quad_perm [2,3,0,1]
+    v = dpp_step<0x141>(v);  // row_half_mirror
+    v = dpp_step<0x140>(v);  // row_mirror
+    GridRed t = readlane_red(v, 0);
+    t = red_combine(t, readlane_red(v, 16));
+    t = red_combine(t, readlane_red(v, 32));
+    return red_combine(t, readlane_red(v, 48));
+}
+
+// Workgroup reduction with one barrier: every thread gets the result.  The
+// caller alternates slot arrays so that a later reduction never overwrites
+// slots another wave may still be reading (a barrier always separates two
+// uses of the same array).
+template <int NT>
+__device__ __forceinline__ GridRed block_red1(GridRed v, GridRed* slots)
+{
+    v = wave_red_dpp(v);
+    if ((threadIdx.x & (kWave - 1)) == 0) slots[threadIdx.x / kWave] = v;
+    __syncthreads();
+    GridRed t = slots[0];
+#pragma unroll
+    for (int w = 1; w < NT / kWave; ++w) t = red_combine(t, slots[w]);
+    return t;
+}
+
 // Fixed-shape reduction over a workgroup of NT threads; every thread gets the
 // result.  slots: NT/64 records in LDS.
 template <int NT>

@@ -246,27 +246,28 @@ __device__ __forceinline__ void store_lp(void* base, int64_t off, double v)
     if constexpr (LP == CSK_BF16) static_cast<uint16_t*>(base)[off] = round_store<tag_bf16>(v);
 }
 
-// Raw element loads of one lane's part of a row chunk: VPL vectors of VW
-// elements (16 bytes each when VW > 1); columns at or past n read as zero.
+// Raw loads of one lane's part of a row chunk: VPL vectors of VW elements
+// (16 bytes each when VW > 1).  Branch-free: a vector that starts at or past
+// column n reads the row's first vector instead; a vector that starts before
+// n may end past it, inside the row's 16-byte padded length (the vector
+// path requires 16-byte rows).  Elements past n are never stored, so their
+// bits do not matter.  Without branches the compiler never merges different
+// loads, and its waits on the in-order vector-memory counter only wait for
+// the row slot that is consumed.
 template <class TA, int VW, int VPL>
-__device__ __forceinline__ void load_row_chunk(TA (&v)[VPL][VW], const TA* __restrict__ rowp, int col0, int lane, int n,
-                                               bool on)
+__device__ __forceinline__ void load_row_chunk(TA (&v)[VPL][VW], const TA* __restrict__ rowp, int col0, int lane, int n)
 {
 #pragma unroll
     for (int q = 0; q < VPL; ++q) {
         const int col = col0 + (q * kWave + lane) * VW;
-        if (on && col + VW <= n) {
-            if constexpr (VW == 1) {
-                v[q][0] = rowp[col];
-            } else {
-                using V = typename VecOf<TA>::type;
-                const V x = *reinterpret_cast<const V*>(rowp + col);
-                static_assert(sizeof(V) == sizeof(TA) * VW, "vector width");
-                __builtin_memcpy(&v[q][0], &x, sizeof(V));
-            }
+        const int cc = col < n ? col : 0;
+        if constexpr (VW == 1) {
+            v[q][0] = rowp[cc];
         } else {
-#pragma unroll
-            for (int e = 0; e < VW; ++e) v[q][e] = (on && col + e < n) ? rowp[col + e] : TA(0);
+            using V = typename VecOf<TA>::type;
+            static_assert(sizeof(V) == sizeof(TA) * VW, "vector width");
+            const V x = *reinterpret_cast<const V*>(rowp + cc);
+            __builtin_memcpy(&v[q][0], &x, sizeof(V));
         }
     }
 }
@@ -275,8 +276,11 @@ __device__ __forceinline__ void load_row_chunk(TA (&v)[VPL][VW], const TA* __res
 // elements per lane, i.e. 64*VW*VPL columns.  The bucket's row indices are
 // read 64 at a time (one per lane, with their signs and b values); the rows
 // then stream through a ring of D row slots whose indices are broadcast from
-// those lanes, so D rows are always in flight.  Every accumulation stays in
-// ascending row order, sequential per output element (one lane each).
+// those lanes, so D rows are always in flight.  The ring runs whole rounds
+// (slots past the bucket's last row reload that row and are not added), so
+// every load is unconditional.  Every accumulation stays in ascending row
+// order, sequential per output element (one lane each); a padding slot is
+// excluded by a select, never by a zero factor.
 template <class TA, int VW, int VPL, int D, int LP>
 __global__ __launch_bounds__(256) void k_segsum(Batch b)
 {
@@ -309,28 +313,32 @@ __global__ __launch_bounds__(256) void k_segsum(Batch b)
             const uint32_t my_row = lane < cnt ? b.perm[base + lane] : 0u;
             const double my_sg = draw_sign(draw_word(S.seed, my_row));
             const double my_b = (with_b && lane < cnt) ? S.B[(int64_t)my_row * S.ldb] : 0.0;
+            const int nround = (cnt + D - 1) / D;
             TA val[D][VPL][VW];
 #pragma unroll
             for (int u = 0; u < D; ++u) {
-                const uint32_t row = __builtin_amdgcn_readlane(my_row, u < cnt ? u : 0);
-                load_row_chunk<TA, VW, VPL>(val[u], A + (int64_t)row * lda, col0, lane, n, u < cnt);
+                const uint32_t row = __builtin_amdgcn_readlane(my_row, min(u, cnt - 1));
+                load_row_chunk<TA, VW, VPL>(val[u], A + (int64_t)row * lda, col0, lane, n);
             }
-            for (int p = 0; p < cnt; p += D) {
+            for (int rd = 0; rd < nround; ++rd) {
 #pragma unroll
                 for (int u = 0; u < D; ++u) {
-                    const int qi = p + u;
-                    if (qi < cnt) {
-                        const double sg = __shfl(my_sg, qi, kWave);
+                    const int qi = rd * D + u;
+                    const bool use = qi < cnt;
+                    const double sg = __shfl(my_sg, min(qi, kWave - 1), kWave);
 #pragma unroll
-                        for (int q = 0; q < VPL; ++q)
+                    for (int q = 0; q < VPL; ++q)
 #pragma unroll
-                            for (int e = 0; e < VW; ++e)
-                                acc[q][e] = acc[q][e] + sg * static_cast<double>(val[u][q][e]);
-                        if (with_b) bacc = bacc + sg * __shfl(my_b, qi, kWave);
-                        const int nq = qi + D;
-                        const uint32_t row = __builtin_amdgcn_readlane(my_row, nq < cnt ? nq : 0);
-                        load_row_chunk<TA, VW, VPL>(val[u], A + (int64_t)row * lda, col0, lane, n, nq < cnt);
+                        for (int e = 0; e < VW; ++e) {
+                            const double nv = acc[q][e] + sg * static_cast<double>(val[u][q][e]);
+                            acc[q][e] = use ? nv : acc[q][e];
+                        }
+                    if (with_b) {
+                        const double nb = bacc + sg * __shfl(my_b, min(qi, kWave - 1), kWave);
+                        bacc = use ? nb : bacc;
                     }
+                    const uint32_t row = __builtin_amdgcn_readlane(my_row, min(qi + D, cnt - 1));
+                    load_row_chunk<TA, VW, VPL>(val[u], A + (int64_t)row * lda, col0, lane, n);
                 }
             }
         }

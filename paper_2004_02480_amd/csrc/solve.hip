@@ -278,27 +278,35 @@ __device__ __forceinline__ void stream_rows(const typename Elem<Tag>::S* __restr
         }
         if (++cseg == nseg) { cseg = 0; ++crow; }
     }
+    // consume slot u (chunk c) of the ring
     int c = Lg;
-    for (int rd = 0; rd < nround; ++rd) {
-        const bool last = rd == nround - 1;
+    auto consume = [&](const uint4 (&v)[KK], int lm, double p, double nn) {
+        const int cbase = cseg * SW + q * VW;
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) acc += E::template dot<VW>(v[kk], xs + cbase + kk * LPR * VW, lm - kk * LPR * VW);
+        if (cseg == nseg - 1) {
+            const Acc s = group_sum_t<Acc, LPR>(acc);
+            acc = Acc(0);
+            if (c < nchunk) finish(crow, s, p, nn);
+        }
+        if (++cseg == nseg) { cseg = 0; ++crow; }
+        ++c;
+    };
+    // all rounds but the last refill every slot; the last one, a
+    // straight-line epilogue, issues no loads that nothing would consume
+    for (int rd = 0; rd + 1 < nround; ++rd) {
 #pragma unroll
         for (int u = 0; u < kD; ++u) {
-            const int cbase = cseg * SW + q * VW;
-#pragma unroll
-            for (int kk = 0; kk < KK; ++kk)
-                acc += E::template dot<VW>(buf[u][kk], xs + cbase + kk * LPR * VW, lim[u] - kk * LPR * VW);
-            if (cseg == nseg - 1) {
-                const Acc s = group_sum_t<Acc, LPR>(acc);
-                acc = Acc(0);
-                if (c < nchunk) finish(crow, s, pr[u], pn[u]);
-            }
-            if (++cseg == nseg) { cseg = 0; ++crow; }
-            ++c;
+            consume(buf[u], lim[u], pr[u], pn[u]);
             lim[u] = load_chunk<Tag, VW, LPR, KK>(buf[u], pr[u], pn[u], A, lda, n, r0 + g + NG * irow, r0, iseg, q,
-                                                  !last && iload < nchunk, rhs, nu2);
+                                                  iload < nchunk, rhs, nu2);
             ++iload;
             if (++iseg == nseg) { iseg = 0; ++irow; }
         }
+    }
+    if (nround > 0) {
+#pragma unroll
+        for (int u = 0; u < kD; ++u) consume(buf[u], lim[u], pr[u], pn[u]);
     }
 }
 
@@ -359,7 +367,7 @@ __device__ __forceinline__ double join_f64(uint64_t lo, uint64_t hi)
 }
 
 __device__ __forceinline__ Red exchange(const Red& mine, XRec* exch, int wg, int G, int64_t k, Red* slots,
-                                        bool rel_err)
+                                        bool rel_err)  // slots: reduced with block_red1
 {
     XRec* slot = exch + (size_t)(k & 1) * G;
     const uint64_t tag = static_cast<uint64_t>(static_cast<uint32_t>(k + 1)) << 32;
@@ -376,7 +384,18 @@ __device__ __forceinline__ Red exchange(const Red& mine, XRec* exch, int wg, int
     for (int w = threadIdx.x; w < G; w += kNT) {
         uint64_t v[8];
         uint32_t spins = 0;
-        for (;;) {
+        // Poll one word of the record (one request per record and round:
+        // the G x G polls of a grid are the exchange's main traffic), then
+        // read the line; the eight words leave in one store instruction, so
+        // a stale word after a fresh first one is rare and just re-read.
+        while ((coh_load(&slot[w].w[0]) & 0xFFFFFFFF00000000ull) != tag) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins > kSpinLimit) {
+                ok = false;
+                break;
+            }
+        }
+        while (ok) {
 #pragma unroll
             for (int f = 0; f < 8; ++f) v[f] = coh_load(&slot[w].w[f]);
             bool fresh = true;
@@ -401,7 +420,7 @@ __device__ __forceinline__ Red exchange(const Red& mine, XRec* exch, int wg, int
         all = red_combine(all, o);
     }
     if (!ok) all.flags |= kFlagTimeout;
-    return block_red<kNT>(all, slots);
+    return block_red1<kNT>(all, slots);
 }
 
 // LDS carve of the solve: x (FP64), x - x_ref in the accumulation type
@@ -446,6 +465,7 @@ __device__ __forceinline__ void solve_loop(const SolveSys& S, const Ctl& C, XRec
     constexpr int NG = kNT / LPR;
     constexpr int LAYER = kNT * chunk_k<Tag>() * 16;
     __shared__ Red slots[kNW];
+    __shared__ Red slots2[kNW];  // the exchange's reduction (one barrier each)
 
     const int tid = threadIdx.x;
     const int n = S.n;
@@ -536,8 +556,8 @@ __device__ __forceinline__ void solve_loop(const SolveSys& S, const Ctl& C, XRec
             }
         if (wg == 0 && tid == 0 && C.cancel && (k % C.check_every) == 0 && *C.cancel != 0)
             loc.flags |= kFlagCancel;
-        Red tot = block_red<kNT>(loc, slots);
-        if constexpr (GRID) tot = exchange(tot, exch, wg, G, k, slots, rel_err);
+        Red tot = block_red1<kNT>(loc, slots);
+        if constexpr (GRID) tot = exchange(tot, exch, wg, G, k, slots2, rel_err);
 
         // Stop test on x_k (top of iteration k).
         bool conv;
