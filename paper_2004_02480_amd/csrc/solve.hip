@@ -125,11 +125,36 @@ template <class Tag> struct Elem16 {
 template <> struct Elem<tag_f16> : Elem16<tag_f16> {};
 template <> struct Elem<tag_bf16> : Elem16<tag_bf16> {};
 
+// Sum over an aligned group of W lanes (4, 16 or 64), every lane of the
+// group getting the same bits: DPP moves inside quads and 16-lane rows (each
+// step adds two partial sums over disjoint lane sets, a + b on one side and
+// b + a on the other), and for W = 64 the four row sums read from lanes 0,
+// 16, 32, 48 and added in that order.
+template <int CTRL> __device__ __forceinline__ float dpp_move(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL> __device__ __forceinline__ double dpp_move(double v)
+{
+    return dpp_f64<CTRL>(v);
+}
+__device__ __forceinline__ float lane_value(float v, int lane)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+__device__ __forceinline__ double lane_value(double v, int lane) { return readlane_f64(v, lane); }
+
 template <class T, int W>
 __device__ __forceinline__ T group_sum_t(T v)
 {
-#pragma unroll
-    for (int off = W / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, W);
+    static_assert(W == 4 || W == 16 || W == 64, "lane group");
+    v = v + dpp_move<0xB1>(v);  // quad_perm [1,0,3,2]
+    v = v + dpp_move<0x4E>(v);  // quad_perm [2,3,0,1]
+    if constexpr (W >= 16) {
+        v = v + dpp_move<0x141>(v);  // row_half_mirror
+        v = v + dpp_move<0x140>(v);  // row_mirror
+    }
+    if constexpr (W == 64) v = ((lane_value(v, 0) + lane_value(v, 16)) + lane_value(v, 32)) + lane_value(v, 48);
     return v;
 }
 
@@ -189,6 +214,45 @@ struct ResLds {
     int L;
 };
 
+// The load ring of a streamed walk: kD chunk slots with the right-hand
+// side, squared norm and element limit of each (registers).  Its first
+// loads are not issued across iterations: they are about a third of an
+// iteration's streamed bytes, and with the in-order load counter any later
+// wait (exchange polls, the projection's row) would wait for them too.
+template <class Tag, int kD> struct Ring {
+    uint4 buf[kD][chunk_k<Tag>()];
+    double pr[kD], pn[kD];
+    int lim[kD];
+};
+
+// Issues the ring's first kD loads: chunks L, L+1, ... of each lane group's
+// walk over rows [r0, r1) (the first L are LDS-resident).
+template <class Tag, bool VEC, int LPR, int kD>
+__device__ __forceinline__ void ring_prime(Ring<Tag, kD>& R, const typename Elem<Tag>::S* __restrict__ A,
+                                           int64_t lda, int n, int nseg, int r0, int r1,
+                                           const double* __restrict__ rhs, const double* __restrict__ nu2, int L)
+{
+    using E = Elem<Tag>;
+    constexpr int VW = VEC ? E::kVec : 1;
+    constexpr int NG = kNT / LPR;
+    constexpr int KK = chunk_k<Tag>();
+    const int q = threadIdx.x % LPR;
+    const int g = threadIdx.x / LPR;
+    const int span = r1 - r0;
+    const int nrows = span > g ? (span - g + NG - 1) / NG : 0;
+    const int nchunk = nrows * nseg;
+    const int nchunk_max = (span > 0 ? (span + NG - 1) / NG : 0) * nseg;
+    const int Lg = min(L, nchunk_max);
+    if (nchunk_max - Lg <= 0) return;
+    int irow = Lg / nseg, iseg = Lg - (Lg / nseg) * nseg;
+#pragma unroll
+    for (int u = 0; u < kD; ++u) {
+        R.lim[u] = load_chunk<Tag, VW, LPR, KK>(R.buf[u], R.pr[u], R.pn[u], A, lda, n, r0 + g + NG * irow, r0, iseg,
+                                                q, Lg + u < nchunk, rhs, nu2);
+        if (++iseg == nseg) { iseg = 0; ++irow; }
+    }
+}
+
 // Residuals, candidates and partial ||r||^2 for rows [r0, r1) of the
 // workgroup.  Lane groups of LPR lanes share a row; a row is split into
 // nseg segments of LPR*VW*kK columns; the group walks its (row, segment)
@@ -206,6 +270,7 @@ __device__ __forceinline__ void stream_rows(const typename Elem<Tag>::S* __restr
                                             const double* __restrict__ nu2, Red& loc, const ResLds& res,
                                             double* lrout, int nrow_out)
 {
+    Ring<Tag, kD> R;
     using E = Elem<Tag>;
     using Acc = typename E::Acc;
     constexpr int VW = VEC ? E::kVec : 1;
@@ -248,20 +313,13 @@ __device__ __forceinline__ void stream_rows(const typename Elem<Tag>::S* __restr
         }
     };
 
-    uint4 buf[kD][KK];
-    double pr[kD], pn[kD];  // right-hand side and squared norm of the slot's row
-    int lim[kD];            // valid elements of the slot from this lane's first column
-    int irow = Lg / nseg, iseg = Lg - (Lg / nseg) * nseg;  // next chunk to load
-    int iload = Lg;
-    if (nround > 0) {
-#pragma unroll
-        for (int u = 0; u < kD; ++u) {
-            lim[u] = load_chunk<Tag, VW, LPR, KK>(buf[u], pr[u], pn[u], A, lda, n, r0 + g + NG * irow, r0, iseg, q,
-                                                  iload < nchunk, rhs, nu2);
-            ++iload;
-            if (++iseg == nseg) { iseg = 0; ++irow; }
-        }
-    }
+    auto& buf = R.buf;
+    auto& pr = R.pr;  // right-hand side and squared norm of the slot's row
+    auto& pn = R.pn;
+    auto& lim = R.lim;  // valid elements of the slot from this lane's first column
+    ring_prime<Tag, VEC, LPR, kD>(R, A, lda, n, nseg, r0, r1, rhs, nu2, res.L);
+    int iload = Lg + kD;  // next chunk to load
+    int irow = iload / nseg, iseg = iload - (iload / nseg) * nseg;
     int crow = 0, cseg = 0;  // next chunk to consume
     Acc acc = Acc(0);
     for (int c = 0; c < Lg; ++c) {
@@ -382,41 +440,44 @@ __device__ __forceinline__ Red exchange(const Red& mine, XRec* exch, int wg, int
     bool ok = true;
     Red all = red_identity();
     for (int w = threadIdx.x; w < G; w += kNT) {
-        uint64_t v[8];
-        uint32_t spins = 0;
-        // Poll one word of the record (one request per record and round:
-        // the G x G polls of a grid are the exchange's main traffic), then
-        // read the line; the eight words leave in one store instruction, so
-        // a stale word after a fresh first one is rare and just re-read.
-        while ((coh_load(&slot[w].w[0]) & 0xFFFFFFFF00000000ull) != tag) {
-            __builtin_amdgcn_s_sleep(2);
-            if (++spins > kSpinLimit) {
-                ok = false;
-                break;
-            }
-        }
-        while (ok) {
-#pragma unroll
-            for (int f = 0; f < 8; ++f) v[f] = coh_load(&slot[w].w[f]);
-            bool fresh = true;
-#pragma unroll
-            for (int f = 0; f < 8; ++f) fresh = fresh && ((v[f] & 0xFFFFFFFF00000000ull) == tag);
-            if (fresh) break;
-            __builtin_amdgcn_s_sleep(1);
-            if (++spins > kSpinLimit) {
-                ok = false;
-                break;
-            }
-        }
-        if (!ok) break;
         Red o;
-        o.score = join_f64(v[0], v[1]);
-        o.r = join_f64(v[2], v[3]);
-        const double meas = join_f64(v[4], v[5]);
-        o.r2 = rel_err ? 0.0 : meas;
-        o.e2 = rel_err ? meas : 0.0;
-        o.idx = static_cast<uint32_t>(v[6]);
-        o.flags = static_cast<uint32_t>(v[7]);
+        if (w == wg) {
+            o = mine;  // this workgroup's own record needs no round trip
+            if (rel_err) o.r2 = 0.0;
+            else o.e2 = 0.0;
+        } else {
+            // Poll one word of the record (one request per record and round:
+            // the G x G polls of a grid are the exchange's main traffic), then
+            // read the line; its eight words leave in one store instruction, so
+            // a stale word after a fresh first one is rare and just re-read.
+            uint64_t v[8];
+            uint32_t spins = 0;
+            while ((coh_load(&slot[w].w[0]) & 0xFFFFFFFF00000000ull) != tag) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > kSpinLimit) {
+                    ok = false;
+                    break;
+                }
+            }
+            while (ok) {
+#pragma unroll
+                for (int f = 0; f < 8; ++f) v[f] = coh_load(&slot[w].w[f]);
+                bool fresh = true;
+#pragma unroll
+                for (int f = 0; f < 8; ++f) fresh = fresh && ((v[f] & 0xFFFFFFFF00000000ull) == tag);
+                if (fresh) break;
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > kSpinLimit) ok = false;
+            }
+            if (!ok) break;
+            o.score = join_f64(v[0], v[1]);
+            o.r = join_f64(v[2], v[3]);
+            const double meas = join_f64(v[4], v[5]);
+            o.r2 = rel_err ? 0.0 : meas;
+            o.e2 = rel_err ? meas : 0.0;
+            o.idx = static_cast<uint32_t>(v[6]);
+            o.flags = static_cast<uint32_t>(v[7]);
+        }
         all = red_combine(all, o);
     }
     if (!ok) all.flags |= kFlagTimeout;
@@ -541,9 +602,12 @@ __device__ __forceinline__ void solve_loop(const SolveSys& S, const Ctl& C, XRec
             // (it streams every chunk: the resident ones are low precision)
             stream_rows<tag_f64, VEC, LPR, 2, true>(S.At64, S.ldat64, n, nseg64, r0, r1, sx, S.bt, S.rref, S.nu2,
                                                     loc, none, lrhs, nrow_res);
-        } else if (exact) {
-            stream_rows<tag_f64, VEC, LPR, MIXED ? 2 : ring_depth<tag_f64>(), false>(
-                S.At64, S.ldat64, n, nseg64, r0, r1, sx, S.bt, nullptr, S.nu2, loc, MIXED ? none : res, nullptr, 0);
+        } else if (MIXED && exact) {
+            stream_rows<tag_f64, VEC, LPR, 2, false>(S.At64, S.ldat64, n, nseg64, r0, r1, sx, S.bt, nullptr, S.nu2,
+                                                     loc, none, nullptr, 0);
+        } else if constexpr (!MIXED) {
+            stream_rows<tag_f64, VEC, LPR, ring_depth<tag_f64>(), false>(S.At64, S.ldat64, n, nseg64, r0, r1, sx,
+                                                                         S.bt, nullptr, S.nu2, loc, res, nullptr, 0);
         } else {
             stream_rows<Tag, VEC, LPR, ring_depth<Tag>(), false>(static_cast<const LPS*>(S.At), S.ldat, n, nseglp,
                                                                  r0, r1, sd, S.rref, nullptr, S.nu2, loc, res,
@@ -862,6 +926,24 @@ int64_t solve_npad(int64_t n, csk_dtype at_dtype, int lpr, bool vec)
 
 int solve_batch_lpr() { return kBatchLPR; }
 
+// Lanes per row: the one of {64, 16, 4} whose segments cover the row with
+// the fewest padded columns (elements past n cost the same work as real
+// ones); ties go to the wider group (fewer segments per row).
+int pick_lpr(int64_t n, int64_t per_lane)
+{
+    int best = 64;
+    int64_t best_cover = -1;
+    for (int lpr : {64, 16, 4}) {
+        const int64_t sw = lpr * per_lane;
+        const int64_t cover = (n + sw - 1) / sw * sw;
+        if (best_cover < 0 || cover < best_cover) {
+            best = lpr;
+            best_cover = cover;
+        }
+    }
+    return best;
+}
+
 SolvePlan solve_plan(int64_t d, int64_t n, csk_dtype at_dtype, int64_t ldat, const void* At,
                      const csk_solve_opts* o)
 {
@@ -870,9 +952,7 @@ SolvePlan solve_plan(int64_t d, int64_t n, csk_dtype at_dtype, int64_t ldat, con
     const int64_t vec = 16 / (int64_t)dtype_size(at_dtype);
     const bool vec_ok = al16(At) && ((ldat * (int64_t)dtype_size(at_dtype)) % 16 == 0);
     p.vw = vec_ok ? (int)vec : 1;
-    // Lanes per row: the fewest of {4, 16, 64} whose chunk covers the row.
-    const int64_t per_lane = (int64_t)p.vw * chunk_k_of(at_dtype);
-    p.lpr = (4 * per_lane >= n) ? 4 : (16 * per_lane >= n) ? 16 : 64;
+    p.lpr = pick_lpr(n, (int64_t)p.vw * chunk_k_of(at_dtype));
     int grid;
     if (o && o->single_wg == 1) grid = 1;
     else if (o && o->grid > 0) grid = o->grid;
@@ -905,8 +985,7 @@ csk_status solve_run(const SolveSys& sys_in, csk_dtype at_dtype, const csk_solve
     // The exact FP64 product shares the vector path, so At64 must qualify too.
     if (plan.vw > 1 && (!al16(S.At64) || (S.ldat64 * 8) % 16 != 0)) {
         plan.vw = 1;
-        const int64_t per_lane = chunk_k_of(at_dtype);
-        plan.lpr = (4 * per_lane >= S.n) ? 4 : (16 * per_lane >= S.n) ? 16 : 64;
+        plan.lpr = pick_lpr(S.n, chunk_k_of(at_dtype));
     }
     S.npad = (int32_t)solve_npad(S.n, at_dtype, plan.lpr, plan.vw > 1);
 
