@@ -139,7 +139,7 @@ __device__ __forceinline__ GridRed block_red1(GridRed v, GridRed* slots)
 template <int NT>
 __device__ __forceinline__ GridRed block_red(GridRed v, GridRed* slots)
 {
-    v = wave_red(v);
+    v = wave_red_dpp(v);
     if ((threadIdx.x & (kWave - 1)) == 0) slots[threadIdx.x / kWave] = v;
     __syncthreads();
     GridRed t = slots[0];
@@ -149,37 +149,46 @@ __device__ __forceinline__ GridRed block_red(GridRed v, GridRed* slots)
     return t;
 }
 
-// Grid barrier: arrival counter (zeroed before launch) with release/acquire
-// at device scope; epoch e waits for e * G arrivals.  The spin is bounded,
-// so a kernel always terminates; false means the wait timed out.
-// Only thread 0 performs the device-scope release, and a workgroup barrier
-// by itself does not wait for other wavefronts' stores to complete.  When
-// wavefronts other than the one holding thread 0 wrote data that other
-// workgroups read after the barrier, ALL_WAVES makes every wavefront wait
-// for its stores before the workgroup barrier, so the release covers them.
-template <bool ALL_WAVES = false>
-__device__ __forceinline__ bool grid_barrier(uint32_t* ctr, uint32_t target, uint32_t* s_ok)
+// Device-coherent accesses ("sc1": coherent across the chip's L2 slices,
+// without writing back or invalidating them).  Data that one workgroup
+// writes and another reads while the kernel runs moves only through these.
+template <class T> __device__ __forceinline__ void coh_store(T* p, T v)
 {
-    if constexpr (ALL_WAVES) {
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        uint32_t ok = 1u;
-        __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T> __device__ __forceinline__ T coh_load(const T* p)
+{
+    return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid barrier for kernels whose cross-workgroup data moves only through
+// coh_store / coh_load.  Every wavefront waits for its own stores to be
+// acknowledged; then workgroup wg stores the epoch in its own flag and all
+// workgroups poll all G flags in parallel (one request per flag and round).
+// There is no shared atomic counter, whose G serialized updates would
+// dominate, and no fence: the L2 slices keep their (read-only) lines, where
+// a release/acquire pair would write them back and invalidate them.  Flags
+// start at zero and epochs count up from 1; the spin is bounded (false:
+// timed out).
+__device__ __forceinline__ bool grid_barrier_flags(uint32_t* flags, int wg, int G, uint32_t epoch, uint32_t* s_ok)
+{
+    __builtin_amdgcn_s_waitcnt(0);
+    if (threadIdx.x == 0) *s_ok = 1u;
+    __syncthreads();
+    if (threadIdx.x == 0) coh_store(&flags[wg], epoch);
+    for (int w = threadIdx.x; w < G; w += blockDim.x) {
         uint32_t spins = 0;
-        while (static_cast<int32_t>(__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
-            __builtin_amdgcn_s_sleep(1);
+        while (static_cast<int32_t>(coh_load(&flags[w]) - epoch) < 0) {
+            __builtin_amdgcn_s_sleep(2);
             if (++spins > kSpinLimit) {
-                ok = 0u;
+                *s_ok = 0u;
                 break;
             }
         }
-        *s_ok = ok;
     }
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return *s_ok != 0u;
 }
+
 
 }  // namespace csk

@@ -2,7 +2,10 @@
 // run independently for every column j of Bt, with all columns' residuals
 // formed together on the matrix cores.
 //
-// Per iteration (one persistent cooperative launch, two grid barriers):
+// Per iteration (one persistent cooperative launch, two grid barriers).
+// Data that crosses workgroups (candidates, Delta, its scale, X for the
+// refresh) moves through device-coherent accesses, so the barriers need no
+// cache write-back or invalidation and the read-only operands stay in L2:
 //   1. residual block R = R_ref - At_lp * Delta for the workgroup's rows and
 //      128 columns, with Delta = X - X_ref rounded to BF16/FP16 and the
 //      product on v_mfma_f32_16x16x32 (FP32 accumulation); every
@@ -27,6 +30,10 @@ constexpr int kNT = 512;          // 8 wavefronts
 constexpr int kCols = 128;        // columns per workgroup (one 16-column tile per wavefront)
 constexpr int kMaxRT = 8;         // 16-row tiles per workgroup
 constexpr int kMaxOwned = 8;      // columns owned (reduced and projected) per workgroup
+constexpr int kMaxGrid = 4096;    // workgroups (arrival flags of the grid barrier)
+// k-steps of the B operand loaded together (fewer when many row tiles
+// already hold registers)
+template <int RT> constexpr int kb_batch() { return RT <= 5 ? 8 : 4; }
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
@@ -34,7 +41,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 struct CandRec {
-    double score, r, r2;
+    double score, alpha, r2;  // alpha = r / ||At64^(i)||^2 of the best row
     uint32_t idx, flags;
 };
 
@@ -52,7 +59,7 @@ struct MCtl {
     const double* colbt2;     // Rpad: ||Bt[:, j]||^2
     double* dinv;             // Rpad: 2^-e_j, Delta[:, j] is stored as Delta * 2^e_j
     csk_solve_result* res;    // R
-    uint32_t* barrier;
+    uint32_t* flags;          // kMaxGrid arrival flags of the grid barrier, zero at launch
     uint32_t* active;
     int32_t* cancel_seen;
     const volatile int32_t* cancel;
@@ -60,29 +67,42 @@ struct MCtl {
     int64_t maxit;
     int64_t lda64, ldbt;
     int32_t d, n, npad, R, Rpad, RB, CB, refresh_every, check_every, stop_mode;
+    int32_t a_lds;            // 1: the workgroup's rows of Alp are staged in LDS
+    int32_t a_stride;         // LDS row stride of that tile (npad + 8: no bank conflicts)
 };
 
 template <class Tag> struct Mfma;
 template <> struct Mfma<tag_bf16> {
-    __device__ static f32x4 run(const uint16_t* a, const uint16_t* b, f32x4 c)
+    __device__ static f32x4 run(const uint16_t* a, const uint4& b, f32x4 c)
     {
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const bf16x8*>(a),
-                                                       *reinterpret_cast<const bf16x8*>(b), c, 0, 0, 0);
+                                                       __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
     }
     __device__ static uint16_t round(double v) { return f64_to_bf16_bits(v); }
 };
 template <> struct Mfma<tag_f16> {
-    __device__ static f32x4 run(const uint16_t* a, const uint16_t* b, f32x4 c)
+    __device__ static f32x4 run(const uint16_t* a, const uint4& b, f32x4 c)
     {
         return __builtin_amdgcn_mfma_f32_16x16x32_f16(*reinterpret_cast<const f16x8*>(a),
-                                                      *reinterpret_cast<const f16x8*>(b), c, 0, 0, 0);
+                                                      __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
     }
     __device__ static uint16_t round(double v) { return f64_to_f16_bits(v); }
 };
 
+// 16 bytes written by other workgroups during the kernel (two coherent
+// 8-byte loads).
+__device__ __forceinline__ uint4 coh_load16(const uint16_t* p)
+{
+    const uint64_t lo = coh_load(reinterpret_cast<const uint64_t*>(p));
+    const uint64_t hi = coh_load(reinterpret_cast<const uint64_t*>(p) + 1);
+    return make_uint4(static_cast<uint32_t>(lo), static_cast<uint32_t>(lo >> 32), static_cast<uint32_t>(hi),
+                      static_cast<uint32_t>(hi >> 32));
+}
+
 template <class Tag, int RT>
 __global__ __launch_bounds__(kNT) void k_mrhs(MCtl C)
 {
+    constexpr int kKB = kb_batch<RT>();
     __shared__ GridRed slots[kNT / kWave];
     __shared__ uint32_t s_ok;
     __shared__ double s_nu2[RT * 16];
@@ -105,6 +125,17 @@ __global__ __launch_bounds__(kNT) void k_mrhs(MCtl C)
     const int arow_perm = 4 * (lc & 3) + (lc >> 2);
     const int n = C.n, d = C.d, R = C.R;
 
+    // The low-precision rows of this workgroup stay in LDS for the whole
+    // solve when they fit (read-only: Alp was padded before the launch).
+    extern __shared__ __align__(16) uint16_t sA[];
+    if (C.a_lds) {
+        const int chunks = C.npad / 8;
+        for (int e = tid; e < RT * 16 * chunks; e += kNT) {
+            const int r = e / chunks, c8 = (e - r * chunks) * 8;
+            *reinterpret_cast<uint4*>(sA + r * C.a_stride + c8) =
+                *reinterpret_cast<const uint4*>(C.Alp + (int64_t)(row0 + r) * C.npad + c8);
+        }
+    }
     for (int i = tid; i < RT * 16; i += kNT) s_nu2[i] = (row0 + i < d) ? C.nu2[row0 + i] : 0.0;
     if (tid < kMaxOwned) {
         s_done[tid] = 0;
@@ -125,15 +156,27 @@ __global__ __launch_bounds__(kNT) void k_mrhs(MCtl C)
             f64x4 acc64[RT];
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt) acc64[rt] = f64x4{0.0, 0.0, 0.0, 0.0};
-            for (int kk = 0; kk < n; kk += 4) {
-                const int kq = kk + lg;
-                const double bv = C.XT[(int64_t)mycol * C.npad + kq];
+            // both operands of a batch of k-steps are loaded before its
+            // products (X coherent, At64 read-only), one round trip a batch
+            constexpr int kKB64 = 2;
+            for (int kb = 0; kb < n; kb += 4 * kKB64) {
+                double bq[kKB64];
+                double aq[kKB64][RT];
 #pragma unroll
-                for (int rt = 0; rt < RT; ++rt) {
-                    const int row = row0 + rt * 16 + arow_perm;
-                    const double av = (row < d && kq < n) ? C.A64[(int64_t)row * C.lda64 + kq] : 0.0;
-                    acc64[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc64[rt], 0, 0, 0);
+                for (int t = 0; t < kKB64; ++t) {
+                    const int kq = kb + 4 * t + lg;
+                    bq[t] = (kq < C.npad) ? coh_load(&C.XT[(int64_t)mycol * C.npad + kq]) : 0.0;
+#pragma unroll
+                    for (int rt = 0; rt < RT; ++rt) {
+                        const int row = row0 + rt * 16 + arow_perm;
+                        aq[t][rt] = (row < d && kq < n) ? C.A64[(int64_t)row * C.lda64 + kq] : 0.0;
+                    }
                 }
+#pragma unroll
+                for (int t = 0; t < kKB64; ++t)
+#pragma unroll
+                    for (int rt = 0; rt < RT; ++rt)
+                        acc64[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(aq[t][rt], bq[t], acc64[rt], 0, 0, 0);
             }
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt)
@@ -145,18 +188,45 @@ __global__ __launch_bounds__(kNT) void k_mrhs(MCtl C)
             k_ref = k;
             ++nref;
         } else {
+            // Delta's fragments are coherent loads, which the compiler keeps
+            // in program order: issue kKB k-steps of them at once, then their
+            // products, so a batch costs one round trip rather than kKB.
             const uint16_t* bcol = C.DT + (int64_t)mycol * C.npad + lg * 8;
-            for (int kk = 0; kk < C.npad; kk += 32) {
+            for (int kb = 0; kb < C.npad; kb += 32 * kKB) {
+                uint4 bq[kKB];
 #pragma unroll
-                for (int rt = 0; rt < RT; ++rt) {
-                    const uint16_t* arow = C.Alp + (int64_t)(row0 + rt * 16 + lc) * C.npad + lg * 8 + kk;
-                    acc[rt] = Mfma<Tag>::run(arow, bcol + kk, acc[rt]);
+                for (int t = 0; t < kKB; ++t)
+                    bq[t] = (kb + 32 * t < C.npad) ? coh_load16(bcol + kb + 32 * t) : make_uint4(0, 0, 0, 0);
+                if (C.a_lds) {
+#pragma unroll
+                    for (int t = 0; t < kKB; ++t) {
+                        const int kk = kb + 32 * t;
+                        if (kk < C.npad) {
+#pragma unroll
+                            for (int rt = 0; rt < RT; ++rt)
+                                acc[rt] = Mfma<Tag>::run(sA + (rt * 16 + lc) * C.a_stride + lg * 8 + kk, bq[t],
+                                                         acc[rt]);
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int t = 0; t < kKB; ++t) {
+                        const int kk = kb + 32 * t;
+                        if (kk < C.npad) {
+#pragma unroll
+                            for (int rt = 0; rt < RT; ++rt) {
+                                const uint16_t* arow =
+                                    C.Alp + (int64_t)(row0 + rt * 16 + lc) * C.npad + lg * 8 + kk;
+                                acc[rt] = Mfma<Tag>::run(arow, bq[t], acc[rt]);
+                            }
+                        }
+                    }
                 }
             }
         }
 
         // Delta of this column is stored scaled by an exact power of two
-        const double dinv = (mycol < R) ? C.dinv[mycol] : 1.0;
+        const double dinv = (mycol < R) ? coh_load(&C.dinv[mycol]) : 1.0;
         // best row of this block for column mycol
         GridRed cv = red_identity();
         if (mycol < R) {
@@ -175,7 +245,7 @@ __global__ __launch_bounds__(kNT) void k_mrhs(MCtl C)
                             if (!isfinite(score)) cv.flags |= kFlagNonfinite;
                             else if (cand_better(score, (uint32_t)row, cv.score, cv.idx)) {
                                 cv.score = score;
-                                cv.r = r;
+                                cv.r = r / nn;  // the step length alpha
                                 cv.idx = (uint32_t)row;
                             }
                         } else if (isnan(nn)) {
@@ -197,18 +267,16 @@ __global__ __launch_bounds__(kNT) void k_mrhs(MCtl C)
             cv = red_combine(cv, o);
         }
         if (lg == 0 && mycol < R) {
-            CandRec c;
-            c.score = cv.score;
-            c.r = cv.r;
-            c.r2 = cv.r2;
-            c.idx = cv.idx;
-            c.flags = cv.flags;
-            C.cand[(int64_t)rb * C.Rpad + mycol] = c;
+            CandRec* c = &C.cand[(int64_t)rb * C.Rpad + mycol];
+            coh_store(&c->score, cv.score);
+            coh_store(&c->alpha, cv.r);
+            coh_store(&c->r2, cv.r2);
+            coh_store(reinterpret_cast<uint64_t*>(&c->idx), (static_cast<uint64_t>(cv.flags) << 32) | cv.idx);
         }
         if (blockIdx.x == 0 && tid == 0 && C.cancel && (k % C.check_every) == 0 && *C.cancel != 0)
-            *C.cancel_seen = 1;
+            coh_store(C.cancel_seen, int32_t(1));
         ++epoch;
-        bool ok = grid_barrier<true>(C.barrier, epoch * (uint32_t)G, &s_ok);
+        bool ok = grid_barrier_flags(C.flags, blockIdx.x, G, epoch, &s_ok);
 
         // owner phase: column j belongs to workgroup j mod G
         const int32_t cancelled = __hip_atomic_load(C.cancel_seen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -217,20 +285,21 @@ __global__ __launch_bounds__(kNT) void k_mrhs(MCtl C)
             if (s_done[t]) continue;
             GridRed v = red_identity();
             for (int b = tid; b < C.RB; b += kNT) {
-                const CandRec c = C.cand[(int64_t)b * C.Rpad + j];
+                const CandRec* c = &C.cand[(int64_t)b * C.Rpad + j];
                 GridRed o;
-                o.score = c.score;
-                o.r = c.r;
-                o.r2 = c.r2;
+                o.score = coh_load(&c->score);
+                o.r = coh_load(&c->alpha);
+                o.r2 = coh_load(&c->r2);
                 o.e2 = 0.0;
-                o.idx = c.idx;
-                o.flags = c.flags;
+                const uint64_t w = coh_load(reinterpret_cast<const uint64_t*>(&c->idx));
+                o.idx = static_cast<uint32_t>(w);
+                o.flags = static_cast<uint32_t>(w >> 32);
                 v = red_combine(v, o);
             }
             double* xj = C.XT + (int64_t)j * C.npad;
             if (C.XuT)
                 for (int q = tid; q < n; q += kNT) {
-                    const double e = xj[q] - C.XuT[(int64_t)j * C.npad + q];
+                    const double e = coh_load(&xj[q]) - C.XuT[(int64_t)j * C.npad + q];
                     v.e2 += e * e;
                 }
             const GridRed tot = block_red<kNT>(v, slots);
@@ -266,39 +335,49 @@ __global__ __launch_bounds__(kNT) void k_mrhs(MCtl C)
                 __syncthreads();
                 continue;
             }
-            const double alpha = tot.r / C.nu2[tot.idx];
+            const double alpha = tot.r;
             const double* arow = C.A64 + (int64_t)tot.idx * C.lda64;
             // At a refresh Delta restarts at alpha * a; scale it by 2^e with
             // ||alpha a|| * 2^e in [16, 32) so the 16-bit operand keeps its
             // precision (FP16's exponent range is narrow) as x converges.
             if (refresh) {
-                const double v = fabs(alpha) * sqrt(C.nu2[tot.idx]);
+                const double v = sqrt(tot.score);  // |alpha| ||At64^(i)|| = |r| / ||At64^(i)||
                 int e = 0;
                 if (v > 0.0 && isfinite(v)) e = 4 - ilogb(v);
                 e = e < -960 ? -960 : (e > 960 ? 960 : e);
-                if (tid == 0) C.dinv[j] = ldexp(1.0, -e);
+                if (tid == 0) coh_store(&C.dinv[j], ldexp(1.0, -e));
                 s_scale[t] = ldexp(1.0, e);
             }
             __syncthreads();
             const double dscale = s_scale[t];
             double* xr = C.XrT + (int64_t)j * C.npad;
             uint16_t* dj = C.DT + (int64_t)j * C.npad;
-            for (int q = tid; q < n; q += kNT) {
-                const double x = xj[q];
-                double base;
-                if (refresh) {
-                    xr[q] = x;
-                    base = x;
-                } else {
-                    base = xr[q];
+            // four columns per thread: Delta leaves in one coherent 8-byte
+            // store (columns n .. npad stay zero)
+            for (int q0 = tid * 4; q0 < C.npad; q0 += kNT * 4) {
+                uint64_t packed = 0;
+#pragma unroll
+                for (int e4 = 0; e4 < 4; ++e4) {
+                    const int q = q0 + e4;
+                    if (q < n) {
+                        const double x = coh_load(&xj[q]);
+                        double base;
+                        if (refresh) {
+                            xr[q] = x;
+                            base = x;
+                        } else {
+                            base = xr[q];
+                        }
+                        const double xn = x + alpha * arow[q];
+                        coh_store(&xj[q], xn);
+                        packed |= static_cast<uint64_t>(Mfma<Tag>::round((xn - base) * dscale)) << (16 * e4);
+                    }
                 }
-                const double xn = x + alpha * arow[q];
-                xj[q] = xn;
-                dj[q] = Mfma<Tag>::round((xn - base) * dscale);
+                coh_store(reinterpret_cast<uint64_t*>(dj + q0), packed);
             }
         }
         ++epoch;
-        ok = grid_barrier<true>(C.barrier, epoch * (uint32_t)G, &s_ok) && ok;
+        ok = grid_barrier_flags(C.flags, blockIdx.x, G, epoch, &s_ok) && ok;
         const uint32_t left = __hip_atomic_load(C.active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (left == 0u || !ok) break;
     }
@@ -358,20 +437,21 @@ __global__ __launch_bounds__(256) void k_col_norms(const double* __restrict__ Xu
     }
 }
 
-__global__ void k_init_counters(uint32_t* barrier, uint32_t* active, int32_t* cancel_seen, int R,
+__global__ void k_init_counters(uint32_t* flags, uint32_t* active, int32_t* cancel_seen, int R,
                                 CandRec* cand, int64_t ncand, double* dinv, int Rpad)
 {
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < Rpad; e += (int64_t)gridDim.x * blockDim.x)
         dinv[e] = 1.0;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < kMaxGrid; e += (int64_t)gridDim.x * blockDim.x)
+        flags[e] = 0u;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        *barrier = 0u;
         *active = (uint32_t)R;
         *cancel_seen = 0;
     }
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ncand; e += (int64_t)gridDim.x * blockDim.x) {
         CandRec c;
         c.score = 0.0;
-        c.r = 0.0;
+        c.alpha = 0.0;
         c.r2 = 0.0;
         c.idx = kNoRow;
         c.flags = 0u;
@@ -414,18 +494,27 @@ int grid_for(int64_t items, int cap)
 }
 
 template <class Tag, int RT>
-csk_status launch_mrhs(const MCtl& C, int G, hipStream_t st)
+csk_status launch_mrhs(const MCtl& C_in, int G, hipStream_t st)
 {
     auto kern = k_mrhs<Tag, RT>;
+    MCtl arg = C_in;
+    // stage the workgroup's rows of Alp in LDS when they fit beside the
+    // kernel's static LDS (about 2 KB)
+    arg.a_stride = arg.npad + 8;
+    size_t shm = (size_t)RT * 16 * arg.a_stride * sizeof(uint16_t);
+    arg.a_lds = shm + 4096 <= (size_t)device_max_lds() ? 1 : 0;
+    if (!arg.a_lds) shm = 0;
+    CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)shm));
     int per_cu = 0;
-    CSK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern), kNT, 0));
+    CSK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern), kNT, shm));
     if (G > per_cu * device_cu_count()) {
         set_error("multi-RHS grid of %d workgroups exceeds the %d co-resident ones", G, per_cu * device_cu_count());
         return CSK_ERR_UNSUPPORTED;
     }
-    MCtl arg = C;
     void* args[] = {&arg};
-    CSK_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(G), dim3(kNT), args, 0, st));
+    CSK_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(G), dim3(kNT), args,
+                                       (unsigned)shm, st));
     return CSK_OK;
 }
 
@@ -461,6 +550,7 @@ size_t mrhs_ws_bytes(int64_t d, int64_t n, int64_t nrhs)
     c.take<double>(g.Rpad);
     c.take<double>(g.Rpad);
     c.take<uint32_t>(64);
+    c.take<uint32_t>(kMaxGrid);
     return c.bytes();
 }
 
@@ -479,6 +569,10 @@ csk_status mrhs_run(const void* At_lp, csk_dtype lp_dtype, int64_t ldat_lp, cons
         set_error("multi-RHS: d=%lld needs %d row tiles per workgroup (max %d)", (long long)d, g.RT, kMaxRT);
         return CSK_ERR_UNSUPPORTED;
     }
+    if (g.RB * g.CB > kMaxGrid) {
+        set_error("multi-RHS: %d workgroups exceed the %d barrier flags", g.RB * g.CB, kMaxGrid);
+        return CSK_ERR_UNSUPPORTED;
+    }
     Carve c(ws);
     MCtl C{};
     uint16_t* alp = c.take<uint16_t>((size_t)g.rows_pad * g.npad);
@@ -491,6 +585,7 @@ csk_status mrhs_run(const void* At_lp, csk_dtype lp_dtype, int64_t ldat_lp, cons
     double* colbt2 = c.take<double>(g.Rpad);
     C.dinv = c.take<double>(g.Rpad);
     uint32_t* ctr = c.take<uint32_t>(64);
+    uint32_t* flags = c.take<uint32_t>(kMaxGrid);
     if (c.bytes() > ws_bytes) {
         set_error("multi-RHS workspace too small: need %zu bytes, got %zu", c.bytes(), ws_bytes);
         return CSK_ERR_WORKSPACE;
@@ -505,7 +600,7 @@ csk_status mrhs_run(const void* At_lp, csk_dtype lp_dtype, int64_t ldat_lp, cons
     C.colref2 = colref2;
     C.colbt2 = colbt2;
     C.res = res;
-    C.barrier = ctr;
+    C.flags = flags;
     C.active = ctr + 1;
     C.cancel_seen = reinterpret_cast<int32_t*>(ctr + 2);
     C.cancel = o->cancel;
@@ -530,7 +625,7 @@ csk_status mrhs_run(const void* At_lp, csk_dtype lp_dtype, int64_t ldat_lp, cons
     CSK_LAUNCH_CHECK("k_init_cols");
     k_col_norms<<<(int)nrhs, 256, 0, st>>>(C.XuT, g.npad, (int)n, Bt, ldbt, (int)d, colref2, colbt2);
     CSK_LAUNCH_CHECK("k_col_norms");
-    k_init_counters<<<grid_for((int64_t)g.RB * g.Rpad, 1024), 256, 0, st>>>(C.barrier, C.active, C.cancel_seen,
+    k_init_counters<<<grid_for((int64_t)g.RB * g.Rpad, 1024), 256, 0, st>>>(C.flags, C.active, C.cancel_seen,
                                                                               (int)nrhs, C.cand,
                                                                               (int64_t)g.RB * g.Rpad, C.dinv,
                                                                               g.Rpad);

@@ -410,14 +410,6 @@ __device__ void fill_resident(const typename Elem<Tag>::S* __restrict__ A, int64
 // and no cache write-back or invalidation (the workgroup's rows of At stay
 // in L2).  Payload: score, alpha, the stop measure (||x - x_ref||^2 part or
 // ||r||^2 part), row index, flags.
-template <class T> __device__ __forceinline__ void coh_store(T* p, T v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <class T> __device__ __forceinline__ T coh_load(const T* p)
-{
-    return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 __device__ __forceinline__ double join_f64(uint64_t lo, uint64_t hi)
 {
