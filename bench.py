@@ -212,18 +212,28 @@ def batched_workload(P, W, torch):
         s = W.gaussian(sh.m, sh.n, sh.seed, dtype=torch.float32, device=dev)
         systems.append(dict(A=s.A, b=s.b, d=sh.d, seed=sh.sketch_seed, x_ref=s.x_star))
     torch.cuda.synchronize()
-    P.csk_solve_batched(systems[:4], lp_dtype=torch.float32, tol=c["tol"], maxit=c["maxit"])
-    t, (xs, raw, ws) = timed(lambda: P.csk_solve_batched(systems, lp_dtype=torch.float32, tol=c["tol"],
-                                                          maxit=c["maxit"], sync=False))
-    res = P.parse_results(raw)
-    ok = sum(1 for r in res if r[1] == P.CSK_OK)
-    worst = max(((x - sd["x_ref"]).norm() / sd["x_ref"].norm()).item() for x, sd in zip(xs, systems))
     a_bytes = sum(sh.m * sh.n * 4 for sh in shapes)
-    log(f"[bench] batched: {t * 1e3:.1f} ms for {len(shapes)} systems, {ok} converged, worst rel {worst:.2e}")
+    out = dict(systems=len(shapes), a_bytes=a_bytes, redraws=redraws)
+    # the sketch is stored in FP32 and, separately, in BF16 (half the bytes
+    # per inner iteration); both refresh in FP64
+    for name, lp in (("f32", torch.float32), ("bf16", torch.bfloat16)):
+        P.csk_solve_batched(systems[:4], lp_dtype=lp, tol=c["tol"], maxit=c["maxit"])
+        t, (xs, raw, ws) = timed(lambda: P.csk_solve_batched(systems, lp_dtype=lp, tol=c["tol"],
+                                                              maxit=c["maxit"], sync=False))
+        res = P.parse_results(raw)
+        ok = sum(1 for r in res if r[1] == P.CSK_OK)
+        worst = max(((x - sd["x_ref"]).norm() / sd["x_ref"].norm()).item() for x, sd in zip(xs, systems))
+        log(f"[bench] batched {name}: {t * 1e3:.1f} ms for {len(shapes)} systems, {ok} converged, "
+            f"worst rel {worst:.2e}")
+        out[name] = dict(time_s=t, converged=ok, systems_per_s=len(shapes) / t, worst_relerr=worst,
+                         total_iters=int(sum(r[0] for r in res)))
+        del xs, raw, ws
+    out["time_s"] = out["f32"]["time_s"]
+    out["systems_per_s"] = out["f32"]["systems_per_s"]
+    out["bf16_speedup_vs_f32"] = out["f32"]["time_s"] / out["bf16"]["time_s"]
     del systems
     torch.cuda.empty_cache()
-    return dict(time_s=t, systems=len(shapes), converged=ok, systems_per_s=len(shapes) / t, worst_relerr=worst,
-                total_iters=int(sum(r[0] for r in res)), a_bytes=a_bytes, redraws=redraws)
+    return out
 
 
 def mrhs_workload(P, W, torch):

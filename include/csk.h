@@ -207,6 +207,35 @@ csk_status csk_solve(const void* At, csk_dtype at_dtype, int64_t ldat,
                      const csk_solve_opts* opts /*host*/, csk_solve_result* res,
                      void* ws, size_t ws_bytes, void* stream);
 
+/* ---- Tuning of the persistent solve's launch shape ---------------------- *
+ * csk_tune_solve times trial_iters MWRK iterations (no convergence test) of
+ * each candidate launch shape on the given system -- one workgroup while the
+ * matrix is small, 64, 128, 192 and one workgroup per CU, each with the
+ * lanes-per-row splits whose padded row length is within 25% of the best --
+ * and records the fastest in a process-wide cache keyed by (device, d, n,
+ * at_dtype, vector rows).  Every later csk_solve of that key that leaves the
+ * shape to the library (opts->grid == 0, opts->single_wg == -1) uses it.
+ * The timing synchronizes the stream; the workspace holds the trial runs'
+ * x and result (csk_tune_solve_workspace_size).  Arguments as csk_solve.
+ * csk_tune_lookup reads the cache (grid 0: no entry; vector_rows: whether
+ * the rows are 16-byte vectors, i.e. At 16-byte aligned and ldat * element
+ * size a multiple of 16); csk_tune_clear empties it.  The cache is guarded
+ * by a mutex; all other calls stay reentrant.                               */
+typedef struct csk_tune_entry {
+    int32_t grid;            /* workgroups (1: single-workgroup kernel)          */
+    int32_t lanes_per_row;   /* 4, 16 or 64                                      */
+    double us_per_iter;      /* measured microseconds per iteration              */
+} csk_tune_entry;
+csk_status csk_tune_solve_workspace_size(int64_t d, int64_t n, csk_dtype at_dtype, size_t* bytes /*host*/);
+csk_status csk_tune_solve(const void* At, csk_dtype at_dtype, int64_t ldat,
+                          const double* At64, int64_t ldat64,
+                          int64_t d, int64_t n, const double* bt, const double* nu2,
+                          int32_t trial_iters, csk_tune_entry* best /*host, nullable*/,
+                          void* ws, size_t ws_bytes, void* stream);
+csk_status csk_tune_lookup(int64_t d, int64_t n, csk_dtype at_dtype, int32_t vector_rows,
+                           csk_tune_entry* out /*host*/);
+void csk_tune_clear(void);
+
 /* ---- A8: many independent systems, sketch + solve in one pass ---------- *
  * Each descriptor (host array) names one system's device buffers.  A is
  * a_dtype (F64 or F32); the solve runs in lp_dtype (F64 = plain, else mixed

@@ -10,7 +10,8 @@ import importlib
 
 _BINDING_NAMES = {
     "CskError", "SketchOut", "SolveResult", "csk_hash", "csk_sketch", "csk_sketch_csr", "csk_solve",
-    "csk_solve_batched", "csk_solve_mrhs", "csk_status_string", "parse_results", "lib",
+    "csk_solve_batched", "csk_solve_mrhs", "csk_tune_solve", "csk_tune_lookup", "csk_tune_clear",
+    "csk_status_string", "parse_results", "lib",
     "CSK_OK", "CSK_NOT_CONVERGED", "CSK_ERR_INVALID_ARG", "CSK_ERR_UNSUPPORTED", "CSK_ERR_DEVICE",
     "CSK_ERR_WORKSPACE", "CSK_ERR_NONFINITE", "CSK_ERR_DEGENERATE", "CSK_CANCELLED",
     "CSK_F64", "CSK_F32", "CSK_F16", "CSK_BF16", "CSK_STOP_REL_ERR", "CSK_STOP_REL_RESID",

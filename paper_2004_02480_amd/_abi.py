@@ -37,6 +37,7 @@ EXPORTED = [
     "csk_solve_workspace_size", "csk_solve",
     "csk_solve_batched_workspace_size", "csk_solve_batched",
     "csk_solve_mrhs_workspace_size", "csk_solve_mrhs",
+    "csk_tune_solve_workspace_size", "csk_tune_solve", "csk_tune_lookup", "csk_tune_clear",
 ]
 
 
@@ -66,6 +67,14 @@ class SystemDesc(ctypes.Structure):
         ("lda", ctypes.c_int64),
         ("d", ctypes.c_int64),
         ("seed", ctypes.c_uint64),
+    ]
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [
+        ("grid", ctypes.c_int32),
+        ("lanes_per_row", ctypes.c_int32),
+        ("us_per_iter", ctypes.c_double),
     ]
 
 
@@ -120,4 +129,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.csk_solve_mrhs.restype = I32
     lib.csk_solve_mrhs.argtypes = [P, I32, I64, P, I64, I64, I64, P, I64, I64, P,
                                    P, P, I64, P, I64, ctypes.POINTER(SolveOpts), P, P, SZ, P]
+    lib.csk_tune_solve_workspace_size.restype = I32
+    lib.csk_tune_solve_workspace_size.argtypes = [I64, I64, I32, PSZ]
+    lib.csk_tune_solve.restype = I32
+    lib.csk_tune_solve.argtypes = [P, I32, I64, P, I64, I64, I64, P, P, I32, ctypes.POINTER(TuneEntry), P, SZ, P]
+    lib.csk_tune_lookup.restype = I32
+    lib.csk_tune_lookup.argtypes = [I64, I64, I32, I32, ctypes.POINTER(TuneEntry)]
+    lib.csk_tune_clear.restype = None
+    lib.csk_tune_clear.argtypes = []
     return lib

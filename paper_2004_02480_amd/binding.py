@@ -25,7 +25,8 @@ from ._abi import (CSK_BF16, CSK_CANCELLED, CSK_ERR_DEGENERATE, CSK_ERR_DEVICE, 
 _lib = _abi.load()
 
 __all__ = ["CskError", "SketchOut", "SolveResult", "csk_hash", "csk_sketch", "csk_sketch_csr",
-           "csk_solve", "csk_solve_batched", "csk_solve_mrhs", "csk_status_string", "lib"]
+           "csk_solve", "csk_solve_batched", "csk_solve_mrhs", "csk_tune_solve", "csk_tune_lookup",
+           "csk_tune_clear", "csk_status_string", "lib"]
 
 lib = _lib
 
@@ -325,3 +326,37 @@ def csk_solve_mrhs(At_lp: torch.Tensor, At64: torch.Tensor, Bt: torch.Tensor, nu
         return X, res
     (stream or torch.cuda.current_stream()).synchronize()
     return X, parse_results(res)
+
+
+def csk_tune_solve(At: torch.Tensor, bt: torch.Tensor, *, At64: Optional[torch.Tensor] = None,
+                   nu2: Optional[torch.Tensor] = None, trial_iters: int = 200, stream=None) -> dict:
+    """Times the persistent solve's candidate launch shapes on (At, bt) and
+    caches the fastest for later default-shaped csk_solve calls of the same
+    shape (synchronizes the stream).  Returns the chosen entry."""
+    _need_cuda(At, "At")
+    ldat = _rowmajor(At, "At")
+    d, n = At.shape
+    at_code = _TORCH_TO_CSK[At.dtype]
+    ldat64 = ldat if At64 is None else _rowmajor(At64, "At64")
+    nbytes = ctypes.c_size_t(0)
+    _check(_lib.csk_tune_solve_workspace_size(d, n, at_code, ctypes.byref(nbytes)), "csk_tune_solve_workspace_size")
+    ws = _workspace(nbytes.value, At.device)
+    best = _abi.TuneEntry()
+    _check(_lib.csk_tune_solve(_ptr(At), at_code, ldat, _ptr(At64), ldat64, d, n, _ptr(bt), _ptr(nu2),
+                               int(trial_iters), ctypes.byref(best), _ptr(ws), ws.numel(), _stream(stream)),
+           "csk_tune_solve")
+    return dict(grid=best.grid, lanes_per_row=best.lanes_per_row, us_per_iter=best.us_per_iter)
+
+
+def csk_tune_lookup(d: int, n: int, dtype: torch.dtype, vector_rows: bool = True) -> dict:
+    """The cached launch shape for (d, n, dtype) on the current device
+    (grid 0: none)."""
+    e = _abi.TuneEntry()
+    _check(_lib.csk_tune_lookup(d, n, _TORCH_TO_CSK[dtype], 1 if vector_rows else 0, ctypes.byref(e)),
+           "csk_tune_lookup")
+    return dict(grid=e.grid, lanes_per_row=e.lanes_per_row, us_per_iter=e.us_per_iter)
+
+
+def csk_tune_clear() -> None:
+    """Empties the cache of tuned launch shapes."""
+    _lib.csk_tune_clear()

@@ -370,6 +370,138 @@ csk_status csk_solve(const void* At, csk_dtype at_dtype, int64_t ldat, const dou
     return solve_run(S, at_dtype, opts, ws, ws_bytes, as_stream(stream));
 }
 
+// ---- tuning of the persistent solve's launch shape --------------------------
+
+csk_status csk_tune_solve_workspace_size(int64_t d, int64_t n, csk_dtype at_dtype, size_t* bytes)
+{
+    g_err[0] = 0;
+    if (!bytes || d < 1 || n < 1 || dtype_size(at_dtype) == 0) { set_error("bad sizes"); return CSK_ERR_INVALID_ARG; }
+    Carve c(nullptr);
+    c.take<char>(solve_ws_bytes(d, n, 65536));
+    c.take<double>(n);                 // x of the trial runs
+    c.take<csk_solve_result>(1);
+    *bytes = c.bytes();
+    return CSK_OK;
+}
+
+csk_status csk_tune_solve(const void* At, csk_dtype at_dtype, int64_t ldat, const double* At64, int64_t ldat64,
+                          int64_t d, int64_t n, const double* bt, const double* nu2, int32_t trial_iters,
+                          csk_tune_entry* best, void* ws, size_t ws_bytes, void* stream)
+{
+    g_err[0] = 0;
+    if (d < 1 || n < 1 || d > INT32_MAX) { set_error("need 1 <= d < 2^31, n >= 1"); return CSK_ERR_INVALID_ARG; }
+    if (n > kMaxN) { set_error("n=%lld exceeds %lld", (long long)n, (long long)kMaxN); return CSK_ERR_UNSUPPORTED; }
+    if (!bt) { set_error("bt is required"); return CSK_ERR_INVALID_ARG; }
+    if (trial_iters < 1 || trial_iters > 1000000) { set_error("trial_iters out of range"); return CSK_ERR_INVALID_ARG; }
+    if (at_dtype == CSK_F64) {
+        if (!At && !At64) { set_error("At is NULL"); return CSK_ERR_INVALID_ARG; }
+        if (!At64) { At64 = static_cast<const double*>(At); ldat64 = ldat; }
+        if (!At) { At = At64; ldat = ldat64; }
+    } else if (lp_ok(at_dtype)) {
+        if (!At || !At64) { set_error("mixed precision needs At and At64"); return CSK_ERR_INVALID_ARG; }
+    } else {
+        set_error("unknown dtype %d", at_dtype);
+        return CSK_ERR_UNSUPPORTED;
+    }
+    if (ldat < n || ldat64 < n) { set_error("leading dimension < n"); return CSK_ERR_INVALID_ARG; }
+    size_t need = 0;
+    csk_tune_solve_workspace_size(d, n, at_dtype, &need);
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u)) { set_error("workspace NULL or unaligned"); return CSK_ERR_INVALID_ARG; }
+    if (ws_bytes < need) { set_error("workspace: need %zu bytes, got %zu", need, ws_bytes); return CSK_ERR_WORKSPACE; }
+    Carve c(ws);
+    void* sws = c.take<char>(solve_ws_bytes(d, n, 65536));
+    double* x = c.take<double>(n);
+    csk_solve_result* res = c.take<csk_solve_result>(1);
+    hipStream_t stm = as_stream(stream);
+
+    // Candidates: one workgroup (while the matrix is small), then 64, 128,
+    // 192 and one per CU, each with the lanes-per-row splits whose padded
+    // row length is within 25% of the best.
+    const int cus = device_cu_count();
+    const int64_t gmax = std::min<int64_t>(cus, std::max<int64_t>(1, (d + 15) / 16));
+    std::vector<int> grids;
+    if (d * n * (int64_t)dtype_size(at_dtype) <= (int64_t)(4 << 20)) grids.push_back(1);
+    for (int g : {64, 128, 192, cus})
+        if (g >= 2 && g <= gmax && std::find(grids.begin(), grids.end(), g) == grids.end()) grids.push_back(g);
+    if (grids.empty()) grids.push_back((int)std::max<int64_t>(1, gmax));
+    const int vw = solve_vw(at_dtype, ldat, At);
+    const int vw_eff = (vw > 1 && (reinterpret_cast<uintptr_t>(At64) & 15u) == 0 && (ldat64 * 8) % 16 == 0) ? vw : 1;
+    const int64_t per_lane = (int64_t)vw_eff * chunk_k_of(at_dtype);
+    int64_t best_cover = INT64_MAX;
+    for (int l : {64, 16, 4}) best_cover = std::min(best_cover, (n + l * per_lane - 1) / (l * per_lane) * l * per_lane);
+    std::vector<int> lprs;
+    for (int l : {64, 16, 4})
+        if ((n + l * per_lane - 1) / (l * per_lane) * l * per_lane * 4 <= best_cover * 5) lprs.push_back(l);
+
+    SolveSys S{};
+    S.At = At;
+    S.At64 = At64;
+    S.bt = bt;
+    S.nu2 = nu2;
+    S.x = x;
+    S.res = res;
+    S.ldat = ldat;
+    S.ldat64 = ldat64;
+    S.d = (int32_t)d;
+    S.n = (int32_t)n;
+    S.stop_mode = CSK_STOP_REL_RESID;
+    csk_solve_opts o{};
+    o.tol = 0.0;  // never converged: every candidate runs trial_iters iterations
+    o.maxit = trial_iters;
+    o.stop_mode = CSK_STOP_REL_RESID;
+    o.refresh_every = 64;
+    o.check_every = 256;
+    o.single_wg = -1;
+
+    hipEvent_t e0, e1;
+    CSK_HIP(hipEventCreate(&e0));
+    CSK_HIP(hipEventCreate(&e1));
+    csk_tune_entry pick{0, 0, 0.0};
+    csk_status r = CSK_OK;
+    for (int g : grids) {
+        for (int l : lprs) {
+            SolvePlan plan;
+            plan.block = 512;
+            plan.vw = vw_eff;
+            plan.lpr = l;
+            plan.grid = g;
+            // one untimed run (first launch of the shape), then one timed
+            r = solve_run(S, at_dtype, &o, sws, solve_ws_bytes(d, n, 65536), stm, &plan);
+            if (r != CSK_OK) break;
+            hipEventRecord(e0, stm);
+            r = solve_run(S, at_dtype, &o, sws, solve_ws_bytes(d, n, 65536), stm, &plan);
+            hipEventRecord(e1, stm);
+            if (r != CSK_OK) break;
+            if (hipEventSynchronize(e1) != hipSuccess) { set_error("tuning run failed"); r = CSK_ERR_DEVICE; break; }
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, e0, e1);
+            const double us = 1e3 * ms / trial_iters;
+            if (pick.grid == 0 || us < pick.us_per_iter) pick = csk_tune_entry{g, l, us};
+        }
+        if (r != CSK_OK) break;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (r != CSK_OK) return r;
+    tune_store(d, n, at_dtype, vw, pick.grid, pick.lanes_per_row, pick.us_per_iter);
+    if (best) *best = pick;
+    return CSK_OK;
+}
+
+csk_status csk_tune_lookup(int64_t d, int64_t n, csk_dtype at_dtype, int32_t vector_rows, csk_tune_entry* out)
+{
+    g_err[0] = 0;
+    if (!out || d < 1 || n < 1 || dtype_size(at_dtype) == 0) { set_error("bad arguments"); return CSK_ERR_INVALID_ARG; }
+    int g = 0, l = 0;
+    double us = 0.0;
+    const int vw = vector_rows ? 16 / (int)dtype_size(at_dtype) : 1;
+    if (tune_lookup(d, n, at_dtype, vw, &g, &l, &us)) *out = csk_tune_entry{g, l, us};
+    else *out = csk_tune_entry{0, 0, 0.0};
+    return CSK_OK;
+}
+
+void csk_tune_clear(void) { tune_clear(); }
+
 csk_status csk_solve_batched_workspace_size(const csk_system_desc* sys, int32_t nsys, csk_dtype a_dtype,
                                             csk_dtype lp_dtype, size_t* bytes)
 {

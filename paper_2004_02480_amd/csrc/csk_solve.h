@@ -37,8 +37,18 @@ int64_t solve_npad(int64_t n, csk_dtype at_dtype, int lpr, bool vec);
 // Lanes per row used by the batched kernel.
 int solve_batch_lpr();
 
+// forced: a launch shape to use instead of the planned one (tuning), or null.
 csk_status solve_run(const SolveSys& sys, csk_dtype at_dtype, const csk_solve_opts* o,
-                     void* ws, size_t ws_bytes, hipStream_t st);
+                     void* ws, size_t ws_bytes, hipStream_t st, const SolvePlan* forced = nullptr);
+
+// Lanes per row with the least padded coverage, vector width of the
+// working matrix, and the cache of tuned launch shapes.
+int pick_lpr(int64_t n, int64_t per_lane);
+int64_t chunk_k_of(csk_dtype t);
+int solve_vw(csk_dtype at_dtype, int64_t ldat, const void* At);
+void tune_store(int64_t d, int64_t n, csk_dtype at_dtype, int vw, int grid, int lpr, double us);
+bool tune_lookup(int64_t d, int64_t n, csk_dtype at_dtype, int vw, int* grid, int* lpr, double* us);
+void tune_clear();
 
 // Batched.  Systems are handed out from an atomic queue in `order` (host,
 // largest estimated work first); a system whose work is well above the

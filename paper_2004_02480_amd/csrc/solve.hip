@@ -31,6 +31,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <type_traits>
 #include <vector>
 
@@ -936,6 +939,61 @@ int pick_lpr(int64_t n, int64_t per_lane)
     return best;
 }
 
+// Tuned launch shapes, keyed by (device, d, n, working dtype, vector path):
+// written by csk_tune_solve, read by every default-shaped solve.
+namespace {
+struct TuneKey {
+    int dev;
+    int64_t d, n;
+    int dtype, vw;
+    bool operator<(const TuneKey& o) const
+    {
+        return std::tie(dev, d, n, dtype, vw) < std::tie(o.dev, o.d, o.n, o.dtype, o.vw);
+    }
+};
+struct TuneVal {
+    int grid, lpr;
+    double us;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tune;
+
+int current_device()
+{
+    int dev = 0;
+    return hipGetDevice(&dev) == hipSuccess ? dev : -1;
+}
+}  // namespace
+
+void tune_store(int64_t d, int64_t n, csk_dtype at_dtype, int vw, int grid, int lpr, double us)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune[TuneKey{current_device(), d, n, (int)at_dtype, vw}] = TuneVal{grid, lpr, us};
+}
+
+bool tune_lookup(int64_t d, int64_t n, csk_dtype at_dtype, int vw, int* grid, int* lpr, double* us)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    const auto it = g_tune.find(TuneKey{current_device(), d, n, (int)at_dtype, vw});
+    if (it == g_tune.end()) return false;
+    *grid = it->second.grid;
+    *lpr = it->second.lpr;
+    if (us) *us = it->second.us;
+    return true;
+}
+
+void tune_clear()
+{
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune.clear();
+}
+
+int solve_vw(csk_dtype at_dtype, int64_t ldat, const void* At)
+{
+    const int64_t vec = 16 / (int64_t)dtype_size(at_dtype);
+    return (al16(At) && ((ldat * (int64_t)dtype_size(at_dtype)) % 16 == 0)) ? (int)vec : 1;
+}
+
 SolvePlan solve_plan(int64_t d, int64_t n, csk_dtype at_dtype, int64_t ldat, const void* At,
                      const csk_solve_opts* o)
 {
@@ -955,6 +1013,14 @@ SolvePlan solve_plan(int64_t d, int64_t n, csk_dtype at_dtype, int64_t ldat, con
         const int64_t bytes = d * n * (int64_t)dtype_size(at_dtype);
         grid = (bytes <= (int64_t)(1 << 20)) ? 1 : std::max(2, std::min<int>(device_cu_count(), (int)((d + 15) / 16)));
     }
+    // a shape from csk_tune_solve replaces the defaults (never an explicit choice)
+    if (o && o->grid == 0 && o->single_wg == -1) {
+        int tg = 0, tl = 0;
+        if (tune_lookup(d, n, at_dtype, p.vw, &tg, &tl, nullptr) && tg >= 1 && tg <= device_cu_count()) {
+            grid = tg;
+            p.lpr = tl;
+        }
+    }
     p.grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, d));
     return p;
 }
@@ -970,10 +1036,10 @@ size_t solve_ws_bytes(int64_t d, int64_t n, int grid)
 }
 
 csk_status solve_run(const SolveSys& sys_in, csk_dtype at_dtype, const csk_solve_opts* o,
-                     void* ws, size_t ws_bytes, hipStream_t st)
+                     void* ws, size_t ws_bytes, hipStream_t st, const SolvePlan* forced)
 {
     SolveSys S = sys_in;
-    SolvePlan plan = solve_plan(S.d, S.n, at_dtype, S.ldat, S.At, o);
+    SolvePlan plan = forced ? *forced : solve_plan(S.d, S.n, at_dtype, S.ldat, S.At, o);
     // The exact FP64 product shares the vector path, so At64 must qualify too.
     if (plan.vw > 1 && (!al16(S.At64) || (S.ldat64 * 8) % 16 != 0)) {
         plan.vw = 1;

@@ -14,7 +14,7 @@ HEADER = os.path.join(ROOT, "include", "csk.h")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:const\s+char\s*\*|csk_status|int32_t)\s+(csk_\w+)\s*\(", text, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:const\s+char\s*\*|csk_status|int32_t|void)\s+(csk_\w+)\s*\(", text, flags=re.M)))
 
 
 @pytest.fixture(scope="module")
@@ -118,3 +118,21 @@ def test_product_does_not_reach_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "csk_oracle" not in text, f
+
+
+def test_tune_cache_lookup_and_clear(lib):
+    # the cache is host state: empty on a fresh process, and lookups of any
+    # key answer "no entry" (grid 0) without touching a device
+    from paper_2004_02480_amd import _abi
+    import ctypes
+    lib.csk_tune_clear()
+    e = _abi.TuneEntry()
+    assert lib.csk_tune_lookup(20000, 1000, _abi.CSK_F64, 1, ctypes.byref(e)) == _abi.CSK_OK
+    assert e.grid == 0 and e.lanes_per_row == 0
+    assert lib.csk_tune_lookup(0, 1000, _abi.CSK_F64, 1, ctypes.byref(e)) == _abi.CSK_ERR_INVALID_ARG
+    nb = ctypes.c_size_t(0)
+    assert lib.csk_tune_solve_workspace_size(1000, 100, _abi.CSK_F64, ctypes.byref(nb)) == _abi.CSK_OK
+    assert nb.value > 1000 * 8
+    # argument errors return before anything is enqueued
+    assert lib.csk_tune_solve(None, _abi.CSK_F64, 100, None, 100, 1000, 100, None, None, 10, None, None, 0,
+                              None) == _abi.CSK_ERR_INVALID_ARG
