@@ -54,11 +54,6 @@ struct tag_f64 { using storage = double; };
 template <class Tag> constexpr int ring_depth() { return std::is_same<Tag, tag_f64>::value ? 3 : std::is_same<Tag, tag_f32>::value ? 2 : 3; }
 template <class Tag> constexpr int chunk_k() { return sizeof(typename Tag::storage) == 2 ? kK16 : kK; }
 
-// One workgroup's published contribution to an iteration (tagged words, see
-// exchange()).
-struct alignas(64) XRec {
-    uint64_t w[8];
-};
 
 struct Ctl {
     double tol2;
@@ -127,39 +122,6 @@ template <class Tag> struct Elem16 {
 };
 template <> struct Elem<tag_f16> : Elem16<tag_f16> {};
 template <> struct Elem<tag_bf16> : Elem16<tag_bf16> {};
-
-// Sum over an aligned group of W lanes (4, 16 or 64), every lane of the
-// group getting the same bits: DPP moves inside quads and 16-lane rows (each
-// step adds two partial sums over disjoint lane sets, a + b on one side and
-// b + a on the other), and for W = 64 the four row sums read from lanes 0,
-// 16, 32, 48 and added in that order.
-template <int CTRL> __device__ __forceinline__ float dpp_move(float v)
-{
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-template <int CTRL> __device__ __forceinline__ double dpp_move(double v)
-{
-    return dpp_f64<CTRL>(v);
-}
-__device__ __forceinline__ float lane_value(float v, int lane)
-{
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
-}
-__device__ __forceinline__ double lane_value(double v, int lane) { return readlane_f64(v, lane); }
-
-template <class T, int W>
-__device__ __forceinline__ T group_sum_t(T v)
-{
-    static_assert(W == 4 || W == 16 || W == 64, "lane group");
-    v = v + dpp_move<0xB1>(v);  // quad_perm [1,0,3,2]
-    v = v + dpp_move<0x4E>(v);  // quad_perm [2,3,0,1]
-    if constexpr (W >= 16) {
-        v = v + dpp_move<0x141>(v);  // row_half_mirror
-        v = v + dpp_move<0x140>(v);  // row_mirror
-    }
-    if constexpr (W == 64) v = ((lane_value(v, 0) + lane_value(v, 16)) + lane_value(v, 32)) + lane_value(v, 48);
-    return v;
-}
 
 // Loads chunk slot `b` (KK vectors of one lane) of (row, seg), with the
 // row's right-hand side and squared norm.  Every load is issued, from a
@@ -403,82 +365,6 @@ __device__ void fill_resident(const typename Elem<Tag>::S* __restrict__ A, int64
     }
 }
 
-// Publish this workgroup's record for iteration k and reduce all G records
-// (grid path).  A record is one 64-byte line of eight 64-bit words, each
-// carrying 32 bits of payload and, in its upper half, the iteration tag
-// k + 1 (tags start at zero; two slots alternate by parity, so a stale word
-// is never mistaken for a fresh one).  Words are written and read with
-// device-coherent 64-bit accesses, so a reader accepts the record once all
-// eight tags match: no acknowledgement wait on the writer, no second read,
-// and no cache write-back or invalidation (the workgroup's rows of At stay
-// in L2).  Payload: score, alpha, the stop measure (||x - x_ref||^2 part or
-// ||r||^2 part), row index, flags.
-
-__device__ __forceinline__ double join_f64(uint64_t lo, uint64_t hi)
-{
-    return __longlong_as_double((long long)((hi << 32) | (lo & 0xFFFFFFFFull)));
-}
-
-__device__ __forceinline__ Red exchange(const Red& mine, XRec* exch, int wg, int G, int64_t k, Red* slots,
-                                        bool rel_err)  // slots: reduced with block_red1
-{
-    XRec* slot = exch + (size_t)(k & 1) * G;
-    const uint64_t tag = static_cast<uint64_t>(static_cast<uint32_t>(k + 1)) << 32;
-    if (threadIdx.x < 8) {
-        const int f = threadIdx.x;
-        const double dv = f < 2 ? mine.score : f < 4 ? mine.r : (rel_err ? mine.e2 : mine.r2);
-        const uint64_t bits = static_cast<uint64_t>(__double_as_longlong(dv));
-        const uint32_t p = f < 6 ? static_cast<uint32_t>((f & 1) ? (bits >> 32) : bits)
-                                 : (f == 6 ? mine.idx : mine.flags);
-        coh_store(&slot[wg].w[f], tag | p);
-    }
-    bool ok = true;
-    Red all = red_identity();
-    for (int w = threadIdx.x; w < G; w += kNT) {
-        Red o;
-        if (w == wg) {
-            o = mine;  // this workgroup's own record needs no round trip
-            if (rel_err) o.r2 = 0.0;
-            else o.e2 = 0.0;
-        } else {
-            // Poll one word of the record (one request per record and round:
-            // the G x G polls of a grid are the exchange's main traffic), then
-            // read the line; its eight words leave in one store instruction, so
-            // a stale word after a fresh first one is rare and just re-read.
-            uint64_t v[8];
-            uint32_t spins = 0;
-            while ((coh_load(&slot[w].w[0]) & 0xFFFFFFFF00000000ull) != tag) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > kSpinLimit) {
-                    ok = false;
-                    break;
-                }
-            }
-            while (ok) {
-#pragma unroll
-                for (int f = 0; f < 8; ++f) v[f] = coh_load(&slot[w].w[f]);
-                bool fresh = true;
-#pragma unroll
-                for (int f = 0; f < 8; ++f) fresh = fresh && ((v[f] & 0xFFFFFFFF00000000ull) == tag);
-                if (fresh) break;
-                __builtin_amdgcn_s_sleep(1);
-                if (++spins > kSpinLimit) ok = false;
-            }
-            if (!ok) break;
-            o.score = join_f64(v[0], v[1]);
-            o.r = join_f64(v[2], v[3]);
-            const double meas = join_f64(v[4], v[5]);
-            o.r2 = rel_err ? 0.0 : meas;
-            o.e2 = rel_err ? meas : 0.0;
-            o.idx = static_cast<uint32_t>(v[6]);
-            o.flags = static_cast<uint32_t>(v[7]);
-        }
-        all = red_combine(all, o);
-    }
-    if (!ok) all.flags |= kFlagTimeout;
-    return block_red1<kNT>(all, slots);
-}
-
 // LDS carve of the solve: x (FP64), x - x_ref in the accumulation type
 // (mixed), this workgroup's slice of x_ref, then the resident right-hand
 // sides and norms and the resident chunks (16-byte aligned).
@@ -616,7 +502,7 @@ __device__ __forceinline__ void solve_loop(const SolveSys& S, const Ctl& C, XRec
         if (wg == 0 && tid == 0 && C.cancel && (k % C.check_every) == 0 && *C.cancel != 0)
             loc.flags |= kFlagCancel;
         Red tot = block_red1<kNT>(loc, slots);
-        if constexpr (GRID) tot = exchange(tot, exch, wg, G, k, slots2, rel_err);
+        if constexpr (GRID) tot = exchange<kNT>(tot, exch, wg, G, k, slots2, rel_err);
 
         // Stop test on x_k (top of iteration k).
         bool conv;
