@@ -332,8 +332,8 @@ def table1_workload(P, W, torch, trials=5):
 
 
 def csr_workload(P, W, torch, solve=True):
-    """CSR A 1e6 x 5000 at 0.1%, d = 50000: sketch bandwidth, and the mixed
-    FP32 solve to 1e-8."""
+    """CSR A 1e6 x 5000 at 0.1%, d = 50000: the sketch kept sparse and the FP64
+    loop on it, beside the dense sketch and its mixed FP32 solve, to 1e-8."""
     c = W.config("sparse_csr")
     dev = "cuda:0"
     log("[bench] generating sparse_csr 1e6 x 5000 @ 0.1%")
@@ -343,13 +343,36 @@ def csr_workload(P, W, torch, solve=True):
     val = torch.from_numpy(s.val).to(dev)
     b = torch.from_numpy(s.b).to(dev)
     xs = torch.from_numpy(s.x_star).to(dev)
+    nnz = int(s.row_ptr[-1])
+    in_bytes = nnz * 8 + (c["m"] + 1) * 8 + c["m"] * 8
+    out = dict(nnz=nnz)
+
+    # sparse: At as CSR, FP64 loop over its stored entries
+    run_sp = lambda: P.csk_sketch_csr_sparse(rp, col, val, c["n"], b, c["d"], c["sketch_seed"])
+    run_sp()
+    t, sk = timed(run_sp, 3)
+    out.update(sparse_sketch_s=t, nnz_at=sk.nnz, nnz_at_per_row=sk.nnz / c["d"])
+    log(f"[bench] sparse_csr sparse sketch {t * 1e3:.2f} ms, nnz(At) = {sk.nnz} ({sk.nnz / c['d']:.1f} per row)")
+    if solve:
+        t2, r = timed(lambda: P.csk_solve_csr(sk.row_ptr, sk.col, sk.val, c["n"], sk.bt, nu2=sk.nu2, x_ref=xs,
+                                              tol=c["tol"], maxit=c["maxit"]))
+        rel = ((r.x - xs).norm() / xs.norm()).item()
+        us = t2 / max(r.iters, 1) * 1e6
+        out.update(sparse_solve_s=t2, sparse_iters=r.iters, sparse_status=P.csk_status_string(r.status),
+                   sparse_relerr=rel, sparse_us_per_iter=us,
+                   sparse_entry_gbs=sk.nnz * 12 / (us * 1e-6) / 1e9)
+        log(f"[bench] sparse_csr sparse solve {t2:.3f} s iters={r.iters} ({us:.2f} us/iter) rel={rel:.2e} "
+            f"{P.csk_status_string(r.status)}")
+    del sk
+    torch.cuda.empty_cache()
+
+    # dense: At stored dense (FP32 copy + FP64), mixed FP32 loop
     run = lambda: P.csk_sketch_csr(rp, col, val, c["n"], b, c["d"], c["sketch_seed"], lp_dtype=torch.float32)
     run()
     t, sk = timed(run, 3)
-    nnz = int(s.row_ptr[-1])
-    byts = nnz * 8 + (c["m"] + 1) * 8 + c["m"] * 8 + c["d"] * c["n"] * (4 + 8) + 16 * c["d"]
-    out = dict(sketch_s=t, sketch_gbs=byts / t / 1e9, nnz=nnz)
-    log(f"[bench] sparse_csr sketch {t * 1e3:.2f} ms ({byts / t / 1e9:.0f} GB/s)")
+    byts = in_bytes + c["d"] * c["n"] * (4 + 8) + 16 * c["d"]
+    out.update(sketch_s=t, sketch_gbs=byts / t / 1e9)
+    log(f"[bench] sparse_csr dense sketch {t * 1e3:.2f} ms ({byts / t / 1e9:.0f} GB/s)")
     if solve:
         t2, (x, raw) = timed(lambda: P.csk_solve(sk.At_lp, sk.bt, At64=sk.At64, nu2=sk.nu2, x_ref=xs, tol=c["tol"],
                                                  maxit=c["maxit"], sync=False))
@@ -357,7 +380,9 @@ def csr_workload(P, W, torch, solve=True):
         rel = ((x - xs).norm() / xs.norm()).item()
         out.update(solve_s=t2, iters=it, status=P.csk_status_string(st), relerr=rel,
                    us_per_iter=t2 / max(it, 1) * 1e6)
-        log(f"[bench] sparse_csr solve {t2:.3f} s iters={it} rel={rel:.2e} {P.csk_status_string(st)}")
+        log(f"[bench] sparse_csr dense mixed solve {t2:.3f} s iters={it} rel={rel:.2e} {P.csk_status_string(st)}")
+        if "sparse_solve_s" in out:
+            out["sparse_speedup_vs_dense"] = t2 / out["sparse_solve_s"]
     del sk
     torch.cuda.empty_cache()
     return out

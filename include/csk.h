@@ -178,6 +178,26 @@ csk_status csk_sketch_csr(const int64_t* row_ptr, const int32_t* col, const floa
                           double* bt, double* nu2,
                           void* ws, size_t ws_bytes, void* stream);
 
+/* ---- A10, sparse result: the sketch of a CSR matrix as a CSR matrix ---- *
+ * Same input contract as csk_sketch_csr (Definition 1 and Algorithm 1,
+ * Initialize).  Row j of At holds the union of the stored columns of the
+ * rows hashed to bucket j, in ascending column order, each value the
+ * ascending-row FP64 sum of the signed stored entries landing on it (bitwise
+ * the entry csk_sketch_csr writes densely; a sum that cancels to zero stays
+ * stored).  Outputs (device): at_row_ptr (d + 1 int64, at_row_ptr[0] = 0,
+ * at_row_ptr[d] = nnz(At) <= nnz), at_col (int32) and at_val (FP64), each
+ * with room for nnz entries (the caller cannot know nnz(At) before the call;
+ * read at_row_ptr[d] after it).  nu2 (nullable): squared row norms, bitwise
+ * those of csk_sketch_csr.  b and bt are nullable together.
+ * Requires 1 <= m, d < 2^31, 1 <= n <= 131072, nnz < 2^32 - 1.            */
+csk_status csk_sketch_csr_sparse_workspace_size(int64_t m, int64_t n, int64_t d, size_t* bytes /*host*/);
+csk_status csk_sketch_csr_sparse(const int64_t* row_ptr, const int32_t* col, const float* val,
+                                 int64_t m, int64_t n, int64_t nnz, const double* b,
+                                 int64_t d, uint64_t seed,
+                                 int64_t* at_row_ptr, int32_t* at_col, double* at_val,
+                                 double* bt, double* nu2,
+                                 void* ws, size_t ws_bytes, void* stream);
+
 /* ---- A6/A7: the MWRK loop on the sketched system (Algorithm 1, loop) ---- *
  * at_dtype = F64: At is the FP64 sketch (At64 may be NULL or equal to At);
  *   plain FP64 iterations.
@@ -206,6 +226,26 @@ csk_status csk_solve(const void* At, csk_dtype at_dtype, int64_t ldat,
                      const double* x0, double* x,
                      const csk_solve_opts* opts /*host*/, csk_solve_result* res,
                      void* ws, size_t ws_bytes, void* stream);
+
+/* ---- The MWRK loop on a CSR sketch (Algorithm 1, loop) ------------------ *
+ * The loop of csk_solve in FP64 with At given as CSR (at_row_ptr d + 1
+ * int64 with at_row_ptr[0] = 0 and at_row_ptr[d] = nnz, at_col int32 in
+ * [0, n) and distinct within a row, at_val FP64), e.g. from
+ * csk_sketch_csr_sparse.  Each iteration reads the nnz stored entries
+ * instead of d * n.  nu2: squared row norms (nullable: computed into ws).
+ * opts as for csk_solve (refresh_every is ignored: there is no low-precision
+ * copy).  A row pointer array inconsistent with nnz ends the solve with
+ * result.status = CSK_ERR_INVALID_ARG.
+ * Requires 1 <= d < 2^31, 1 <= n <= 16384, nnz < 2^31; the workgroup's
+ * share of rows must fit LDS beside x (else CSK_ERR_UNSUPPORTED: ask for
+ * more workgroups).  Each workgroup keeps part of its rows' entries in LDS
+ * for the whole solve.                                                      */
+csk_status csk_solve_csr_workspace_size(int64_t d, int64_t n, int64_t nnz, size_t* bytes /*host*/);
+csk_status csk_solve_csr(const int64_t* at_row_ptr, const int32_t* at_col, const double* at_val,
+                         int64_t d, int64_t n, int64_t nnz, const double* bt, const double* nu2,
+                         const double* x0, double* x,
+                         const csk_solve_opts* opts /*host*/, csk_solve_result* res,
+                         void* ws, size_t ws_bytes, void* stream);
 
 /* ---- Tuning of the persistent solve's launch shape ---------------------- *
  * csk_tune_solve times trial_iters MWRK iterations (no convergence test) of

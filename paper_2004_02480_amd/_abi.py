@@ -34,7 +34,9 @@ EXPORTED = [
     "csk_status_string", "csk_last_error", "csk_version", "csk_hash",
     "csk_sketch_workspace_size", "csk_sketch",
     "csk_sketch_csr_workspace_size", "csk_sketch_csr",
+    "csk_sketch_csr_sparse_workspace_size", "csk_sketch_csr_sparse",
     "csk_solve_workspace_size", "csk_solve",
+    "csk_solve_csr_workspace_size", "csk_solve_csr",
     "csk_solve_batched_workspace_size", "csk_solve_batched",
     "csk_solve_mrhs_workspace_size", "csk_solve_mrhs",
     "csk_tune_solve_workspace_size", "csk_tune_solve", "csk_tune_lookup", "csk_tune_clear",
@@ -114,6 +116,16 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.csk_sketch_csr.restype = I32
     lib.csk_sketch_csr.argtypes = [P, P, P, I64, I64, I64, P, I64, U64,
                                    P, I64, P, I32, I64, P, P, P, SZ, P]
+    lib.csk_sketch_csr_sparse_workspace_size.restype = I32
+    lib.csk_sketch_csr_sparse_workspace_size.argtypes = [I64, I64, I64, PSZ]
+    lib.csk_sketch_csr_sparse.restype = I32
+    lib.csk_sketch_csr_sparse.argtypes = [P, P, P, I64, I64, I64, P, I64, U64,
+                                          P, P, P, P, P, P, SZ, P]
+    lib.csk_solve_csr_workspace_size.restype = I32
+    lib.csk_solve_csr_workspace_size.argtypes = [I64, I64, I64, PSZ]
+    lib.csk_solve_csr.restype = I32
+    lib.csk_solve_csr.argtypes = [P, P, P, I64, I64, I64, P, P, P, P,
+                                  ctypes.POINTER(SolveOpts), P, P, SZ, P]
     lib.csk_solve_workspace_size.restype = I32
     lib.csk_solve_workspace_size.argtypes = [I64, I64, I32, PSZ]
     lib.csk_solve.restype = I32

@@ -172,6 +172,84 @@ def csk_sketch_csr(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, 
 
 
 @dataclass
+class CsrSketchOut:
+    row_ptr: torch.Tensor   # d + 1 int64
+    col: torch.Tensor       # nnz(At) int32 (a view of the first row_ptr[d] entries)
+    val: torch.Tensor       # nnz(At) float64
+    bt: Optional[torch.Tensor]
+    nu2: torch.Tensor
+    nnz: int
+
+
+def csk_sketch_csr_sparse(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, n: int,
+                          b: Optional[torch.Tensor], d: int, seed: int, *, stream=None) -> CsrSketchOut:
+    """At = S A as a CSR matrix from a CSR A (Algorithm 1, Initialize).
+
+    Synchronizes the stream once to read nnz(At)."""
+    for t, nm in ((row_ptr, "row_ptr"), (col, "col"), (val, "val")):
+        _need_cuda(t, nm)
+    if row_ptr.dtype != torch.int64 or col.dtype != torch.int32 or val.dtype != torch.float32:
+        raise ValueError("row_ptr int64, col int32, val float32 expected")
+    m = row_ptr.numel() - 1
+    nnz = col.numel()
+    dev = row_ptr.device
+    at_rp = torch.empty(d + 1, dtype=torch.int64, device=dev)
+    at_col = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
+    at_val = torch.empty(max(nnz, 1), dtype=torch.float64, device=dev)
+    nu2 = torch.empty(d, dtype=torch.float64, device=dev)
+    bt = torch.empty(d, dtype=torch.float64, device=dev) if b is not None else None
+    nbytes = ctypes.c_size_t(0)
+    _check(_lib.csk_sketch_csr_sparse_workspace_size(m, n, d, ctypes.byref(nbytes)),
+           "csk_sketch_csr_sparse_workspace_size")
+    ws = _workspace(nbytes.value, dev)
+    _check(_lib.csk_sketch_csr_sparse(_ptr(row_ptr), _ptr(col), _ptr(val), m, n, nnz,
+                                      _ptr(b.contiguous() if b is not None else None), d,
+                                      ctypes.c_uint64(seed & (2**64 - 1)), _ptr(at_rp), _ptr(at_col), _ptr(at_val),
+                                      _ptr(bt), _ptr(nu2), _ptr(ws), ws.numel(), _stream(stream)),
+           "csk_sketch_csr_sparse")
+    nnz_at = int(at_rp[d].item())
+    return CsrSketchOut(at_rp, at_col[:nnz_at], at_val[:nnz_at], bt, nu2, nnz_at)
+
+
+def csk_solve_csr(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, n: int, bt: torch.Tensor, *,
+                  nu2: Optional[torch.Tensor] = None, x0: Optional[torch.Tensor] = None,
+                  x_ref: Optional[torch.Tensor] = None, tol: float = 1e-10, maxit: int = 100000,
+                  stop_mode: Optional[int] = None, cancel: Optional[int] = None, check_every: int = 256,
+                  grid: int = 0, single_wg: int = -1, out: Optional[torch.Tensor] = None,
+                  result: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
+                  sync: bool = True, stream=None):
+    """MWRK (Algorithm 1, loop) on a CSR At (int64 row_ptr, int32 col, float64 val), FP64.
+
+    Returns a SolveResult when sync=True, else (x, raw_result_tensor)."""
+    for t, nm in ((row_ptr, "row_ptr"), (col, "col"), (val, "val"), (bt, "bt")):
+        _need_cuda(t, nm)
+    if row_ptr.dtype != torch.int64 or col.dtype != torch.int32 or val.dtype != torch.float64:
+        raise ValueError("row_ptr int64, col int32, val float64 expected")
+    d = row_ptr.numel() - 1
+    nnz = col.numel()
+    if val.numel() != nnz:
+        raise ValueError("col and val lengths differ")
+    if stop_mode is None:
+        stop_mode = CSK_STOP_REL_ERR if x_ref is not None else CSK_STOP_REL_RESID
+    dev = row_ptr.device
+    x = out if out is not None else torch.empty(n, dtype=torch.float64, device=dev)
+    res = result if result is not None else torch.zeros(_abi.RESULT_BYTES, dtype=torch.uint8, device=dev)
+    if workspace is None:
+        nbytes = ctypes.c_size_t(0)
+        _check(_lib.csk_solve_csr_workspace_size(d, n, nnz, ctypes.byref(nbytes)), "csk_solve_csr_workspace_size")
+        workspace = _workspace(nbytes.value, dev)
+    o = _opts(tol, maxit, stop_mode, 0, x_ref, cancel, check_every, grid, single_wg)
+    _check(_lib.csk_solve_csr(_ptr(row_ptr), _ptr(col), _ptr(val), d, n, nnz, _ptr(bt), _ptr(nu2), _ptr(x0),
+                              _ptr(x), ctypes.byref(o), _ptr(res), _ptr(workspace), workspace.numel(),
+                              _stream(stream)), "csk_solve_csr")
+    if not sync:
+        return x, res
+    (stream or torch.cuda.current_stream()).synchronize()
+    it, st, fb, meas, nref = parse_results(res)[0]
+    return SolveResult(x, it, st, fb, meas, nref)
+
+
+@dataclass
 class SolveResult:
     x: torch.Tensor
     iters: int

@@ -12,6 +12,7 @@
 
 #include "csk_sketch.h"
 #include "csk_solve.h"
+#include "csk_solve_csr.h"
 #include "csk_mrhs.h"
 
 namespace csk {
@@ -311,6 +312,88 @@ csk_status csk_sketch_csr(const int64_t* row_ptr, const int32_t* col, const floa
     if (ws_bytes < need) { set_error("workspace: need %zu bytes, got %zu", need, ws_bytes); return CSK_ERR_WORKSPACE; }
     return sketch_csr_run(row_ptr, col, val, m, n, nnz, b, d, seed, At64, ldat64, At_lp,
                           At_lp ? lp_dtype : (csk_dtype)0, ldat_lp, bt, nu2, ws, ws_bytes, as_stream(stream));
+}
+
+constexpr int64_t kMaxCsrSketchN = 131072;  // LDS bitmap of the distinct-column count
+constexpr int64_t kMaxCsrSolveN = 16384;    // x in LDS, 16-bit resident column indices
+
+csk_status csk_sketch_csr_sparse_workspace_size(int64_t m, int64_t n, int64_t d, size_t* bytes)
+{
+    g_err[0] = 0;
+    if (!bytes || m < 1 || n < 1 || d < 1) { set_error("bad sizes"); return CSK_ERR_INVALID_ARG; }
+    *bytes = sketch_csr_ws_bytes(m, d, true);
+    return CSK_OK;
+}
+
+csk_status csk_sketch_csr_sparse(const int64_t* row_ptr, const int32_t* col, const float* val, int64_t m,
+                                 int64_t n, int64_t nnz, const double* b, int64_t d, uint64_t seed,
+                                 int64_t* at_row_ptr, int32_t* at_col, double* at_val, double* bt, double* nu2,
+                                 void* ws, size_t ws_bytes, void* stream)
+{
+    g_err[0] = 0;
+    if (!row_ptr || (nnz > 0 && (!col || !val))) { set_error("row_ptr / col / val required"); return CSK_ERR_INVALID_ARG; }
+    if (m < 1 || n < 1 || d < 1 || nnz < 0 || m > INT32_MAX || d > INT32_MAX || nnz >= (int64_t)UINT32_MAX) {
+        set_error("need 1 <= m, d < 2^31, n >= 1, 0 <= nnz < 2^32 - 1");
+        return CSK_ERR_INVALID_ARG;
+    }
+    if (n > kMaxCsrSketchN) { set_error("n=%lld exceeds %lld", (long long)n, (long long)kMaxCsrSketchN); return CSK_ERR_UNSUPPORTED; }
+    if (!at_row_ptr || (nnz > 0 && (!at_col || !at_val))) { set_error("at_row_ptr / at_col / at_val required"); return CSK_ERR_INVALID_ARG; }
+    if ((b == nullptr) != (bt == nullptr)) { set_error("b and bt go together"); return CSK_ERR_INVALID_ARG; }
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u)) { set_error("workspace NULL or unaligned"); return CSK_ERR_INVALID_ARG; }
+    size_t need = 0;
+    csk_sketch_csr_sparse_workspace_size(m, n, d, &need);
+    if (ws_bytes < need) { set_error("workspace: need %zu bytes, got %zu", need, ws_bytes); return CSK_ERR_WORKSPACE; }
+    return sketch_csr_sparse_run(row_ptr, col, val, m, n, b, d, seed, at_row_ptr, at_col, at_val, bt, nu2, ws,
+                                 ws_bytes, as_stream(stream));
+}
+
+csk_status csk_solve_csr_workspace_size(int64_t d, int64_t n, int64_t nnz, size_t* bytes)
+{
+    g_err[0] = 0;
+    if (!bytes || d < 1 || n < 1 || nnz < 0) { set_error("bad sizes"); return CSK_ERR_INVALID_ARG; }
+    *bytes = csr_solve_ws_bytes(d, 65536);
+    return CSK_OK;
+}
+
+csk_status csk_solve_csr(const int64_t* at_row_ptr, const int32_t* at_col, const double* at_val, int64_t d,
+                         int64_t n, int64_t nnz, const double* bt, const double* nu2, const double* x0, double* x,
+                         const csk_solve_opts* opts, csk_solve_result* res, void* ws, size_t ws_bytes, void* stream)
+{
+    g_err[0] = 0;
+    csk_status st = check_opts(opts);
+    if (st != CSK_OK) return st;
+    if (d < 1 || n < 1 || d > INT32_MAX || nnz < 0 || nnz > INT32_MAX) {
+        set_error("need 1 <= d < 2^31, n >= 1, 0 <= nnz < 2^31");
+        return CSK_ERR_INVALID_ARG;
+    }
+    if (n > kMaxCsrSolveN) { set_error("n=%lld exceeds %lld", (long long)n, (long long)kMaxCsrSolveN); return CSK_ERR_UNSUPPORTED; }
+    if (!at_row_ptr || (nnz > 0 && (!at_col || !at_val))) { set_error("at_row_ptr / at_col / at_val required"); return CSK_ERR_INVALID_ARG; }
+    if (!bt || !x || !res) { set_error("bt, x and res are required"); return CSK_ERR_INVALID_ARG; }
+    if (opts->stop_mode == CSK_STOP_REL_ERR && !opts->x_ref) {
+        set_error("CSK_STOP_REL_ERR needs opts->x_ref");
+        return CSK_ERR_INVALID_ARG;
+    }
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u)) { set_error("workspace NULL or unaligned"); return CSK_ERR_INVALID_ARG; }
+    const int grid = csr_solve_grid(d, nnz, opts);
+    if (ws_bytes < csr_solve_ws_bytes(d, grid)) {
+        set_error("workspace: need %zu bytes, got %zu", csr_solve_ws_bytes(d, grid), ws_bytes);
+        return CSK_ERR_WORKSPACE;
+    }
+    CsrSolveSys S{};
+    S.rp = at_row_ptr;
+    S.col = at_col;
+    S.val = at_val;
+    S.bt = bt;
+    S.nu2 = nu2;
+    S.x0 = x0;
+    S.xref = opts->x_ref;
+    S.x = x;
+    S.res = res;
+    S.nnz = nnz;
+    S.d = (int32_t)d;
+    S.n = (int32_t)n;
+    S.stop_mode = opts->stop_mode;
+    return csr_solve_run(S, opts, ws, ws_bytes, as_stream(stream));
 }
 
 csk_status csk_solve_workspace_size(int64_t d, int64_t n, csk_dtype at_dtype, size_t* bytes)

@@ -48,7 +48,13 @@ csk_status sketch_run(const SketchJob* jobs, int32_t nsys, csk_dtype a_dtype, cs
                       uint32_t* perm_out, uint32_t* ptr_out,
                       void* ws, size_t ws_bytes, hipStream_t stream);
 
-// CSR sketch (FP32 values) into dense outputs, single system.
+// CSR sketch (FP32 values), single system: dense outputs, or (sparse) At as
+// CSR with FP64 values.  Workspace bytes of either.
+size_t sketch_csr_ws_bytes(int64_t m, int64_t d, bool sparse);
+csk_status sketch_csr_sparse_run(const int64_t* row_ptr, const int32_t* col, const float* val, int64_t m,
+                                 int64_t n, const double* b, int64_t d, uint64_t seed, int64_t* at_rp,
+                                 int32_t* at_col, double* at_val, double* bt, double* nu2, void* ws, size_t ws_bytes,
+                                 hipStream_t st);
 csk_status sketch_csr_run(const int64_t* row_ptr, const int32_t* col, const float* val, int64_t m, int64_t n,
                           int64_t nnz, const double* b, int64_t d, uint64_t seed, double* At64, int64_t ldat64,
                           void* At_lp, csk_dtype lp_dtype, int64_t ldat_lp, double* bt, double* nu2,

@@ -391,18 +391,35 @@ __global__ void k_nu2_finalize(Batch b)
 // sequential in the row order), then the whole workgroup writes the dense
 // row(s) and reduces the squared norm.  Entries beyond the staging capacity
 // are read straight from global memory by the same ordered walk.
+// Sparse output (SP): the accumulation also marks the touched columns in an
+// LDS bitmap, and instead of the dense row the workgroup writes the touched
+// columns, ascending, with their sums at the bucket's offset of the CSR
+// result.  Adding only the stored entries to an accumulator that starts at
+// +0.0 gives the same bits as the dense sum, where the absent entries add
+// signed zeros, so both outputs hold the same values.
 // ---------------------------------------------------------------------------
 constexpr int kCsrNT = 256;
 constexpr int kCsrStage = 1024;   // staged entries per bucket
 constexpr int kCsrRows = 256;     // staged rows per bucket
+constexpr int kCsrChunk = kCsrNT * 32;  // accumulator columns: one bitmap word per thread
 
-template <int LP>
+// Where the sparse result goes: ofs is the exclusive scan of the distinct
+// column counts of the buckets (d + 1 entries).
+struct CsrOut {
+    const uint32_t* ofs;
+    int64_t* rp;     // d + 1
+    int32_t* col;
+    double* val;
+};
+
+template <int LP, bool SP>
 __global__ __launch_bounds__(kCsrNT) void k_segsum_csr(Batch b, const int64_t* __restrict__ row_ptr,
                                                        const int32_t* __restrict__ colidx,
-                                                       const float* __restrict__ val, int chunk)
+                                                       const float* __restrict__ val, int chunk, CsrOut so)
 {
     extern __shared__ __align__(16) char smem[];
     double* acc = reinterpret_cast<double*>(smem);              // chunk columns
+    uint32_t* bm = reinterpret_cast<uint32_t*>(smem + (size_t)chunk * 8);  // SP: touched columns of the chunk
     __shared__ double s_val[kCsrStage];
     __shared__ int32_t s_col[kCsrStage];
     __shared__ int32_t s_rowend[kCsrRows];                      // staged-entry end per row
@@ -455,10 +472,16 @@ __global__ __launch_bounds__(kCsrNT) void k_segsum_csr(Batch b, const int64_t* _
             s_rowend[tid] = (int32_t)(start + mycnt);
         }
         double nrm = 0.0;
+        uint32_t out = 0;  // SP: entries of the bucket written so far
         for (int c0 = 0; c0 < n; c0 += chunk) {
             const int cw = min(chunk, n - c0);
             for (int c = tid; c < cw; c += kCsrNT) acc[c] = 0.0;
+            if constexpr (SP) bm[tid] = 0u;
             __syncthreads();
+            auto add = [&](int c, double v) {
+                acc[c] = acc[c] + v;
+                if constexpr (SP) atomicOr(&bm[c >> 5], 1u << (c & 31));
+            };
             if (wid == 0) {
                 if (fits) {
                     int32_t e0 = 0;
@@ -466,7 +489,7 @@ __global__ __launch_bounds__(kCsrNT) void k_segsum_csr(Batch b, const int64_t* _
                         const int32_t e1 = s_rowend[p];
                         for (int32_t e = e0 + lane; e < e1; e += kWave) {
                             const int c = s_col[e] - c0;
-                            if (c >= 0 && c < cw) acc[c] = acc[c] + s_val[e];
+                            if (c >= 0 && c < cw) add(c, s_val[e]);
                         }
                         e0 = e1;
                     }
@@ -477,7 +500,7 @@ __global__ __launch_bounds__(kCsrNT) void k_segsum_csr(Batch b, const int64_t* _
                         const int64_t e1 = row_ptr[row + 1];
                         for (int64_t e = row_ptr[row] + lane; e < e1; e += kWave) {
                             const int c = colidx[e] - c0;
-                            if (c >= 0 && c < cw) acc[c] = acc[c] + sgn * static_cast<double>(val[e]);
+                            if (c >= 0 && c < cw) add(c, sgn * static_cast<double>(val[e]));
                         }
                     }
                 }
@@ -486,10 +509,36 @@ __global__ __launch_bounds__(kCsrNT) void k_segsum_csr(Batch b, const int64_t* _
             for (int c = tid; c < cw; c += kCsrNT) {
                 const double a = acc[c];
                 nrm += a * a;
-                if (S.At64) S.At64[j * S.ldat64 + c0 + c] = a;
-                if constexpr (LP != 0) store_lp<LP>(S.Atlp, j * S.ldatlp + c0 + c, a);
+                if constexpr (!SP) {
+                    if (S.At64) S.At64[j * S.ldat64 + c0 + c] = a;
+                    if constexpr (LP != 0) store_lp<LP>(S.Atlp, j * S.ldatlp + c0 + c, a);
+                }
+            }
+            if constexpr (SP) {
+                // thread t owns bitmap word t (columns 32t .. 32t + 31 of the
+                // chunk): its marked columns go, ascending, after those of
+                // the threads before it
+                uint32_t word = bm[tid];
+                const uint32_t cnt = __popc(word);
+                uint32_t total;
+                uint32_t pos = so.ofs[j] + out + block_incl_scan<kCsrNT>(cnt, &total) - cnt;
+                while (word) {
+                    const int bit = __ffs(word) - 1;
+                    word &= word - 1u;
+                    const int c = tid * 32 + bit;
+                    so.col[pos] = c0 + c;
+                    so.val[pos] = acc[c];
+                    ++pos;
+                }
+                out += total;
             }
             __syncthreads();
+        }
+        if constexpr (SP) {
+            if (tid == 0) {
+                so.rp[j] = so.ofs[j];
+                if (j == S.d - 1) so.rp[S.d] = so.ofs[S.d];
+            }
         }
         nrm = wave_sum(nrm);
         if (lane == 0) s_red[wid] = nrm;
@@ -512,6 +561,53 @@ __global__ __launch_bounds__(kCsrNT) void k_segsum_csr(Batch b, const int64_t* _
             }
         }
         __syncthreads();
+    }
+}
+
+// Distinct stored columns per bucket, the row lengths of the sparse sketch.
+// One wavefront per bucket; each lane takes whole rows of the bucket and
+// marks their columns in the wavefront's LDS bitmap, counting the marks that
+// were new (the LDS atomic returns the old word, so a column shared by rows
+// on different lanes is counted once).  The marked words are cleared by the
+// same walk afterwards, ready for the next bucket.
+constexpr int kDistinctWaves = 4;
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
+{
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__global__ __launch_bounds__(kDistinctWaves * kWave) void k_csr_distinct(Batch b, const int64_t* __restrict__ row_ptr,
+                                                                      const int32_t* __restrict__ colidx,
+                                                                      int nwords, uint32_t* __restrict__ cnt)
+{
+    extern __shared__ uint32_t bm_all[];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    uint32_t* bm = bm_all + (size_t)wid * nwords;
+    for (int w = lane; w < nwords; w += kWave) bm[w] = 0u;
+    for (int64_t j = (int64_t)blockIdx.x * kDistinctWaves + wid; j < b.D;
+         j += (int64_t)gridDim.x * kDistinctWaves) {
+        const uint32_t beg = b.ptr[j], end = b.ptr[j + 1];
+        uint32_t fresh = 0;
+        for (uint32_t p = beg + lane; p < end; p += kWave) {
+            const uint32_t row = b.perm[p];
+            const int64_t e1 = row_ptr[row + 1];
+            for (int64_t e = row_ptr[row]; e < e1; ++e) {
+                const uint32_t c = static_cast<uint32_t>(colidx[e]);
+                const uint32_t bit = 1u << (c & 31u);
+                fresh += (atomicOr(&bm[c >> 5], bit) & bit) ? 0u : 1u;
+            }
+        }
+        fresh = wave_sum_u32(fresh);
+        if (lane == 0) cnt[j] = fresh;
+        for (uint32_t p = beg + lane; p < end; p += kWave) {
+            const uint32_t row = b.perm[p];
+            const int64_t e1 = row_ptr[row + 1];
+            for (int64_t e = row_ptr[row]; e < e1; ++e) bm[static_cast<uint32_t>(colidx[e]) >> 5] = 0u;
+        }
     }
 }
 
@@ -821,12 +917,14 @@ csk_status sketch_run(const SketchJob* jobs, int32_t nsys, csk_dtype a_dtype, cs
     return CSK_OK;
 }
 
-csk_status sketch_csr_run(const int64_t* row_ptr, const int32_t* col, const float* val, int64_t m, int64_t n,
-                          int64_t nnz, const double* b, int64_t d, uint64_t seed, double* At64, int64_t ldat64,
-                          void* At_lp, csk_dtype lp_dtype, int64_t ldat_lp, double* bt, double* nu2,
-                          void* ws, size_t ws_bytes, hipStream_t st)
+namespace {
+
+// Bucket grouping of a CSR sketch; scratch carved from ws (the layout that
+// sketch_csr_ws_bytes sizes).  ofs (d + 1) only for the sparse output.
+csk_status csr_setup(const double* b, double* bt, double* nu2, int64_t m, int64_t n, int64_t d, uint64_t seed,
+                     double* At64, int64_t ldat64, void* At_lp, int64_t ldat_lp, void* ws, size_t ws_bytes,
+                     bool sparse, Batch& bt_, uint32_t** ofs, hipStream_t st)
 {
-    (void)nnz;
     std::vector<SketchSys> hs(1);
     SketchSys& S = hs[0];
     S = SketchSys{};
@@ -844,7 +942,7 @@ csk_status sketch_csr_run(const int64_t* row_ptr, const int32_t* col, const floa
     S.nrhs = 1;
     S.nchunks = 1;
     Carve c(ws);
-    Batch bt_{};
+    bt_ = Batch{};
     SketchSys* d_sys = c.take<SketchSys>(1);
     c.take<SketchSys>(1);
     c.take<int64_t>(2);
@@ -856,6 +954,7 @@ csk_status sketch_csr_run(const int64_t* row_ptr, const int32_t* col, const floa
     bt_.perm = c.take<uint32_t>(m);
     bt_.nu2part = c.take<double>(d);
     bt_.scan_part = c.take<uint32_t>(d / kScanTile + 2);
+    if (sparse) *ofs = c.take<uint32_t>(d + 1);
     if (c.bytes() > ws_bytes) {
         set_error("sketch workspace too small: need %zu bytes, got %zu", c.bytes(), ws_bytes);
         return CSK_ERR_WORKSPACE;
@@ -867,31 +966,77 @@ csk_status sketch_csr_run(const int64_t* row_ptr, const int32_t* col, const floa
     bt_.nsys = 1;
     csk_status r;
     if ((r = upload_descs(hs, d_sys, st)) != CSK_OK) return r;
-    if ((r = group_rows(bt_, st)) != CSK_OK) return r;
-    // accumulator chunk: up to 8192 columns (64 KB of LDS)
-    const int chunk = static_cast<int>(std::min<int64_t>(n, 8192));
-    const size_t shm = (size_t)chunk * 8;
+    return group_rows(bt_, st);
+}
+
+template <int LP, bool SP>
+csk_status launch_segsum_csr(const Batch& b, const int64_t* row_ptr, const int32_t* col, const float* val, int64_t n,
+                             int64_t d, const CsrOut& so, hipStream_t st)
+{
+    // accumulator chunk: up to 8192 columns (64 KB of LDS), plus its bitmap
+    const int chunk = static_cast<int>(std::min<int64_t>(n, kCsrChunk));
+    const size_t shm = (size_t)chunk * 8 + (SP ? kCsrNT * 4 : 0);
     const int grid = grid_for(d, 1, 1 << 20);
-    switch (lp_dtype) {
-    case CSK_F32:
-        CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_segsum_csr<CSK_F32>), hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-        k_segsum_csr<CSK_F32><<<grid, kCsrNT, shm, st>>>(bt_, row_ptr, col, val, chunk);
-        break;
-    case CSK_F16:
-        CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_segsum_csr<CSK_F16>), hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-        k_segsum_csr<CSK_F16><<<grid, kCsrNT, shm, st>>>(bt_, row_ptr, col, val, chunk);
-        break;
-    case CSK_BF16:
-        CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_segsum_csr<CSK_BF16>), hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-        k_segsum_csr<CSK_BF16><<<grid, kCsrNT, shm, st>>>(bt_, row_ptr, col, val, chunk);
-        break;
-    default:
-        CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_segsum_csr<0>), hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-        k_segsum_csr<0><<<grid, kCsrNT, shm, st>>>(bt_, row_ptr, col, val, chunk);
-        break;
-    }
+    CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_segsum_csr<LP, SP>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+    k_segsum_csr<LP, SP><<<grid, kCsrNT, shm, st>>>(b, row_ptr, col, val, chunk, so);
     CSK_LAUNCH_CHECK("k_segsum_csr");
     return CSK_OK;
+}
+
+}  // namespace
+
+size_t sketch_csr_ws_bytes(int64_t m, int64_t d, bool sparse)
+{
+    return sketch_ws_bytes(m, d, d, 1) + (sparse ? (size_t)(d + 1) * 4 + 256 : 0);
+}
+
+csk_status sketch_csr_run(const int64_t* row_ptr, const int32_t* col, const float* val, int64_t m, int64_t n,
+                          int64_t nnz, const double* b, int64_t d, uint64_t seed, double* At64, int64_t ldat64,
+                          void* At_lp, csk_dtype lp_dtype, int64_t ldat_lp, double* bt, double* nu2,
+                          void* ws, size_t ws_bytes, hipStream_t st)
+{
+    (void)nnz;
+    Batch bt_;
+    csk_status r = csr_setup(b, bt, nu2, m, n, d, seed, At64, ldat64, At_lp, ldat_lp, ws, ws_bytes, false, bt_,
+                             nullptr, st);
+    if (r != CSK_OK) return r;
+    const CsrOut none{};
+    switch (lp_dtype) {
+    case CSK_F32: return launch_segsum_csr<CSK_F32, false>(bt_, row_ptr, col, val, n, d, none, st);
+    case CSK_F16: return launch_segsum_csr<CSK_F16, false>(bt_, row_ptr, col, val, n, d, none, st);
+    case CSK_BF16: return launch_segsum_csr<CSK_BF16, false>(bt_, row_ptr, col, val, n, d, none, st);
+    default: return launch_segsum_csr<0, false>(bt_, row_ptr, col, val, n, d, none, st);
+    }
+}
+
+csk_status sketch_csr_sparse_run(const int64_t* row_ptr, const int32_t* col, const float* val, int64_t m,
+                                 int64_t n, const double* b, int64_t d, uint64_t seed, int64_t* at_rp,
+                                 int32_t* at_col, double* at_val, double* bt, double* nu2, void* ws, size_t ws_bytes,
+                                 hipStream_t st)
+{
+    Batch bt_;
+    uint32_t* ofs = nullptr;
+    csk_status r = csr_setup(b, bt, nu2, m, n, d, seed, nullptr, 0, nullptr, 0, ws, ws_bytes, true, bt_, &ofs, st);
+    if (r != CSK_OK) return r;
+    // distinct columns per bucket (into cnt, which the grouping left zero),
+    // then their exclusive scan: each bucket's offset in the result
+    const int nwords = static_cast<int>((n + 31) / 32);
+    const size_t shm = (size_t)kDistinctWaves * nwords * 4;
+    CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_csr_distinct),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+    k_csr_distinct<<<grid_for(d, kDistinctWaves, 1 << 16), kDistinctWaves * kWave, shm, st>>>(bt_, row_ptr, col,
+                                                                                             nwords, bt_.cnt);
+    CSK_LAUNCH_CHECK("k_csr_distinct");
+    const int nb_scan = static_cast<int>((d + kScanTile - 1) / kScanTile);
+    k_scan_reduce<<<nb_scan, 256, 0, st>>>(bt_.cnt, d, bt_.scan_part);
+    CSK_LAUNCH_CHECK("k_scan_reduce");
+    k_scan_top<<<1, 1024, 0, st>>>(bt_.scan_part, nb_scan, ofs, d);
+    CSK_LAUNCH_CHECK("k_scan_top");
+    k_scan_apply<<<nb_scan, 256, 0, st>>>(bt_.cnt, d, bt_.scan_part, ofs);
+    CSK_LAUNCH_CHECK("k_scan_apply");
+    const CsrOut so{ofs, at_rp, at_col, at_val};
+    return launch_segsum_csr<0, true>(bt_, row_ptr, col, val, n, d, so, st);
 }
 
 }  // namespace csk

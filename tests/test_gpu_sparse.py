@@ -1,0 +1,170 @@
+"""GPU parity of the sparse path: the sketch of a CSR matrix kept as CSR
+(Algorithm 1, Initialize) and the MWRK loop on it (Algorithm 1, loop).
+
+The sparse sketch must hold, bit for bit, the oracle's dense sketch (scattered
+into a dense array), with each row's pattern the union of the stored columns
+of its bucket's rows.  The loop's residuals are summed over the stored entries
+in another order than the oracle's dense sums, so iterates are compared after
+K steps to ~1e-12 and converged solutions against x* and the oracle."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2004_02480_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _upload(s):
+    return (torch.from_numpy(s.row_ptr).to(DEV), torch.from_numpy(s.col).to(DEV), torch.from_numpy(s.val).to(DEV),
+            torch.from_numpy(s.b).to(DEV))
+
+
+def _dense(sk, d, n):
+    rp = sk.row_ptr.cpu().numpy()
+    out = np.zeros((d, n), np.float64)
+    rows = np.repeat(np.arange(d), np.diff(rp))
+    out[rows, sk.col.cpu().numpy()] = sk.val.cpu().numpy()
+    return out
+
+
+def _union_pattern(orc, s, d, seed):
+    """Per bucket, the sorted union of the stored columns of its rows."""
+    bucket, _ = orc.hash_rows(seed, s.m, d)
+    rows = np.repeat(np.arange(s.m), np.diff(s.row_ptr))
+    key = np.unique(bucket[rows].astype(np.int64) * s.n + s.col)
+    return key // s.n, key % s.n
+
+
+@pytest.mark.parametrize("m,n,dens,d", [(3000, 400, 0.01, 150), (20000, 3000, 0.002, 700), (50, 9000, 0.01, 10),
+                                        (40000, 2000, 0.003, 4000)])
+def test_sparse_sketch_bitexact(gpu, orc, m, n, dens, d):
+    s = W.sparse_csr(m, n, dens, seed=m + 1)
+    rp, col, val, b = _upload(s)
+    sk = gpu.csk_sketch_csr_sparse(rp, col, val, n, b, d, 29)
+    At, bt = orc.sketch_csr(s.row_ptr, s.col, s.val, m, n, s.b, d, 29)
+    # values: bitwise the oracle's dense sketch
+    np.testing.assert_array_equal(_dense(sk, d, n), At)
+    np.testing.assert_array_equal(sk.bt.cpu().numpy(), bt)
+    # pattern: the union of the bucket rows' columns, ascending within a row
+    prow, pcol = _union_pattern(orc, s, d, 29)
+    gp = sk.row_ptr.cpu().numpy()
+    assert gp[0] == 0 and gp[-1] == sk.nnz == prow.size
+    np.testing.assert_array_equal(np.repeat(np.arange(d), np.diff(gp)), prow)
+    np.testing.assert_array_equal(sk.col.cpu().numpy(), pcol)
+    # squared norms: bitwise those of the dense CSR sketch, close to the oracle's
+    dense = gpu.csk_sketch_csr(rp, col, val, n, b, d, 29)
+    torch.cuda.synchronize()
+    assert torch.equal(sk.nu2, dense.nu2)
+    np.testing.assert_allclose(sk.nu2.cpu().numpy(), orc.row_norms2(At), rtol=1e-13, atol=0)
+
+
+def test_sparse_sketch_full_size_sampled(gpu, orc):
+    # A 1e6 x 5000 at 0.1%, d = 50000: the whole sparse sketch against the
+    # oracle's dense one on 400 sampled rows (values and pattern), bt in full
+    c = W.config("sparse_csr")
+    s = W.sparse_csr(c["m"], c["n"], c["density"], c["seed"])
+    rp, col, val, b = _upload(s)
+    sk = gpu.csk_sketch_csr_sparse(rp, col, val, c["n"], b, c["d"], c["sketch_seed"])
+    At, bt = orc.sketch_csr(s.row_ptr, s.col, s.val, s.m, s.n, s.b, c["d"], c["sketch_seed"])
+    np.testing.assert_array_equal(sk.bt.cpu().numpy(), bt)
+    gp = sk.row_ptr.cpu().numpy()
+    gc = sk.col.cpu().numpy()
+    gv = sk.val.cpu().numpy()
+    for j in np.random.default_rng(1).choice(c["d"], 400, replace=False):
+        row = np.zeros(c["n"])
+        row[gc[gp[j]:gp[j + 1]]] = gv[gp[j]:gp[j + 1]]
+        np.testing.assert_array_equal(row, At[j])
+        assert np.all(np.diff(gc[gp[j]:gp[j + 1]]) > 0)
+    assert sk.nnz <= s.row_ptr[-1]
+
+
+def _system(orc, gpu, m, n, dens, d, seed):
+    s = W.sparse_csr(m, n, dens, seed=seed)
+    rp, col, val, b = _upload(s)
+    sk = gpu.csk_sketch_csr_sparse(rp, col, val, n, b, d, seed + 7)
+    At, bt = orc.sketch_csr(s.row_ptr, s.col, s.val, m, n, s.b, d, seed + 7)
+    return s, sk, At, bt
+
+
+@pytest.mark.parametrize("path,K", [("single", 1), ("single", 9), ("single", 70), ("grid", 1), ("grid", 9),
+                                    ("grid", 70)])
+def test_sparse_iterates_match_oracle(gpu, orc, path, K):
+    s, sk, At, bt = _system(orc, gpu, 30000, 400, 0.01, 3000, 41)
+    xs = torch.from_numpy(s.x_star).to(DEV)
+    kw = dict(single_wg=1) if path == "single" else dict(single_wg=0, grid=24)
+    r = gpu.csk_solve_csr(sk.row_ptr, sk.col, sk.val, s.n, sk.bt, nu2=sk.nu2, x_ref=xs, tol=0.0, maxit=K, **kw)
+    assert r.status == gpu.CSK_NOT_CONVERGED and r.iters == K
+    o = orc.mwrk(At, bt, xref=s.x_star, tol=0.0, maxit=K)
+    assert np.linalg.norm(r.x.cpu().numpy() - o.x) <= 1e-12 * np.linalg.norm(o.x)
+
+
+@pytest.mark.parametrize("path", ["single", "grid"])
+def test_sparse_converges_and_matches_oracle(gpu, orc, path):
+    s, sk, At, bt = _system(orc, gpu, 30000, 300, 0.01, 3000, 43)
+    xs = torch.from_numpy(s.x_star).to(DEV)
+    kw = dict(single_wg=1) if path == "single" else dict(single_wg=0)
+    r = gpu.csk_solve_csr(sk.row_ptr, sk.col, sk.val, s.n, sk.bt, nu2=sk.nu2, x_ref=xs, tol=1e-10, maxit=200000,
+                          **kw)
+    assert r.status == gpu.CSK_OK
+    rel = np.linalg.norm(r.x.cpu().numpy() - s.x_star) / np.linalg.norm(s.x_star)
+    assert rel <= 1e-10
+    o = orc.mwrk(At, bt, xref=s.x_star, tol=1e-10, maxit=200000)
+    assert o.status == 0
+    assert np.linalg.norm(r.x.cpu().numpy() - o.x) <= 3e-10 * np.linalg.norm(s.x_star)
+    assert abs(r.iters - o.iters) <= max(5, 0.1 * o.iters), (r.iters, o.iters)
+
+
+def test_sparse_residual_mode_norms_computed_and_x0(gpu, orc):
+    s, sk, At, bt = _system(orc, gpu, 20000, 250, 0.01, 2500, 47)
+    x0 = torch.randn(s.n, dtype=torch.float64, generator=torch.Generator().manual_seed(5)).to(DEV)
+    r = gpu.csk_solve_csr(sk.row_ptr, sk.col, sk.val, s.n, sk.bt, x0=x0, tol=1e-9, maxit=200000,
+                          stop_mode=gpu.CSK_STOP_REL_RESID, single_wg=0)
+    assert r.status == gpu.CSK_OK
+    x = r.x.cpu().numpy()
+    assert np.linalg.norm(bt - At @ x) <= 1e-9 * np.linalg.norm(bt) * (1 + 1e-6)
+    # first steps from x0, with the norms computed by the library, agree with the oracle's
+    r1 = gpu.csk_solve_csr(sk.row_ptr, sk.col, sk.val, s.n, sk.bt, x0=x0, tol=0.0, maxit=5,
+                           stop_mode=gpu.CSK_STOP_REL_RESID, single_wg=0)
+    o = orc.mwrk(At, bt, x0=x0.cpu().numpy(), tol=0.0, maxit=5, stop_mode=orc.STOP_REL_RESID)
+    assert np.linalg.norm(r1.x.cpu().numpy() - o.x) <= 1e-12 * np.linalg.norm(o.x)
+
+
+def test_sparse_status_paths(gpu):
+    rp = torch.tensor([0, 2, 2, 3], dtype=torch.int64, device=DEV)
+    col = torch.tensor([0, 2, 1], dtype=torch.int32, device=DEV)
+    val = torch.tensor([1.0, 2.0, -1.0], dtype=torch.float64, device=DEV)
+    bt = torch.tensor([1.0, 0.5, 2.0], dtype=torch.float64, device=DEV)
+    # consistent system with an empty row: converges
+    r = gpu.csk_solve_csr(rp, col, val, 3, bt[[0, 0, 2]] * torch.tensor([1.0, 0.0, 1.0], device=DEV,
+                                                                       dtype=torch.float64),
+                          tol=1e-12, maxit=10000, stop_mode=gpu.CSK_STOP_REL_RESID)
+    assert r.status == gpu.CSK_OK
+    # all stored values zero: nothing can be selected
+    r = gpu.csk_solve_csr(rp, col, torch.zeros_like(val), 3, bt, tol=1e-12, maxit=100,
+                          stop_mode=gpu.CSK_STOP_REL_RESID)
+    assert r.status == gpu.CSK_ERR_DEGENERATE
+    # row pointers that disagree with nnz
+    bad = torch.tensor([0, 2, 2, 2], dtype=torch.int64, device=DEV)
+    r = gpu.csk_solve_csr(bad, col, val, 3, bt, tol=1e-12, maxit=100, stop_mode=gpu.CSK_STOP_REL_RESID)
+    assert r.status == gpu.CSK_ERR_INVALID_ARG
+    # maxit
+    r = gpu.csk_solve_csr(rp, col, val, 3, bt, tol=0.0, maxit=3, stop_mode=gpu.CSK_STOP_REL_RESID)
+    assert r.status == gpu.CSK_NOT_CONVERGED and r.iters == 3
+
+
+def test_sparse_full_size_converges(gpu):
+    # the C4-shaped system: A 1e6 x 5000 CSR at 0.1%, d = 50000, FP64 loop
+    # on the sparse sketch to relative error 1e-8 against x*
+    c = W.config("sparse_csr")
+    s = W.sparse_csr(c["m"], c["n"], c["density"], c["seed"])
+    rp, col, val, b = _upload(s)
+    sk = gpu.csk_sketch_csr_sparse(rp, col, val, c["n"], b, c["d"], c["sketch_seed"])
+    xs = torch.from_numpy(s.x_star).to(DEV)
+    r = gpu.csk_solve_csr(sk.row_ptr, sk.col, sk.val, c["n"], sk.bt, nu2=sk.nu2, x_ref=xs, tol=c["tol"],
+                          maxit=c["maxit"])
+    assert r.status == gpu.CSK_OK
+    assert ((r.x - xs).norm() / xs.norm()).item() <= c["tol"]
+    print(f"sparse_csr iterations {r.iters}")
