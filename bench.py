@@ -94,6 +94,12 @@ def main_workload(args, P, W, torch):
     P.lib.csk_solve_workspace_size(d, n, P.CSK_F64, ctypes.byref(nb))
     ws = torch.empty(nb.value + 512, dtype=torch.uint8, device=dev)
     ws = ws[(-ws.data_ptr()) % 256:]
+    sk_out = P.SketchOut(torch.empty((d, n), dtype=torch.float64, device=dev), None,
+                         torch.empty(d, dtype=torch.float64, device=dev),
+                         torch.empty(d, dtype=torch.float64, device=dev), None, None)
+    P.lib.csk_sketch_workspace_size(m, n, d, 1, ctypes.byref(nb))
+    sk_ws = torch.empty(nb.value + 512, dtype=torch.uint8, device=dev)
+    sk_ws = sk_ws[(-sk_ws.data_ptr()) % 256:]
 
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     sk_ms, sv_ms = [], []
@@ -101,7 +107,7 @@ def main_workload(args, P, W, torch):
     def step(record):
         if record:
             ev[0].record()
-        sk = P.csk_sketch(s.A, s.b, d, c["sketch_seed"])
+        sk = P.csk_sketch(s.A, s.b, d, c["sketch_seed"], out=sk_out, workspace=sk_ws)
         if record:
             ev[1].record()
         P.csk_solve(sk.At64, sk.bt, nu2=sk.nu2, x_ref=s.x_star, tol=c["tol"], maxit=c["maxit"],

@@ -98,22 +98,35 @@ class SketchOut:
 
 def csk_sketch(A: torch.Tensor, b: Optional[torch.Tensor], d: int, seed: int, *,
                lp_dtype: Optional[torch.dtype] = None, want_f64: bool = True,
-               want_perm: bool = False, stream=None) -> SketchOut:
+               want_perm: bool = False, out: Optional[SketchOut] = None,
+               workspace: Optional[torch.Tensor] = None, stream=None) -> SketchOut:
     """At = S A and bt = S b (Algorithm 1, Initialize).
 
     A: m x n, float64 or float32, row-major.  b: m (vector) or m x nrhs,
-    float64, or None.  lp_dtype: also return the low-precision copy."""
+    float64, or None.  lp_dtype: also return the low-precision copy.
+    out: a SketchOut of the same shapes to write into (no allocation);
+    workspace: a uint8 tensor of at least csk_sketch_workspace_size bytes,
+    256-byte aligned."""
     _need_cuda(A, "A")
     if A.dtype not in (torch.float64, torch.float32):
         raise ValueError("A must be float64 or float32")
     lda = _rowmajor(A, "A")
     m, n = A.shape
     dev = A.device
-    At64 = torch.empty((d, n), dtype=torch.float64, device=dev) if want_f64 else None
-    At_lp = torch.empty((d, n), dtype=lp_dtype, device=dev) if lp_dtype is not None else None
+    if out is not None:
+        At64, At_lp, nu2, perm, ptr = out.At64, out.At_lp, out.nu2, out.perm, out.ptr
+        if (At64 is None and At_lp is None) or nu2 is None:
+            raise ValueError("out needs nu2 and At64 or At_lp")
+        if lp_dtype is None and At_lp is not None:
+            lp_dtype = At_lp.dtype
+    else:
+        At64 = torch.empty((d, n), dtype=torch.float64, device=dev) if want_f64 else None
+        At_lp = torch.empty((d, n), dtype=lp_dtype, device=dev) if lp_dtype is not None else None
+        nu2 = torch.empty(d, dtype=torch.float64, device=dev)
+        perm = torch.empty(m, dtype=torch.int32, device=dev) if want_perm else None
+        ptr = torch.empty(d + 1, dtype=torch.int32, device=dev) if want_perm else None
     if At64 is None and At_lp is None:
         raise ValueError("nothing to compute")
-    nu2 = torch.empty(d, dtype=torch.float64, device=dev)
     B = bt = None
     nrhs, ldb, ldbt = 0, 1, 1
     if b is not None:
@@ -123,19 +136,22 @@ def csk_sketch(A: torch.Tensor, b: Optional[torch.Tensor], d: int, seed: int, *,
         if b.dim() == 1:
             B = b.contiguous()
             nrhs, ldb = 1, 1
-            bt = torch.empty(d, dtype=torch.float64, device=dev)
+            bt = out.bt if out is not None else torch.empty(d, dtype=torch.float64, device=dev)
             ldbt = 1
         else:
             B = b
             nrhs = b.shape[1]
             ldb = _rowmajor(b, "b")
-            bt = torch.empty((d, nrhs), dtype=torch.float64, device=dev)
+            bt = out.bt if out is not None else torch.empty((d, nrhs), dtype=torch.float64, device=dev)
             ldbt = nrhs
-    perm = torch.empty(m, dtype=torch.int32, device=dev) if want_perm else None
-    ptr = torch.empty(d + 1, dtype=torch.int32, device=dev) if want_perm else None
-    nbytes = ctypes.c_size_t(0)
-    _check(_lib.csk_sketch_workspace_size(m, n, d, nrhs, ctypes.byref(nbytes)), "csk_sketch_workspace_size")
-    ws = _workspace(nbytes.value, dev)
+        if bt is None:
+            raise ValueError("out needs bt when b is given")
+    if workspace is not None:
+        ws = workspace
+    else:
+        nbytes = ctypes.c_size_t(0)
+        _check(_lib.csk_sketch_workspace_size(m, n, d, nrhs, ctypes.byref(nbytes)), "csk_sketch_workspace_size")
+        ws = _workspace(nbytes.value, dev)
     lp_code = _TORCH_TO_CSK[lp_dtype] if lp_dtype is not None else CSK_F64
     _check(_lib.csk_sketch(_ptr(A), _TORCH_TO_CSK[A.dtype], m, n, lda, _ptr(B), nrhs, ldb, d,
                            ctypes.c_uint64(seed & (2**64 - 1)),

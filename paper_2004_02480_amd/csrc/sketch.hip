@@ -29,7 +29,8 @@ constexpr int kSortCap = 512;     // longest segment sorted by one wavefront in 
 constexpr int kScanTile = 4096;   // counts per block in the scan (256 threads x 16)
 
 struct Batch {
-    const SketchSys* sys;        // nsys descriptors (device)
+    const SketchSys* sys;        // nsys descriptors (device), when nsys > 1
+    SketchSys one;               // the descriptor itself, when nsys == 1
     const int64_t* row_offs;     // nsys+1 prefix over rows (device)
     const int64_t* bkt_offs;     // nsys+1 prefix over buckets
     const int64_t* task_offs;    // nsys+1 prefix over segsum tasks
@@ -41,6 +42,11 @@ struct Batch {
     int64_t M, D, T;
     int32_t nsys;
 };
+
+__device__ __forceinline__ const SketchSys& sys_at(const Batch& b, int s)
+{
+    return b.nsys == 1 ? b.one : b.sys[s];
+}
 
 // Largest s with offs[s] <= g (offs[0] = 0, strictly increasing).
 __device__ __forceinline__ int find_sys(const int64_t* offs, int nsys, int64_t g)
@@ -65,7 +71,7 @@ __global__ __launch_bounds__(256) void k_hash_hist(Batch b)
     for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < b.M;
          g += (int64_t)gridDim.x * blockDim.x) {
         const int s = b.nsys == 1 ? 0 : find_sys(b.row_offs, b.nsys, g);
-        const SketchSys& S = b.sys[s];
+        const SketchSys& S = sys_at(b, s);
         const uint64_t w = draw_word(S.seed, static_cast<uint64_t>(g - S.row_off));
         atomicAdd(&b.cnt[S.bkt_off + draw_bucket(w, static_cast<uint32_t>(S.d))], 1u);
     }
@@ -150,12 +156,61 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__
     }
 }
 
+// The whole exclusive scan in one block when the counts are few: wave w of
+// 16 holds a contiguous segment of ceil(D / 16) counts in registers (lane l
+// has elements l, l + 64, ...), so every load is issued at once and
+// coalesced; the wave totals are scanned in LDS, then each wave scans its
+// 64-element slices in order with a running carry.
+constexpr int kScanRegs = 32;
+constexpr int64_t kScanSingleMax = 16 * 64 * kScanRegs;
+__global__ __launch_bounds__(1024) void k_scan_single(const uint32_t* __restrict__ cnt, int64_t D,
+                                                     uint32_t* __restrict__ ptr)
+{
+    __shared__ uint32_t wtot[16];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+    const int64_t seg = (D + 15) / 16;
+    const int64_t lo = min<int64_t>(D, w * seg), hi = min<int64_t>(D, lo + seg);
+    uint32_t v[kScanRegs];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < kScanRegs; ++i) {
+        const int64_t j = lo + i * kWave + lane;
+        v[i] = j < hi ? cnt[j] : 0u;
+        sum += v[i];
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, kWave);
+    if (lane == 0) wtot[w] = sum;
+    __syncthreads();
+    uint32_t carry = 0, total = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const uint32_t t = wtot[k];
+        if (k < w) carry += t;
+        total += t;
+    }
+#pragma unroll
+    for (int i = 0; i < kScanRegs; ++i) {
+        uint32_t x = v[i];
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t t = __shfl_up(x, off, kWave);
+            if (lane >= off) x += t;
+        }
+        const int64_t j = lo + i * kWave + lane;
+        if (j < hi) ptr[j] = carry + x - v[i];
+        carry += __shfl(x, kWave - 1, kWave);
+    }
+    if (threadIdx.x == 0) ptr[D] = total;
+}
+
 __global__ __launch_bounds__(256) void k_scatter(Batch b)
 {
     for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < b.M;
          g += (int64_t)gridDim.x * blockDim.x) {
         const int s = b.nsys == 1 ? 0 : find_sys(b.row_offs, b.nsys, g);
-        const SketchSys& S = b.sys[s];
+        const SketchSys& S = sys_at(b, s);
         const uint64_t i = static_cast<uint64_t>(g - S.row_off);
         const int64_t gb = S.bkt_off + draw_bucket(draw_word(S.seed, i), static_cast<uint32_t>(S.d));
         // Counting down through cnt leaves it zero; the order inside the
@@ -209,7 +264,7 @@ __global__ __launch_bounds__(256) void k_long_segments(Batch b)
         const uint32_t len = b.ptr[gb + 1] - beg;
         if (len <= (uint32_t)kSortCap) continue;
         const int s = b.nsys == 1 ? 0 : find_sys(b.bkt_offs, b.nsys, gb);
-        const SketchSys& S = b.sys[s];
+        const SketchSys& S = sys_at(b, s);
         const uint32_t j = static_cast<uint32_t>(gb - S.bkt_off);
         uint32_t running = 0;
         for (int64_t base = 0; base < S.m; base += 256) {
@@ -289,7 +344,7 @@ __global__ __launch_bounds__(256) void k_segsum(Batch b)
     const int64_t nwaves = (int64_t)gridDim.x * 4;
     for (int64_t t = blockIdx.x * 4 + threadIdx.x / kWave; t < b.T; t += nwaves) {
         const int s = b.nsys == 1 ? 0 : find_sys(b.task_offs, b.nsys, t);
-        const SketchSys& S = b.sys[s];
+        const SketchSys& S = sys_at(b, s);
         const int64_t lt = t - S.task_off;
         const int64_t j = lt / S.nchunks;
         const int c = static_cast<int>(lt - j * S.nchunks);
@@ -373,7 +428,7 @@ __global__ void k_nu2_finalize(Batch b)
     for (int64_t gb = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; gb < b.D;
          gb += (int64_t)gridDim.x * blockDim.x) {
         const int s = b.nsys == 1 ? 0 : find_sys(b.bkt_offs, b.nsys, gb);
-        const SketchSys& S = b.sys[s];
+        const SketchSys& S = sys_at(b, s);
         if (S.nchunks <= 1 || S.nu2 == nullptr) continue;
         const int64_t j = gb - S.bkt_off;
         double acc = 0.0;
@@ -429,7 +484,7 @@ __global__ __launch_bounds__(kCsrNT) void k_segsum_csr(Batch b, const int64_t* _
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wid = tid / kWave;
-    const SketchSys S = b.sys[0];
+    const SketchSys S = sys_at(b, 0);
     const int n = S.n;
     for (int64_t j = blockIdx.x; j < S.d; j += gridDim.x) {
         const uint32_t beg = b.ptr[j], end = b.ptr[j + 1];
@@ -647,15 +702,18 @@ Geometry pick_geometry(int64_t n_max, csk_dtype a_dtype, bool vec_ok)
 {
     const int vw = vec_ok ? (a_dtype == CSK_F64 ? 2 : 4) : 1;
     const int64_t per_vpl = (int64_t)kWave * vw;
-    int vpl = static_cast<int>(std::min<int64_t>(4, (n_max + per_vpl - 1) / per_vpl));
+    // up to 8 vectors per lane: a row of up to 1024 FP64 (2048 FP32) columns
+    // is one chunk, so the squared norm needs no second pass
+    int vpl = static_cast<int>(std::min<int64_t>(8, (n_max + per_vpl - 1) / per_vpl));
     if (vpl == 3) vpl = 4;
+    if (vpl > 4) vpl = 8;
     return {vw, std::max(1, vpl)};
 }
 
 template <class TA, int VW, int VPL, int LP>
 void launch_segsum_lp(const Batch& b, hipStream_t st)
 {
-    constexpr int D = (VPL >= 4) ? 4 : 8;  // rows in flight per wavefront
+    constexpr int D = VPL >= 8 ? 2 : VPL >= 4 ? 4 : 8;  // rows in flight per wavefront (16 KB of FP64)
     k_segsum<TA, VW, VPL, D, LP><<<grid_for(b.T, 4, 1 << 20), 256, 0, st>>>(b);
 }
 
@@ -676,7 +734,8 @@ void launch_segsum_vw(const Batch& b, int vpl, csk_dtype lp, hipStream_t st)
     switch (vpl) {
     case 1: launch_segsum_vpl<TA, VW, 1>(b, lp, st); break;
     case 2: launch_segsum_vpl<TA, VW, 2>(b, lp, st); break;
-    default: launch_segsum_vpl<TA, VW, 4>(b, lp, st); break;
+    case 4: launch_segsum_vpl<TA, VW, 4>(b, lp, st); break;
+    default: launch_segsum_vpl<TA, VW, 8>(b, lp, st); break;
     }
 }
 
@@ -691,22 +750,36 @@ void launch_segsum(const Batch& b, csk_dtype a_dtype, Geometry g, csk_dtype lp, 
     }
 }
 
+// ptr[0 .. D] = exclusive scan of cnt[0 .. D) (ptr[D] = total): one block for
+// few counts, else per-tile sums, a scan of those, and the tiles' scans.
+csk_status exclusive_scan(const uint32_t* cnt, int64_t D, uint32_t* part, uint32_t* ptr, hipStream_t st)
+{
+    if (D <= kScanSingleMax) {
+        k_scan_single<<<1, 1024, 0, st>>>(cnt, D, ptr);
+        CSK_LAUNCH_CHECK("k_scan_single");
+        return CSK_OK;
+    }
+    const int nb_scan = static_cast<int>((D + kScanTile - 1) / kScanTile);
+    k_scan_reduce<<<nb_scan, 256, 0, st>>>(cnt, D, part);
+    CSK_LAUNCH_CHECK("k_scan_reduce");
+    k_scan_top<<<1, 1024, 0, st>>>(part, nb_scan, ptr, D);
+    CSK_LAUNCH_CHECK("k_scan_top");
+    k_scan_apply<<<nb_scan, 256, 0, st>>>(cnt, D, part, ptr);
+    CSK_LAUNCH_CHECK("k_scan_apply");
+    return CSK_OK;
+}
+
 // Hash, count, scan, scatter and sort: afterwards perm[ptr[gb] .. ptr[gb+1])
 // lists the rows of global bucket gb in ascending order.
 csk_status group_rows(const Batch& b, hipStream_t st)
 {
     const int64_t M = b.M, D = b.D;
-    const int nb_scan = static_cast<int>((D + kScanTile - 1) / kScanTile);
     k_fill_u32<<<grid_for(D, 256, 4096), 256, 0, st>>>(b.cnt, D, 0u);
     CSK_LAUNCH_CHECK("k_fill_u32");
     k_hash_hist<<<grid_for(M, 256, 16384), 256, 0, st>>>(b);
     CSK_LAUNCH_CHECK("k_hash_hist");
-    k_scan_reduce<<<nb_scan, 256, 0, st>>>(b.cnt, D, b.scan_part);
-    CSK_LAUNCH_CHECK("k_scan_reduce");
-    k_scan_top<<<1, 1024, 0, st>>>(b.scan_part, nb_scan, b.ptr, D);
-    CSK_LAUNCH_CHECK("k_scan_top");
-    k_scan_apply<<<nb_scan, 256, 0, st>>>(b.cnt, D, b.scan_part, b.ptr);
-    CSK_LAUNCH_CHECK("k_scan_apply");
+    csk_status r = exclusive_scan(b.cnt, D, b.scan_part, b.ptr, st);
+    if (r != CSK_OK) return r;
     k_scatter<<<grid_for(M, 256, 16384), 256, 0, st>>>(b);
     CSK_LAUNCH_CHECK("k_scatter");
     k_sort_segments<<<grid_for(D, 4, 8192), 256, 0, st>>>(b);
@@ -832,7 +905,7 @@ csk_status sketch_run(const SketchJob* jobs, int32_t nsys, csk_dtype a_dtype, cs
     }
 
     Carve c(ws);
-    Batch b;
+    Batch b{};
     SketchSys* d_sys = c.take<SketchSys>(nsys);
     SketchSys* d_sys_b = c.take<SketchSys>(nsys);
     int64_t* d_row = c.take<int64_t>(nsys + 1);
@@ -858,7 +931,8 @@ csk_status sketch_run(const SketchJob* jobs, int32_t nsys, csk_dtype a_dtype, cs
     b.nsys = nsys;
 
     csk_status r;
-    if ((r = upload_descs(hs, d_sys, st)) != CSK_OK) return r;
+    if (nsys == 1) b.one = hs[0];
+    else if ((r = upload_descs(hs, d_sys, st)) != CSK_OK) return r;
     if (nsys > 1) {
         if ((r = upload_offs(row_offs, d_row, st)) != CSK_OK) return r;
         if ((r = upload_offs(bkt_offs, d_bkt, st)) != CSK_OK) return r;
@@ -902,9 +976,10 @@ csk_status sketch_run(const SketchJob* jobs, int32_t nsys, csk_dtype a_dtype, cs
             set_error("internal: right-hand-side task space exceeds workspace");
             return CSK_ERR_UNSUPPORTED;
         }
-        if ((r = upload_descs(hb, d_sys_b, st)) != CSK_OK) return r;
-        if (nsys > 1 && (r = upload_offs(toffs, d_task_b, st)) != CSK_OK) return r;
         Batch bb = b;
+        if (nsys == 1) bb.one = hb[0];
+        else if ((r = upload_descs(hb, d_sys_b, st)) != CSK_OK) return r;
+        if (nsys > 1 && (r = upload_offs(toffs, d_task_b, st)) != CSK_OK) return r;
         bb.sys = d_sys_b;
         bb.task_offs = d_task_b;
         bb.T = TB;
@@ -964,8 +1039,7 @@ csk_status csr_setup(const double* b, double* bt, double* nu2, int64_t m, int64_
     bt_.D = d;
     bt_.T = d;
     bt_.nsys = 1;
-    csk_status r;
-    if ((r = upload_descs(hs, d_sys, st)) != CSK_OK) return r;
+    bt_.one = hs[0];
     return group_rows(bt_, st);
 }
 
@@ -1028,13 +1102,7 @@ csk_status sketch_csr_sparse_run(const int64_t* row_ptr, const int32_t* col, con
     k_csr_distinct<<<grid_for(d, kDistinctWaves, 1 << 16), kDistinctWaves * kWave, shm, st>>>(bt_, row_ptr, col,
                                                                                              nwords, bt_.cnt);
     CSK_LAUNCH_CHECK("k_csr_distinct");
-    const int nb_scan = static_cast<int>((d + kScanTile - 1) / kScanTile);
-    k_scan_reduce<<<nb_scan, 256, 0, st>>>(bt_.cnt, d, bt_.scan_part);
-    CSK_LAUNCH_CHECK("k_scan_reduce");
-    k_scan_top<<<1, 1024, 0, st>>>(bt_.scan_part, nb_scan, ofs, d);
-    CSK_LAUNCH_CHECK("k_scan_top");
-    k_scan_apply<<<nb_scan, 256, 0, st>>>(bt_.cnt, d, bt_.scan_part, ofs);
-    CSK_LAUNCH_CHECK("k_scan_apply");
+    if ((r = exclusive_scan(bt_.cnt, d, bt_.scan_part, ofs, st)) != CSK_OK) return r;
     const CsrOut so{ofs, at_rp, at_col, at_val};
     return launch_segsum_csr<0, true>(bt_, row_ptr, col, val, n, d, so, st);
 }
