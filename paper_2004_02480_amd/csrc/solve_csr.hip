@@ -28,6 +28,8 @@ constexpr int kNT = 512;
 constexpr int kNW = kNT / kWave;
 constexpr int kU = 8;                    // streamed entries per lane in flight
 constexpr int kUL = 4;                   // resident entries per lane per LDS round
+constexpr int kKR = 3;                   // register-resident rows per lane group
+constexpr int kJ = 8;                    // register-resident entries per lane and row
 constexpr size_t kLdsReserve = 2048;     // static LDS of the kernel, rounded up
 enum : uint32_t {
     kFlagBadSplit = 8u,   // a row block larger than planned
@@ -163,6 +165,37 @@ __global__ __launch_bounds__(kNT) void k_solve_csr(CsrSolveSys S, CsrCtl C)
     const bool rel_err = S.stop_mode == CSK_STOP_REL_ERR;
     const double* __restrict__ gval = S.val + base;
     const int32_t* __restrict__ gcol = S.col + base;
+    // rsplit: rows [0, rsplit) of the block have all their entries in LDS.
+    // Group g holds in registers, for the whole solve, its rows rsplit + g +
+    // kr * NG (kr < kKR) from their first entry past the LDS prefix: lane q
+    // has entries q + u * LPR (u < kJ); the rest of such a row is streamed.
+    // Slots past a row's end hold zero values with column 0.
+    int rsplit;
+    {
+        int lo = 0, hi = nr;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (lrp[mid + 1] > nres) hi = mid;
+            else lo = mid + 1;
+        }
+        rsplit = lo;
+    }
+    double rv[kKR][kJ];
+    int32_t rc[kKR][kJ];
+#pragma unroll
+    for (int kr = 0; kr < kKR; ++kr) {
+        const int lr = rsplit + g + kr * NG;
+        const bool on = lr < nr;
+        const int s0 = on ? max(lrp[lr], nres) : 0;
+        const int e = on ? lrp[lr + 1] : 0;
+#pragma unroll
+        for (int u = 0; u < kJ; ++u) {
+            const int p = s0 + q + u * LPR;
+            const bool ok = on && p < e;
+            rv[kr][u] = ok ? gval[p] : 0.0;
+            rc[kr][u] = ok ? gcol[p] : 0;
+        }
+    }
 
     int32_t status = CSK_NOT_CONVERGED;
     double meas = NAN;
@@ -170,27 +203,13 @@ __global__ __launch_bounds__(kNT) void k_solve_csr(CsrSolveSys S, CsrCtl C)
     for (;; ++k) {
         GridRed loc = red_identity();
         loc.flags = plan_flags;
-        // residuals of the block's rows: resident entries from LDS, the rest
-        // from memory kU per lane at a time (addresses clamped into the row,
-        // values masked)
-        for (int lr = g; lr < nr; lr += NG) {
-            const int s = lrp[lr], e = lrp[lr + 1];
-            const int em = min(e, nres);  // resident entries of the row: [s, em)
-            const int ps = max(s, nres);  // streamed entries: [ps, e)
-            double acc = 0.0;
-            // the first kU streamed entries per lane are requested before the
-            // resident ones are summed, so their latency overlaps LDS work
-            double v[kU];
-            int32_t cv[kU];
-            if (ps < e) {
-#pragma unroll
-                for (int u = 0; u < kU; ++u) {
-                    const int p = min(ps + q + u * LPR, e - 1);
-                    v[u] = gval[p];
-                    cv[u] = gcol[p];
-                }
-            }
-            for (int p0 = s + q; p0 < em; p0 += kUL * LPR) {
+        // residuals of the block's rows, in three parts: rows whose entries
+        // are all in LDS, then each group's kKR rows held in registers (with
+        // the LDS part of the row that straddles the resident prefix), then
+        // rows beyond those, streamed from memory kU entries per lane at a
+        // time (addresses clamped into the row, values masked)
+        auto lds_part = [&](int s0, int em, double acc) {
+            for (int p0 = s0 + q; p0 < em; p0 += kUL * LPR) {
                 double lv[kUL];
                 int lc[kUL];
 #pragma unroll
@@ -202,20 +221,24 @@ __global__ __launch_bounds__(kNT) void k_solve_csr(CsrSolveSys S, CsrCtl C)
 #pragma unroll
                 for (int u = 0; u < kUL; ++u) acc += (p0 + u * LPR < em) ? lv[u] * sx[lc[u]] : 0.0;
             }
-            if (ps < e) {
+            return acc;
+        };
+        auto stream_part = [&](int ps, int e, double acc) {
+            for (int p0 = ps + q; p0 < e; p0 += kU * LPR) {
+                double v[kU];
+                int32_t cv[kU];
 #pragma unroll
-                for (int u = 0; u < kU; ++u) acc += (ps + q + u * LPR < e) ? v[u] * sx[cv[u]] : 0.0;
-                for (int p0 = ps + q + kU * LPR; p0 < e; p0 += kU * LPR) {
-#pragma unroll
-                    for (int u = 0; u < kU; ++u) {
-                        const int p = min(p0 + u * LPR, e - 1);
-                        v[u] = gval[p];
-                        cv[u] = gcol[p];
-                    }
-#pragma unroll
-                    for (int u = 0; u < kU; ++u) acc += (p0 + u * LPR < e) ? v[u] * sx[cv[u]] : 0.0;
+                for (int u = 0; u < kU; ++u) {
+                    const int p = min(p0 + u * LPR, e - 1);
+                    v[u] = gval[p];
+                    cv[u] = gcol[p];
                 }
+#pragma unroll
+                for (int u = 0; u < kU; ++u) acc += (p0 + u * LPR < e) ? v[u] * sx[cv[u]] : 0.0;
             }
+            return acc;
+        };
+        auto finish = [&](int lr, double acc) {
             const double sum = group_sum_t<double, LPR>(acc);
             const int row = r0 + lr;
             const double r = lrhs[lr] - sum;
@@ -233,7 +256,21 @@ __global__ __launch_bounds__(kNT) void k_solve_csr(CsrSolveSys S, CsrCtl C)
             } else if (isnan(nn)) {
                 loc.flags |= kFlagNonfinite;
             }
+        };
+        for (int lr = g; lr < rsplit; lr += NG) finish(lr, lds_part(lrp[lr], lrp[lr + 1], 0.0));
+#pragma unroll
+        for (int kr = 0; kr < kKR; ++kr) {
+            const int lr = rsplit + g + kr * NG;
+            if (lr < nr) {
+                const int s0 = lrp[lr], e = lrp[lr + 1];
+                double acc = lds_part(s0, min(e, nres), 0.0);
+#pragma unroll
+                for (int u = 0; u < kJ; ++u) acc += rv[kr][u] * sx[rc[kr][u]];
+                finish(lr, stream_part(max(s0, nres) + kJ * LPR, e, acc));
+            }
         }
+        for (int lr = rsplit + g + kKR * NG; lr < nr; lr += NG)
+            finish(lr, stream_part(lrp[lr], lrp[lr + 1], 0.0));
         if (S.xref)
             for (int c = e0 + tid; c < e1; c += kNT) {
                 const double ex = sx[c] - sxr[c - e0];
@@ -351,16 +388,16 @@ int csr_solve_grid(int64_t d, int64_t nnz, const csk_solve_opts* o)
     return (int)std::max<int64_t>(1, std::min<int64_t>(grid, d));
 }
 
-// Lanes per row.  A lane group walks its rows one after another, and each
-// row costs at least one round trip to memory for its streamed entries, so
-// narrow groups (more rows in flight per workgroup) win until a row needs
-// several rounds of kU entries per lane.  At 100 entries per row 4 lanes
-// take 13.2 us per iteration against 14.0 (16 lanes) and 24.8 (64 lanes) on
-// the 1e6 x 5000, d = 50000 sketch.
+// Lanes per row: the narrowest group whose register rows (kJ entries per
+// lane) hold a mean row.  A lane group walks its rows one after another, so
+// narrow groups keep more rows in flight per workgroup; on the 1e6 x 5000,
+// d = 50000 sketch (100 entries per row) 16 lanes take 12.3 us per
+// iteration against 14.4 (4 lanes, rows overflowing the registers) and 22.9
+// (64 lanes).
 int csr_solve_lpr(int64_t d, int64_t nnz)
 {
     const int64_t mean = (nnz + d - 1) / std::max<int64_t>(d, 1);
-    return mean <= 128 ? 4 : mean <= 512 ? 16 : 64;
+    return mean <= 4 * kJ ? 4 : mean <= 16 * kJ ? 16 : 64;
 }
 
 size_t csr_solve_ws_bytes(int64_t d, int grid)
