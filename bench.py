@@ -274,16 +274,12 @@ def mrhs_workload(P, W, torch):
 
 # Section 3, Table 1: the paper's means over 50 trials (MATLAB, unstated
 # CPU): (m, n) -> (CSK iterations, MWRK iterations, CSK s, MWRK s).
-TABLE1_PAPER = {
-    (300000, 50): (54.90, 31.0, 0.2209, 1.6878), (300000, 100): (94.86, 63.0, 0.4569, 5.1097),
-    (300000, 150): (132.76, 96.0, 1.4894, 10.3728), (400000, 50): (54.36, 29.0, 0.2597, 1.9737),
-    (400000, 100): (95.14, 60.0, 0.5778, 6.0903), (400000, 150): (132.56, 94.0, 1.8509, 13.1016),
-    (500000, 50): (55.10, 29.0, 0.3312, 2.5878), (500000, 100): (94.96, 60.0, 0.7366, 8.2903),
-    (500000, 150): (132.54, 91.0, 2.0513, 17.3091), (600000, 50): (54.88, 28.0, 0.4053, 3.1672),
-    (600000, 100): (95.16, 58.0, 0.8566, 10.2019), (600000, 150): (132.58, 92.0, 2.3828, 22.0388),
-    (700000, 50): (54.70, 29.0, 0.4550, 3.9312), (700000, 100): (95.42, 58.0, 1.0025, 12.2144),
-    (700000, 150): (132.36, 89.0, 2.7194, 25.7228),
-}
+def table1_paper():
+    """The printed means of Section 3, Table 1 (tests/golden/table1.json):
+    (m, n) -> (CSK IT, MWRK IT, CSK CPU s, MWRK CPU s)."""
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "table1.json")) as f:
+        rows = json.load(f)["rows"]
+    return {(r["m"], r["n"]): (r["csk_it"], r["mwrk_it"], r["csk_cpu_s"], r["mwrk_cpu_s"]) for r in rows}
 
 
 def table1_workload(P, W, torch, trials=5):
@@ -292,6 +288,7 @@ def table1_workload(P, W, torch, trials=5):
     and times over `trials` seeded draws per shape."""
     c = W.config("table1")
     dev = "cuda:0"
+    paper = table1_paper()
     rows = []
     for m in c["ms"]:
         for n in c["ns"]:
@@ -325,7 +322,7 @@ def table1_workload(P, W, torch, trials=5):
                 t_m.append(tm)
                 del s
             mean = lambda v: sum(v) / len(v)
-            pc, pm, pct, pmt = TABLE1_PAPER[(m, n)]
+            pc, pm, pct, pmt = paper[(m, n)]
             row = dict(m=m, n=n, d=d, csk_it=mean(it_c), mwrk_it=mean(it_m), csk_s=mean(t_c), mwrk_s=mean(t_m),
                        it_speedup=mean(it_m) / mean(it_c), time_speedup=mean(t_m) / mean(t_c),
                        paper_csk_it=pc, paper_mwrk_it=pm, paper_time_speedup=pmt / pct)
