@@ -81,14 +81,14 @@ template <> struct Elem<tag_f64> {
     using S = double;
     using Acc = double;
     static constexpr int kVec = 2;
-    template <int VW> __device__ static double dot(const uint4& v, const double* x, int lim)
+    template <int VW, bool M> __device__ static double dot(const uint4& v, const double* x, int lim)
     {
         if constexpr (VW == 1) {
             const double a = __builtin_bit_cast(double, make_uint2(v.x, v.y));
-            return (lim > 0 ? a : 0.0) * x[0];
+            return (!M || lim > 0 ? a : 0.0) * x[0];
         } else {
             const double2 a = __builtin_bit_cast(double2, v);
-            return (lim > 0 ? a.x : 0.0) * x[0] + (lim > 1 ? a.y : 0.0) * x[1];
+            return (!M || lim > 0 ? a.x : 0.0) * x[0] + (!M || lim > 1 ? a.y : 0.0) * x[1];
         }
     }
 };
@@ -96,26 +96,26 @@ template <> struct Elem<tag_f32> {
     using S = float;
     using Acc = float;
     static constexpr int kVec = 4;
-    template <int VW> __device__ static float dot(const uint4& v, const float* x, int lim)
+    template <int VW, bool M> __device__ static float dot(const uint4& v, const float* x, int lim)
     {
-        if constexpr (VW == 1) return (lim > 0 ? __uint_as_float(v.x) : 0.f) * x[0];
-        return (lim > 0 ? __uint_as_float(v.x) : 0.f) * x[0] + (lim > 1 ? __uint_as_float(v.y) : 0.f) * x[1] +
-               (lim > 2 ? __uint_as_float(v.z) : 0.f) * x[2] + (lim > 3 ? __uint_as_float(v.w) : 0.f) * x[3];
+        if constexpr (VW == 1) return (!M || lim > 0 ? __uint_as_float(v.x) : 0.f) * x[0];
+        return (!M || lim > 0 ? __uint_as_float(v.x) : 0.f) * x[0] + (!M || lim > 1 ? __uint_as_float(v.y) : 0.f) * x[1] +
+               (!M || lim > 2 ? __uint_as_float(v.z) : 0.f) * x[2] + (!M || lim > 3 ? __uint_as_float(v.w) : 0.f) * x[3];
     }
 };
 template <class Tag> struct Elem16 {
     using S = uint16_t;
     using Acc = float;
     static constexpr int kVec = 8;
-    template <int VW> __device__ static float dot(const uint4& v, const float* x, int lim)
+    template <int VW, bool M> __device__ static float dot(const uint4& v, const float* x, int lim)
     {
-        if constexpr (VW == 1) return (lim > 0 ? widen<Tag>(static_cast<uint16_t>(v.x & 0xFFFFu)) : 0.f) * x[0];
+        if constexpr (VW == 1) return (!M || lim > 0 ? widen<Tag>(static_cast<uint16_t>(v.x & 0xFFFFu)) : 0.f) * x[0];
         const uint32_t w[4] = {v.x, v.y, v.z, v.w};
         float s = 0.f;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            s += (lim > 2 * k ? widen<Tag>(static_cast<uint16_t>(w[k] & 0xFFFFu)) : 0.f) * x[2 * k];
-            s += (lim > 2 * k + 1 ? widen<Tag>(static_cast<uint16_t>(w[k] >> 16)) : 0.f) * x[2 * k + 1];
+            s += (!M || lim > 2 * k ? widen<Tag>(static_cast<uint16_t>(w[k] & 0xFFFFu)) : 0.f) * x[2 * k];
+            s += (!M || lim > 2 * k + 1 ? widen<Tag>(static_cast<uint16_t>(w[k] >> 16)) : 0.f) * x[2 * k + 1];
         }
         return s;
     }
@@ -228,7 +228,7 @@ __device__ __forceinline__ void ring_prime(Ring<Tag, kD>& R, const typename Elem
 // nseg*SW; rhs is bt (exact) or r_ref (inner).  When rout is non-null the
 // residuals are stored there (a refresh), and for the first nrow_out group
 // rows also in the LDS array lrout.
-template <class Tag, bool VEC, int LPR, int kD, bool ROUT>
+template <class Tag, bool VEC, int LPR, int kD, bool ROUT, bool M>
 __device__ __forceinline__ void stream_rows(const typename Elem<Tag>::S* __restrict__ A, int64_t lda, int n,
                                             int nseg, int r0, int r1, const typename Elem<Tag>::Acc* __restrict__ xs,
                                             const double* __restrict__ rhs, double* __restrict__ rout,
@@ -293,7 +293,7 @@ __device__ __forceinline__ void stream_rows(const typename Elem<Tag>::S* __restr
         const int l0 = c < nchunk ? n - cbase : 0;
 #pragma unroll
         for (int kk = 0; kk < KK; ++kk)
-            acc += E::template dot<VW>(slot[kk * kNT], xs + cbase + kk * LPR * VW, l0 - kk * LPR * VW);
+            acc += E::template dot<VW, M>(slot[kk * kNT], xs + cbase + kk * LPR * VW, l0 - kk * LPR * VW);
         if (cseg == nseg - 1) {
             const Acc s = group_sum_t<Acc, LPR>(acc);
             acc = Acc(0);
@@ -306,7 +306,7 @@ __device__ __forceinline__ void stream_rows(const typename Elem<Tag>::S* __restr
     auto consume = [&](const uint4 (&v)[KK], int lm, double p, double nn) {
         const int cbase = cseg * SW + q * VW;
 #pragma unroll
-        for (int kk = 0; kk < KK; ++kk) acc += E::template dot<VW>(v[kk], xs + cbase + kk * LPR * VW, lm - kk * LPR * VW);
+        for (int kk = 0; kk < KK; ++kk) acc += E::template dot<VW, M>(v[kk], xs + cbase + kk * LPR * VW, lm - kk * LPR * VW);
         if (cseg == nseg - 1) {
             const Acc s = group_sum_t<Acc, LPR>(acc);
             acc = Acc(0);
@@ -396,7 +396,7 @@ __host__ __device__ inline SolveLds solve_lds(int npad, bool mixed, int xslice, 
     return o;
 }
 
-template <class Tag, bool VEC, int LPR, bool GRID>
+template <class Tag, bool VEC, int LPR, bool GRID, bool M>
 __device__ __forceinline__ void solve_loop(const SolveSys& S, const Ctl& C, XRec* exch, int wg, int G, char* smem)
 {
     constexpr bool MIXED = !std::is_same<Tag, tag_f64>::value;
@@ -481,16 +481,16 @@ __device__ __forceinline__ void solve_loop(const SolveSys& S, const Ctl& C, XRec
             // the refresh product of the mixed mode runs once per window: a
             // shallower ring leaves the registers to the working-precision one
             // (it streams every chunk: the resident ones are low precision)
-            stream_rows<tag_f64, VEC, LPR, 2, true>(S.At64, S.ldat64, n, nseg64, r0, r1, sx, S.bt, S.rref, S.nu2,
+            stream_rows<tag_f64, VEC, LPR, 2, true, M>(S.At64, S.ldat64, n, nseg64, r0, r1, sx, S.bt, S.rref, S.nu2,
                                                     loc, none, lrhs, nrow_res);
         } else if (MIXED && exact) {
-            stream_rows<tag_f64, VEC, LPR, 2, false>(S.At64, S.ldat64, n, nseg64, r0, r1, sx, S.bt, nullptr, S.nu2,
+            stream_rows<tag_f64, VEC, LPR, 2, false, M>(S.At64, S.ldat64, n, nseg64, r0, r1, sx, S.bt, nullptr, S.nu2,
                                                      loc, none, nullptr, 0);
         } else if constexpr (!MIXED) {
-            stream_rows<tag_f64, VEC, LPR, ring_depth<tag_f64>(), false>(S.At64, S.ldat64, n, nseg64, r0, r1, sx,
+            stream_rows<tag_f64, VEC, LPR, ring_depth<tag_f64>(), false, M>(S.At64, S.ldat64, n, nseg64, r0, r1, sx,
                                                                          S.bt, nullptr, S.nu2, loc, res, nullptr, 0);
         } else {
-            stream_rows<Tag, VEC, LPR, ring_depth<Tag>(), false>(static_cast<const LPS*>(S.At), S.ldat, n, nseglp,
+            stream_rows<Tag, VEC, LPR, ring_depth<Tag>(), false, M>(static_cast<const LPS*>(S.At), S.ldat, n, nseglp,
                                                                  r0, r1, sd, S.rref, nullptr, S.nu2, loc, res,
                                                                  nullptr, 0);
         }
@@ -556,18 +556,23 @@ __device__ __forceinline__ void solve_loop(const SolveSys& S, const Ctl& C, XRec
     }
 }
 
-template <class Tag, bool VEC, int LPR>
+// M: per-element masks of the product.  Without them (n a multiple of the
+// vector width, vector path) every vector lies wholly before or wholly past
+// column n, and one past it multiplies the zero padding of the operand
+// vector, so only the discarded sums of lane groups without a row see
+// elements that the masks would have removed.
+template <class Tag, bool VEC, int LPR, bool M>
 __global__ __launch_bounds__(kNT) void k_solve_grid(SolveSys S, Ctl C)
 {
     extern __shared__ __align__(16) char smem[];
-    solve_loop<Tag, VEC, LPR, true>(S, C, C.exch, blockIdx.x, gridDim.x, smem);
+    solve_loop<Tag, VEC, LPR, true, M>(S, C, C.exch, blockIdx.x, gridDim.x, smem);
 }
 
-template <class Tag, bool VEC, int LPR>
+template <class Tag, bool VEC, int LPR, bool M>
 __global__ __launch_bounds__(kNT) void k_solve_single(SolveSys S, Ctl C)
 {
     extern __shared__ __align__(16) char smem[];
-    solve_loop<Tag, VEC, LPR, false>(S, C, nullptr, 0, 1, smem);
+    solve_loop<Tag, VEC, LPR, false, M>(S, C, nullptr, 0, 1, smem);
 }
 
 // Work items in queue order: queue position p owns items
@@ -598,9 +603,9 @@ __global__ __launch_bounds__(kNT) void k_solve_batched(const SolveSys* __restric
         const int parts = C.item_off[lo + 1] - C.item_off[lo];
         const SolveSys S = sys[C.order[lo]];
         if (parts == 1)
-            solve_loop<Tag, VEC, LPR, false>(S, C, nullptr, 0, 1, smem);
+            solve_loop<Tag, VEC, LPR, false, true>(S, C, nullptr, 0, 1, smem);
         else
-            solve_loop<Tag, VEC, LPR, true>(S, C, C.exch + C.exch_off[lo], item - C.item_off[lo], parts, smem);
+            solve_loop<Tag, VEC, LPR, true, true>(S, C, C.exch + C.exch_off[lo], item - C.item_off[lo], parts, smem);
         __syncthreads();
     }
 }
@@ -643,7 +648,7 @@ SolveLds plan_lds(int npad, int& xslice, int want, int& layers)
     return solve_lds(npad, mixed, xslice, L, NG, LAYER);
 }
 
-template <class Tag, bool VEC, int LPR>
+template <class Tag, bool VEC, int LPR, bool M>
 csk_status launch_solve(const SolveSys& S, Ctl C, int grid, hipStream_t st)
 {
     constexpr bool mixed = !std::is_same<Tag, tag_f64>::value;
@@ -661,14 +666,14 @@ csk_status launch_solve(const SolveSys& S, Ctl C, int grid, hipStream_t st)
         return CSK_ERR_UNSUPPORTED;
     }
     if (grid <= 1) {
-        auto kern = k_solve_single<Tag, VEC, LPR>;
+        auto kern = k_solve_single<Tag, VEC, LPR, M>;
         CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
         kern<<<1, kNT, shm, st>>>(S, C);
         CSK_LAUNCH_CHECK("k_solve_single");
         return CSK_OK;
     }
-    auto kern = k_solve_grid<Tag, VEC, LPR>;
+    auto kern = k_solve_grid<Tag, VEC, LPR, M>;
     CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
     int per_cu = 0;
@@ -686,21 +691,24 @@ csk_status launch_solve(const SolveSys& S, Ctl C, int grid, hipStream_t st)
     return CSK_OK;
 }
 
-template <class Tag, bool VEC>
+template <class Tag, bool VEC, bool M>
 csk_status dispatch_lpr(const SolveSys& S, const Ctl& C, const SolvePlan& p, hipStream_t st)
 {
     switch (p.lpr) {
-    case 4: return launch_solve<Tag, VEC, 4>(S, C, p.grid, st);
-    case 16: return launch_solve<Tag, VEC, 16>(S, C, p.grid, st);
-    default: return launch_solve<Tag, VEC, 64>(S, C, p.grid, st);
+    case 4: return launch_solve<Tag, VEC, 4, M>(S, C, p.grid, st);
+    case 16: return launch_solve<Tag, VEC, 16, M>(S, C, p.grid, st);
+    default: return launch_solve<Tag, VEC, 64, M>(S, C, p.grid, st);
     }
 }
 
 template <class Tag>
 csk_status dispatch_solve(const SolveSys& S, const Ctl& C, const SolvePlan& p, hipStream_t st)
 {
-    if (p.vw > 1) return dispatch_lpr<Tag, true>(S, C, p, st);
-    return dispatch_lpr<Tag, false>(S, C, p, st);
+    // whole vectors: n a multiple of the working type's vector width (and
+    // so of FP64's, for the refresh product)
+    if (p.vw > 1 && S.n % Elem<Tag>::kVec == 0) return dispatch_lpr<Tag, true, false>(S, C, p, st);
+    if (p.vw > 1) return dispatch_lpr<Tag, true, true>(S, C, p, st);
+    return dispatch_lpr<Tag, false, true>(S, C, p, st);
 }
 
 constexpr int kBatchLPR = 16;
