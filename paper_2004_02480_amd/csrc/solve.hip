@@ -80,6 +80,7 @@ template <class Tag> struct Elem;
 template <> struct Elem<tag_f64> {
     using S = double;
     using Acc = double;
+    using Op = double;  // element type of the operand vector in LDS
     static constexpr int kVec = 2;
     template <int VW, bool M> __device__ static double dot(const uint4& v, const double* x, int lim)
     {
@@ -95,6 +96,7 @@ template <> struct Elem<tag_f64> {
 template <> struct Elem<tag_f32> {
     using S = float;
     using Acc = float;
+    using Op = float;
     static constexpr int kVec = 4;
     template <int VW, bool M> __device__ static float dot(const uint4& v, const float* x, int lim)
     {
@@ -106,6 +108,7 @@ template <> struct Elem<tag_f32> {
 template <class Tag> struct Elem16 {
     using S = uint16_t;
     using Acc = float;
+    using Op = float;
     static constexpr int kVec = 8;
     template <int VW, bool M> __device__ static float dot(const uint4& v, const float* x, int lim)
     {
@@ -121,7 +124,48 @@ template <class Tag> struct Elem16 {
     }
 };
 template <> struct Elem<tag_f16> : Elem16<tag_f16> {};
-template <> struct Elem<tag_bf16> : Elem16<tag_bf16> {};
+// BF16: the operand (x - x_ref) is kept in LDS rounded to BF16 as well, and
+// the unmasked product of a 16-byte vector is four two-element dot
+// instructions (BF16 pairs, FP32 accumulation) instead of eight widenings
+// and eight FMAs.  Its rounding (relative 2^-9 of x - x_ref) is of the
+// order of the BF16 rows' own, and each refresh restarts from the exact
+// FP64 residual.
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+template <> struct Elem<tag_bf16> {
+    using S = uint16_t;
+    using Acc = float;
+    using Op = uint16_t;
+    static constexpr int kVec = 8;
+    template <int VW, bool M> __device__ static float dot(const uint4& v, const uint16_t* x, int lim)
+    {
+        if constexpr (VW == 1) {
+            return (!M || lim > 0 ? bf16_bits_to_f32(static_cast<uint16_t>(v.x & 0xFFFFu)) : 0.f) *
+                   bf16_bits_to_f32(x[0]);
+        } else if constexpr (!M) {
+            const uint4 xv = *reinterpret_cast<const uint4*>(x);
+            float s = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, v.x),
+                                                       __builtin_bit_cast(bf16x2_t, xv.x), 0.f, false);
+            s = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, v.y), __builtin_bit_cast(bf16x2_t, xv.y),
+                                                s, false);
+            s = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, v.z), __builtin_bit_cast(bf16x2_t, xv.z),
+                                                s, false);
+            return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, v.w),
+                                                   __builtin_bit_cast(bf16x2_t, xv.w), s, false);
+        } else {
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+            float s = 0.f;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                s += (lim > 2 * k ? bf16_bits_to_f32(static_cast<uint16_t>(w[k] & 0xFFFFu)) : 0.f) *
+                     bf16_bits_to_f32(x[2 * k]);
+                s += (lim > 2 * k + 1 ? bf16_bits_to_f32(static_cast<uint16_t>(w[k] >> 16)) : 0.f) *
+                     bf16_bits_to_f32(x[2 * k + 1]);
+            }
+            return s;
+        }
+    }
+};
+template <class Tag> constexpr bool op16() { return std::is_same<typename Elem<Tag>::Op, uint16_t>::value; }
 
 // Loads chunk slot `b` (KK vectors of one lane) of (row, seg), with the
 // row's right-hand side and squared norm.  Every load is issued, from a
@@ -230,7 +274,7 @@ __device__ __forceinline__ void ring_prime(Ring<Tag, kD>& R, const typename Elem
 // rows also in the LDS array lrout.
 template <class Tag, bool VEC, int LPR, int kD, bool ROUT, bool M>
 __device__ __forceinline__ void stream_rows(const typename Elem<Tag>::S* __restrict__ A, int64_t lda, int n,
-                                            int nseg, int r0, int r1, const typename Elem<Tag>::Acc* __restrict__ xs,
+                                            int nseg, int r0, int r1, const typename Elem<Tag>::Op* __restrict__ xs,
                                             const double* __restrict__ rhs, double* __restrict__ rout,
                                             const double* __restrict__ nu2, Red& loc, const ResLds& res,
                                             double* lrout, int nrow_out)
@@ -369,12 +413,14 @@ __device__ void fill_resident(const typename Elem<Tag>::S* __restrict__ A, int64
 // (mixed), this workgroup's slice of x_ref, then the resident right-hand
 // sides and norms and the resident chunks (16-byte aligned).
 struct SolveLds {
-    size_t sx, sd, sxr, lrhs, lnn, chunks, total;
+    size_t sx, sd, sdb, sxr, lrhs, lnn, chunks, total;
 };
 
 __host__ __device__ inline size_t al_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-__host__ __device__ inline SolveLds solve_lds(int npad, bool mixed, int xslice, int L, int ng, int layer_bytes)
+// mixed: x - x_ref in FP32 (4 bytes per element); op16: also its BF16 copy
+__host__ __device__ inline SolveLds solve_lds(int npad, bool mixed, int xslice, int L, int ng, int layer_bytes,
+                                              bool op16 = false)
 {
     SolveLds o;
     size_t at = 0;
@@ -382,6 +428,9 @@ __host__ __device__ inline SolveLds solve_lds(int npad, bool mixed, int xslice, 
     at += (size_t)npad * 8;
     o.sd = at;
     at += mixed ? (size_t)npad * 4 : 0;
+    at = al_up(at, 16);
+    o.sdb = at;
+    at += op16 ? (size_t)npad * 2 : 0;
     at = al_up(at, 8);
     o.sxr = at;
     at += (size_t)xslice * 8;
@@ -428,9 +477,11 @@ __device__ __forceinline__ void solve_loop(const SolveSys& S, const Ctl& C, XRec
     const int gmax_rows = rows_per > 0 ? (rows_per + NG - 1) / NG : 0;
     const int L = min(C.res_layers, gmax_rows * nseg_res);
 
-    const SolveLds lay = solve_lds(npad, MIXED, C.xslice, C.res_layers, NG, LAYER);
+    constexpr bool OP16 = op16<Tag>();
+    const SolveLds lay = solve_lds(npad, MIXED, C.xslice, C.res_layers, NG, LAYER, OP16);
     double* sx = reinterpret_cast<double*>(smem + lay.sx);   // x, FP64, zero past n
     LAcc* sd = reinterpret_cast<LAcc*>(smem + lay.sd);       // x - x_ref (mixed), zero past n
+    uint16_t* sdb = reinterpret_cast<uint16_t*>(smem + lay.sdb);  // its BF16 copy (OP16)
     double* sxr = reinterpret_cast<double*>(smem + lay.sxr); // x_ref[e0 .. e1)
     double* lrhs = reinterpret_cast<double*>(smem + lay.lrhs);
     double* lnn = reinterpret_cast<double*>(smem + lay.lnn);
@@ -445,6 +496,7 @@ __device__ __forceinline__ void solve_loop(const SolveSys& S, const Ctl& C, XRec
     for (int c = tid; c < npad; c += kNT) {
         sx[c] = (c < n && S.x0) ? S.x0[c] : 0.0;
         if (MIXED) sd[c] = LAcc(0);
+        if (OP16) sdb[c] = 0;
     }
     if (S.xref && C.xslice > 0)
         for (int c = e0 + tid; c < e1; c += kNT) sxr[c - e0] = S.xref[c];
@@ -465,6 +517,9 @@ __device__ __forceinline__ void solve_loop(const SolveSys& S, const Ctl& C, XRec
     const double tol2 = C.tol2;
     const bool rel_err = S.stop_mode == CSK_STOP_REL_ERR;
 
+    const typename Elem<Tag>::Op* op_lp;  // the low-precision product's operand
+    if constexpr (OP16) op_lp = sdb;
+    else op_lp = reinterpret_cast<const typename Elem<Tag>::Op*>(sd);
     bool fp64 = !MIXED;
     bool need_refresh = true;
     int64_t k_ref = 0;
@@ -491,7 +546,7 @@ __device__ __forceinline__ void solve_loop(const SolveSys& S, const Ctl& C, XRec
                                                                          S.bt, nullptr, S.nu2, loc, res, nullptr, 0);
         } else {
             stream_rows<Tag, VEC, LPR, ring_depth<Tag>(), false, M>(static_cast<const LPS*>(S.At), S.ldat, n, nseglp,
-                                                                 r0, r1, sd, S.rref, nullptr, S.nu2, loc, res,
+                                                                 r0, r1, op_lp, S.rref, nullptr, S.nu2, loc, res,
                                                                  nullptr, 0);
         }
         if (S.xref)
@@ -539,7 +594,11 @@ __device__ __forceinline__ void solve_loop(const SolveSys& S, const Ctl& C, XRec
         for (int c = tid; c < n; c += kNT) {
             const double a = arow[c];
             sx[c] = sx[c] + alpha * a;
-            if (MIXED) sd[c] = (refresh ? LAcc(0) : sd[c]) + static_cast<LAcc>(alpha * a);
+            if (MIXED) {
+                const LAcc nv = (refresh ? LAcc(0) : sd[c]) + static_cast<LAcc>(alpha * a);
+                sd[c] = nv;
+                if (OP16) sdb[c] = __builtin_bit_cast(uint16_t, static_cast<__bf16>(nv));
+            }
         }
         __syncthreads();
     }
@@ -637,15 +696,16 @@ template <class Tag, int LPR>
 SolveLds plan_lds(int npad, int& xslice, int want, int& layers)
 {
     const bool mixed = !std::is_same<Tag, tag_f64>::value;
+    constexpr bool o16 = op16<Tag>();
     constexpr int NG = kNT / LPR;
     constexpr int LAYER = kNT * chunk_k<Tag>() * 16;
     const size_t cap = (size_t)device_max_lds() - kLdsReserve;
     // the x_ref slice is a convenience: without room it is read from memory
-    if (xslice > 0 && solve_lds(npad, mixed, xslice, 0, NG, LAYER).total > cap) xslice = 0;
+    if (xslice > 0 && solve_lds(npad, mixed, xslice, 0, NG, LAYER, o16).total > cap) xslice = 0;
     int L = std::max(0, std::min(want, kMaxResLayers));
-    while (L > 0 && solve_lds(npad, mixed, xslice, L, NG, LAYER).total > cap) --L;
+    while (L > 0 && solve_lds(npad, mixed, xslice, L, NG, LAYER, o16).total > cap) --L;
     layers = L;
-    return solve_lds(npad, mixed, xslice, L, NG, LAYER);
+    return solve_lds(npad, mixed, xslice, L, NG, LAYER, o16);
 }
 
 template <class Tag, bool VEC, int LPR, bool M>
