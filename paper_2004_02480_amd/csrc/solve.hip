@@ -962,10 +962,18 @@ SolvePlan solve_plan(int64_t d, int64_t n, csk_dtype at_dtype, int64_t ldat, con
     else if (o && o->grid > 0) grid = o->grid;
     else if (o && o->single_wg == 0) grid = std::max(2, std::min<int>(device_cu_count(), (int)((d + 15) / 16)));
     else {
-        // One workgroup while its rows fit comfortably in one CU's share of
-        // L2; otherwise one workgroup per CU, with at least 16 rows each.
+        // One workgroup while the matrix fits its LDS (no exchange at all);
+        // otherwise enough workgroups for each one's rows to stay in LDS
+        // (about 64 KB each, at least 8 workgroups, at most one per CU and
+        // at least 16 rows each): the exchange grows with the grid (2.4 us
+        // at 8 workgroups, 3.8 at 256), the product of resident rows hardly
+        // at all.  A 256 KB sketch takes 7.5 us per iteration in one
+        // workgroup and 5.6 in eight.
         const int64_t bytes = d * n * (int64_t)dtype_size(at_dtype);
-        grid = (bytes <= (int64_t)(1 << 20)) ? 1 : std::max(2, std::min<int>(device_cu_count(), (int)((d + 15) / 16)));
+        const int64_t want = std::max<int64_t>(8, (bytes + (64 << 10) - 1) >> 16);
+        grid = (bytes <= (int64_t)(96 << 10))
+                   ? 1
+                   : (int)std::max<int64_t>(2, std::min<int64_t>({(int64_t)device_cu_count(), want, (d + 15) / 16}));
     }
     // a shape from csk_tune_solve replaces the defaults (never an explicit choice)
     if (o && o->grid == 0 && o->single_wg == -1) {
