@@ -105,25 +105,43 @@ template <> struct Elem<tag_f32> {
                (!M || lim > 2 ? __uint_as_float(v.z) : 0.f) * x[2] + (!M || lim > 3 ? __uint_as_float(v.w) : 0.f) * x[3];
     }
 };
-template <class Tag> struct Elem16 {
+// FP16: the operand copy is x - x_ref times 2^e, with e chosen at each
+// refresh so that the window's first step has a scaled norm in [16, 32)
+// (FP16's exponent range would lose x - x_ref as the residual shrinks);
+// the product is rescaled by 2^-e.  Two-element dot instructions as BF16.
+typedef _Float16 f16x2_t __attribute__((ext_vector_type(2)));
+template <> struct Elem<tag_f16> {
     using S = uint16_t;
     using Acc = float;
-    using Op = float;
+    using Op = uint16_t;
     static constexpr int kVec = 8;
-    template <int VW, bool M> __device__ static float dot(const uint4& v, const float* x, int lim)
+    template <int VW, bool M> __device__ static float dot(const uint4& v, const uint16_t* x, int lim)
     {
-        if constexpr (VW == 1) return (!M || lim > 0 ? widen<Tag>(static_cast<uint16_t>(v.x & 0xFFFFu)) : 0.f) * x[0];
-        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-        float s = 0.f;
+        if constexpr (VW == 1) {
+            return (!M || lim > 0 ? f16_bits_to_f32(static_cast<uint16_t>(v.x & 0xFFFFu)) : 0.f) *
+                   f16_bits_to_f32(x[0]);
+        } else if constexpr (!M) {
+            const uint4 xv = *reinterpret_cast<const uint4*>(x);
+            float s = __builtin_amdgcn_fdot2(__builtin_bit_cast(f16x2_t, v.x), __builtin_bit_cast(f16x2_t, xv.x), 0.f,
+                                             false);
+            s = __builtin_amdgcn_fdot2(__builtin_bit_cast(f16x2_t, v.y), __builtin_bit_cast(f16x2_t, xv.y), s, false);
+            s = __builtin_amdgcn_fdot2(__builtin_bit_cast(f16x2_t, v.z), __builtin_bit_cast(f16x2_t, xv.z), s, false);
+            return __builtin_amdgcn_fdot2(__builtin_bit_cast(f16x2_t, v.w), __builtin_bit_cast(f16x2_t, xv.w), s,
+                                          false);
+        } else {
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+            float s = 0.f;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            s += (!M || lim > 2 * k ? widen<Tag>(static_cast<uint16_t>(w[k] & 0xFFFFu)) : 0.f) * x[2 * k];
-            s += (!M || lim > 2 * k + 1 ? widen<Tag>(static_cast<uint16_t>(w[k] >> 16)) : 0.f) * x[2 * k + 1];
+            for (int k = 0; k < 4; ++k) {
+                s += (lim > 2 * k ? f16_bits_to_f32(static_cast<uint16_t>(w[k] & 0xFFFFu)) : 0.f) *
+                     f16_bits_to_f32(x[2 * k]);
+                s += (lim > 2 * k + 1 ? f16_bits_to_f32(static_cast<uint16_t>(w[k] >> 16)) : 0.f) *
+                     f16_bits_to_f32(x[2 * k + 1]);
+            }
+            return s;
         }
-        return s;
     }
 };
-template <> struct Elem<tag_f16> : Elem16<tag_f16> {};
 // BF16: the operand (x - x_ref) is kept in LDS rounded to BF16 as well, and
 // the unmasked product of a 16-byte vector is four two-element dot
 // instructions (BF16 pairs, FP32 accumulation) instead of eight widenings
@@ -277,7 +295,7 @@ __device__ __forceinline__ void stream_rows(const typename Elem<Tag>::S* __restr
                                             int nseg, int r0, int r1, const typename Elem<Tag>::Op* __restrict__ xs,
                                             const double* __restrict__ rhs, double* __restrict__ rout,
                                             const double* __restrict__ nu2, Red& loc, const ResLds& res,
-                                            double* lrout, int nrow_out)
+                                            double* lrout, int nrow_out, double dscale = 1.0)
 {
     Ring<Tag, kD> R;
     using E = Elem<Tag>;
@@ -302,7 +320,9 @@ __device__ __forceinline__ void stream_rows(const typename Elem<Tag>::S* __restr
 
     auto finish = [&](int crow, Acc s, double pr, double nn) {
         const int row = r0 + g + NG * crow;
-        const double r = pr - static_cast<double>(s);
+        double r;
+        if constexpr (std::is_same<Tag, tag_f16>::value) r = pr - static_cast<double>(s) * dscale;  // scaled operand
+        else r = pr - static_cast<double>(s);
         if constexpr (ROUT) {
             rout[row] = r;
             if (crow < nrow_out) lrout[crow * NG + g] = r;
@@ -418,7 +438,7 @@ struct SolveLds {
 
 __host__ __device__ inline size_t al_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// mixed: x - x_ref in FP32 (4 bytes per element); op16: also its BF16 copy
+// mixed: x - x_ref in FP32 (4 bytes per element); op16: also its 16-bit copy
 __host__ __device__ inline SolveLds solve_lds(int npad, bool mixed, int xslice, int L, int ng, int layer_bytes,
                                               bool op16 = false)
 {
@@ -481,7 +501,7 @@ __device__ __forceinline__ void solve_loop(const SolveSys& S, const Ctl& C, XRec
     const SolveLds lay = solve_lds(npad, MIXED, C.xslice, C.res_layers, NG, LAYER, OP16);
     double* sx = reinterpret_cast<double*>(smem + lay.sx);   // x, FP64, zero past n
     LAcc* sd = reinterpret_cast<LAcc*>(smem + lay.sd);       // x - x_ref (mixed), zero past n
-    uint16_t* sdb = reinterpret_cast<uint16_t*>(smem + lay.sdb);  // its BF16 copy (OP16)
+    uint16_t* sdb = reinterpret_cast<uint16_t*>(smem + lay.sdb);  // its 16-bit copy (OP16)
     double* sxr = reinterpret_cast<double*>(smem + lay.sxr); // x_ref[e0 .. e1)
     double* lrhs = reinterpret_cast<double*>(smem + lay.lrhs);
     double* lnn = reinterpret_cast<double*>(smem + lay.lnn);
@@ -520,6 +540,8 @@ __device__ __forceinline__ void solve_loop(const SolveSys& S, const Ctl& C, XRec
     const typename Elem<Tag>::Op* op_lp;  // the low-precision product's operand
     if constexpr (OP16) op_lp = sdb;
     else op_lp = reinterpret_cast<const typename Elem<Tag>::Op*>(sd);
+    float fscale = 1.f;   // FP16 operand: 2^e of the current refresh window
+    double dscale = 1.0;  // and 2^-e
     bool fp64 = !MIXED;
     bool need_refresh = true;
     int64_t k_ref = 0;
@@ -547,7 +569,7 @@ __device__ __forceinline__ void solve_loop(const SolveSys& S, const Ctl& C, XRec
         } else {
             stream_rows<Tag, VEC, LPR, ring_depth<Tag>(), false, M>(static_cast<const LPS*>(S.At), S.ldat, n, nseglp,
                                                                  r0, r1, op_lp, S.rref, nullptr, S.nu2, loc, res,
-                                                                 nullptr, 0);
+                                                                 nullptr, 0, dscale);
         }
         if (S.xref)
             for (int c = e0 + tid; c < e1; c += kNT) {
@@ -590,6 +612,14 @@ __device__ __forceinline__ void solve_loop(const SolveSys& S, const Ctl& C, XRec
         // Projection onto row i_k, on this workgroup's copy of x.
         const double alpha = tot.r;
         const double* __restrict__ arow = S.At64 + (int64_t)tot.idx * S.ldat64;
+        if (std::is_same<Tag, tag_f16>::value && refresh) {
+            // ||alpha a|| = |r| / ||a|| = sqrt(score), identical in every workgroup
+            int ex = 0;
+            frexp(sqrt(tot.score), &ex);
+            const int e = min(100, max(-100, 5 - ex));
+            fscale = ldexpf(1.f, e);
+            dscale = ldexp(1.0, -e);
+        }
 #pragma unroll 2
         for (int c = tid; c < n; c += kNT) {
             const double a = arow[c];
@@ -597,7 +627,10 @@ __device__ __forceinline__ void solve_loop(const SolveSys& S, const Ctl& C, XRec
             if (MIXED) {
                 const LAcc nv = (refresh ? LAcc(0) : sd[c]) + static_cast<LAcc>(alpha * a);
                 sd[c] = nv;
-                if (OP16) sdb[c] = __builtin_bit_cast(uint16_t, static_cast<__bf16>(nv));
+                if constexpr (std::is_same<Tag, tag_bf16>::value)
+                    sdb[c] = __builtin_bit_cast(uint16_t, static_cast<__bf16>(nv));
+                else if constexpr (std::is_same<Tag, tag_f16>::value)
+                    sdb[c] = __builtin_bit_cast(uint16_t, static_cast<_Float16>(nv * fscale));
             }
         }
         __syncthreads();

@@ -73,9 +73,10 @@ def test_full_size_dense_coherent(gpu, orc):
     print(f"dense_coherent iterations {r.iters}")
 
 
+@pytest.mark.parametrize("n", [200, 203])  # whole 16-byte vectors, and a masked tail
 @pytest.mark.parametrize("lp", [torch.bfloat16, torch.float16, torch.float32])
-def test_mixed_precision_reaches_1e10(gpu, lp):
-    s = W.row_scaled(60000, 200, seed=31, device=DEV)
+def test_mixed_precision_reaches_1e10(gpu, lp, n):
+    s = W.row_scaled(60000, n, seed=31, device=DEV)
     sk = sketched(gpu, s, 2000, 32, lp=lp)
     r64 = gpu.csk_solve(sk.At64, sk.bt, nu2=sk.nu2, x_ref=s.x_star, tol=1e-10, maxit=200000)
     r = gpu.csk_solve(sk.At_lp, sk.bt, At64=sk.At64, nu2=sk.nu2, x_ref=s.x_star, tol=1e-10, maxit=200000)
@@ -157,11 +158,17 @@ def test_nu2_computed_when_absent(gpu):
     assert relerr(b.x, s.x_star) <= 1e-10
 
 
-def test_mixed_full_size_row_scaled(gpu):
+@pytest.mark.parametrize("lp", [torch.bfloat16, torch.float16])
+def test_mixed_full_size_row_scaled(gpu, lp):
+    # rows scaled over four decades: the FP16 operand copy of x - x_ref is
+    # rescaled at every refresh; both 16-bit formats reach 1e-10 without the
+    # FP64 fallback, in about the FP64 loop's iteration count
     c = W.config("row_scaled")
     s = W.row_scaled(c["m"], c["n"], c["seed"], device=DEV)
-    sk = sketched(gpu, s, c["d"], c["sketch_seed"], lp=torch.bfloat16)
+    sk = sketched(gpu, s, c["d"], c["sketch_seed"], lp=lp)
     r = gpu.csk_solve(sk.At_lp, sk.bt, At64=sk.At64, nu2=sk.nu2, x_ref=s.x_star, tol=1e-10, maxit=c["maxit"])
     assert r.status == gpu.CSK_OK, r.status_name
     assert relerr(r.x, s.x_star) <= 1e-10
-    print(f"row_scaled bf16 iterations {r.iters} refreshes {r.refreshes} fallback {r.fp64_fallback}")
+    assert r.fp64_fallback == 0
+    assert r.iters <= 6400, r.iters
+    print(f"row_scaled {lp} iterations {r.iters} refreshes {r.refreshes} fallback {r.fp64_fallback}")
