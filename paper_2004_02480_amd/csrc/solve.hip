@@ -33,6 +33,7 @@
 #include <cmath>
 #include <map>
 #include <mutex>
+#include <queue>
 #include <tuple>
 #include <type_traits>
 #include <vector>
@@ -829,29 +830,61 @@ csk_status launch_batched(const SolveSys* sys_dev, int32_t nsys, const BatchedPl
     CSK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern), kNT, shm));
     const int cap = std::max(1, per_cu) * device_cu_count();
 
-    // Split plan: the estimated work of a system is d n^2 (bytes per
-    // iteration times an iteration count that grows with n).  A system above
-    // twice the average share of one workgroup gets about work / share
-    // workgroups, at least 32 rows each, at most half the grid.
-    double W = 0.0;
+    // Split plan.  A system's time is modelled as its iteration count times
+    // a per-iteration cost.  The iterations of the greedy loop on a
+    // Gaussian-like sketch grow like n / (1 - sqrt(n/d))^2 (the square of
+    // the sketch's condition number times n; fitted on the 512-system
+    // workload, log error 0.12), so the longest-running systems are the
+    // nearly square ones, not the largest.  The per-iteration cost is a
+    // fixed part (about 2 us alone, 6 us when split, for the exchange) plus
+    // the system's elements per part at one CU's streaming rate (about
+    // 0.18 ns per element in FP32; a CU streams these rows at about
+    // 20 GB/s, so splitting scales almost linearly).  Starting from one
+    // part each, the system with the longest modelled time gets one more
+    // part (at least 32 rows each, at most half the grid) while that
+    // shortens the larger of the longest time and the average load per
+    // workgroup.
+    const double esz = (double)sizeof(typename Elem<Tag>::S);
+    const double ce = 0.18e-3 * (esz == 2.0 ? 1.5 : esz == 8.0 ? 1.4 : 1.0);
+    auto model = [&](const SolveSys& S, int parts) {
+        const double q = std::min(0.9, (double)S.n / (double)std::max(S.d, 1));
+        const double iters = (double)S.n / ((1.0 - std::sqrt(q)) * (1.0 - std::sqrt(q)));
+        return iters * ((parts > 1 ? 6.0 : 2.0) + ce * (double)S.d * (double)S.n / parts);
+    };
+    std::vector<int> nparts(nsys, 1);
+    std::vector<double> tsys(nsys);
+    double total = 0.0;
+    std::priority_queue<std::pair<double, int32_t>> heap;
     for (int32_t p = 0; p < nsys; ++p) {
-        const SolveSys& S = bp.sys[bp.order[p]];
-        W += (double)S.d * (double)S.n * (double)S.n;
+        tsys[p] = model(bp.sys[bp.order[p]], 1);
+        total += tsys[p];
+        heap.push({tsys[p], p});
     }
-    const double share = W / cap;
-    std::vector<int32_t> item_off(nsys + 1), exch_off(nsys, 0);
     size_t rec = 0;
+    while (!heap.empty()) {
+        const int32_t p = heap.top().second;
+        heap.pop();
+        const SolveSys& S = bp.sys[bp.order[p]];
+        const int cur = nparts[p];
+        const int next = cur + 1;
+        const int maxp = std::max(1, std::min(cap / 2, S.d / 32));
+        const size_t rec_next = rec - (cur > 1 ? 2 * (size_t)cur : 0) + 2 * (size_t)next;
+        if (next > maxp || rec_next > bp.exch_records) break;
+        const double t_next = model(S, next);
+        const double total_next = total - cur * tsys[p] + next * t_next;
+        const double crit_next = std::max(t_next, heap.empty() ? 0.0 : heap.top().first);
+        if (std::max(crit_next, total_next / cap) >= std::max(tsys[p], total / cap)) break;
+        nparts[p] = next;
+        tsys[p] = t_next;
+        total = total_next;
+        rec = rec_next;
+        heap.push({t_next, p});
+    }
+    std::vector<int32_t> item_off(nsys + 1), exch_off(nsys, 0);
+    rec = 0;
     int32_t items = 0;
     for (int32_t p = 0; p < nsys; ++p) {
-        const SolveSys& S = bp.sys[bp.order[p]];
-        const double w = (double)S.d * (double)S.n * (double)S.n;
-        int parts = 1;
-        if (w > 2.0 * share) {
-            const double want_parts = std::ceil(w / share);
-            parts = (int)std::min<double>(want_parts, (double)std::max(1, S.d / 32));
-            parts = std::max(1, std::min(parts, cap / 2));
-            if (parts > 1 && rec + 2 * (size_t)parts > bp.exch_records) parts = 1;
-        }
+        const int parts = nparts[p];
         item_off[p] = items;
         exch_off[p] = (int32_t)rec;
         items += parts;
