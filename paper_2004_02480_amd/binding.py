@@ -66,6 +66,20 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
     return buf[off:off + int(nbytes) + 256]
 
 
+def _padded_rows(d: int, n: int, dtype: torch.dtype, device) -> torch.Tensor:
+    """A d x n view of a buffer whose rows are padded to whole 16-byte
+    vectors: the solve reads such rows with vector loads, where unpadded
+    rows of a width that is not a multiple of 16 bytes fall back to scalar
+    loads (several times slower)."""
+    per = 16 // torch.tensor([], dtype=dtype).element_size()
+    ld = (n + per - 1) // per * per
+    return torch.empty((d, ld), dtype=dtype, device=device)[:, :n]
+
+
+def _ld(t: Optional[torch.Tensor], n: int) -> int:
+    return t.stride(0) if t is not None else n
+
+
 def _need_cuda(t: torch.Tensor, name: str):
     if not (isinstance(t, torch.Tensor) and t.is_cuda):
         raise ValueError(f"{name} must be a device tensor")
@@ -120,8 +134,8 @@ def csk_sketch(A: torch.Tensor, b: Optional[torch.Tensor], d: int, seed: int, *,
         if lp_dtype is None and At_lp is not None:
             lp_dtype = At_lp.dtype
     else:
-        At64 = torch.empty((d, n), dtype=torch.float64, device=dev) if want_f64 else None
-        At_lp = torch.empty((d, n), dtype=lp_dtype, device=dev) if lp_dtype is not None else None
+        At64 = _padded_rows(d, n, torch.float64, dev) if want_f64 else None
+        At_lp = _padded_rows(d, n, lp_dtype, dev) if lp_dtype is not None else None
         nu2 = torch.empty(d, dtype=torch.float64, device=dev)
         perm = torch.empty(m, dtype=torch.int32, device=dev) if want_perm else None
         ptr = torch.empty(d + 1, dtype=torch.int32, device=dev) if want_perm else None
@@ -155,7 +169,7 @@ def csk_sketch(A: torch.Tensor, b: Optional[torch.Tensor], d: int, seed: int, *,
     lp_code = _TORCH_TO_CSK[lp_dtype] if lp_dtype is not None else CSK_F64
     _check(_lib.csk_sketch(_ptr(A), _TORCH_TO_CSK[A.dtype], m, n, lda, _ptr(B), nrhs, ldb, d,
                            ctypes.c_uint64(seed & (2**64 - 1)),
-                           _ptr(At64), n, _ptr(At_lp), lp_code, n, _ptr(bt), ldbt, _ptr(nu2),
+                           _ptr(At64), _ld(At64, n), _ptr(At_lp), lp_code, _ld(At_lp, n), _ptr(bt), ldbt, _ptr(nu2),
                            _ptr(perm), _ptr(ptr), _ptr(ws), ws.numel(), _stream(stream)), "csk_sketch")
     return SketchOut(At64, At_lp, bt, nu2, perm, ptr)
 
@@ -172,8 +186,8 @@ def csk_sketch_csr(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, 
     m = row_ptr.numel() - 1
     nnz = col.numel()
     dev = row_ptr.device
-    At64 = torch.empty((d, n), dtype=torch.float64, device=dev) if want_f64 else None
-    At_lp = torch.empty((d, n), dtype=lp_dtype, device=dev) if lp_dtype is not None else None
+    At64 = _padded_rows(d, n, torch.float64, dev) if want_f64 else None
+    At_lp = _padded_rows(d, n, lp_dtype, dev) if lp_dtype is not None else None
     nu2 = torch.empty(d, dtype=torch.float64, device=dev)
     bt = torch.empty(d, dtype=torch.float64, device=dev) if b is not None else None
     nbytes = ctypes.c_size_t(0)
@@ -182,7 +196,8 @@ def csk_sketch_csr(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, 
     lp_code = _TORCH_TO_CSK[lp_dtype] if lp_dtype is not None else CSK_F64
     _check(_lib.csk_sketch_csr(_ptr(row_ptr), _ptr(col), _ptr(val), m, n, nnz,
                                _ptr(b.contiguous() if b is not None else None), d,
-                               ctypes.c_uint64(seed & (2**64 - 1)), _ptr(At64), n, _ptr(At_lp), lp_code, n,
+                               ctypes.c_uint64(seed & (2**64 - 1)), _ptr(At64), _ld(At64, n), _ptr(At_lp), lp_code,
+                               _ld(At_lp, n),
                                _ptr(bt), _ptr(nu2), _ptr(ws), ws.numel(), _stream(stream)), "csk_sketch_csr")
     return SketchOut(At64, At_lp, bt, nu2, None, None)
 
