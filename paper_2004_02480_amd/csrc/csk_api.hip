@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <cmath>
 #include <cstring>
 #include <mutex>
 #include <numeric>
@@ -668,6 +669,7 @@ csk_status csk_solve_batched(const csk_system_desc* sys, int32_t nsys, csk_dtype
         J.Bt = reinterpret_cast<double*>(data + L.off_bt[s]);
         J.ldbt = 1;
         J.nu2 = reinterpret_cast<double*>(data + L.off_nu2[s]);
+        J.zpad = 1;  // the solve then needs no per-element masks
     }
     st = sketch_run(jobs.data(), nsys, a_dtype, lp_dtype == CSK_F64 ? (csk_dtype)0 : lp_dtype, nullptr, nullptr,
                     sk_ws, sk_bytes, stm);
@@ -707,11 +709,13 @@ csk_status csk_solve_batched(const csk_system_desc* sys, int32_t nsys, csk_dtype
     }
     std::vector<int32_t> order(nsys);
     std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-        const double ca = (double)sys[a].d * (double)sys[a].n * (double)sys[a].n;
-        const double cb = (double)sys[b].d * (double)sys[b].n * (double)sys[b].n;
-        return ca > cb;
-    });
+    // longest estimated time first: iterations grow like n / (1 - sqrt(n/d))^2
+    // (the split plan's model), each streaming d * n elements
+    auto est = [&](int32_t i) {
+        const double q = std::min(0.9, (double)sys[i].n / (double)sys[i].d);
+        return (double)sys[i].d * (double)sys[i].n * (double)sys[i].n / ((1.0 - std::sqrt(q)) * (1.0 - std::sqrt(q)));
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return est(a) > est(b); });
     BatchedPlan bp;
     bp.order = order.data();
     bp.sys = hs.data();

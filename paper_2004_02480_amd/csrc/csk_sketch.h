@@ -23,6 +23,8 @@ struct SketchSys {
     int64_t task_off;     // first global segsum task
     uint64_t seed;
     int32_t n, d, nrhs, nchunks;
+    int32_t zpad;         // write zeros to the row padding (columns n .. ld - 1)
+    int32_t pad_;
 };
 
 // Host-side description of a batch before it is laid out.
@@ -35,6 +37,7 @@ struct SketchJob {
     double* nu2;
     int64_t m, n, lda, nrhs, ldb, d, ldat64, ldatlp, ldbt;
     uint64_t seed;
+    int32_t zpad;         // the outputs' row padding is the library's own: zero it
 };
 
 // Workspace bytes for a batch of `nsys` systems with total rows M, total

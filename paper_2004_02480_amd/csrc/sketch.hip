@@ -408,6 +408,11 @@ __global__ __launch_bounds__(256) void k_segsum(Batch b)
                     nrm += acc[q][e] * acc[q][e];
                     if (S.At64) S.At64[j * S.ldat64 + col + e] = acc[q][e];
                     if constexpr (LP != 0) store_lp<LP>(S.Atlp, j * S.ldatlp + col + e, acc[q][e]);
+                } else if (S.zpad) {
+                    // the padding lies in the row's last chunk (ld < n + 32)
+                    if (S.At64 && col + e < S.ldat64) S.At64[j * S.ldat64 + col + e] = 0.0;
+                    if constexpr (LP != 0)
+                        if (col + e < S.ldatlp) store_lp<LP>(S.Atlp, j * S.ldatlp + col + e, 0.0);
                 }
             }
         }
@@ -886,6 +891,7 @@ csk_status sketch_run(const SketchJob* jobs, int32_t nsys, csk_dtype a_dtype, cs
         S.d = static_cast<int32_t>(J.d);
         S.nrhs = static_cast<int32_t>(J.nrhs);
         S.nchunks = static_cast<int32_t>((J.n + cw - 1) / cw);
+        S.zpad = J.zpad;
         S.row_off = M;
         S.bkt_off = D;
         S.task_off = T;

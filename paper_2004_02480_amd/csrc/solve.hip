@@ -668,6 +668,9 @@ __global__ __launch_bounds__(kNT) void k_solve_single(SolveSys S, Ctl C)
     solve_loop<Tag, VEC, LPR, false, M>(S, C, nullptr, 0, 1, smem);
 }
 
+// The batch's sketches live in the library's own layout, rows padded to 64
+// bytes with zeros, so the product needs no per-element masks: a vector
+// that straddles column n reads zeros past it.
 // Work items in queue order: queue position p owns items
 // [item_off[p], item_off[p+1]); a system with one item runs the
 // single-workgroup loop, a split one the grid loop over its P items with its
@@ -696,9 +699,9 @@ __global__ __launch_bounds__(kNT) void k_solve_batched(const SolveSys* __restric
         const int parts = C.item_off[lo + 1] - C.item_off[lo];
         const SolveSys S = sys[C.order[lo]];
         if (parts == 1)
-            solve_loop<Tag, VEC, LPR, false, true>(S, C, nullptr, 0, 1, smem);
+            solve_loop<Tag, VEC, LPR, false, false>(S, C, nullptr, 0, 1, smem);
         else
-            solve_loop<Tag, VEC, LPR, true, true>(S, C, C.exch + C.exch_off[lo], item - C.item_off[lo], parts, smem);
+            solve_loop<Tag, VEC, LPR, true, false>(S, C, C.exch + C.exch_off[lo], item - C.item_off[lo], parts, smem);
         __syncthreads();
     }
 }
