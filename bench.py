@@ -34,11 +34,20 @@ SOLVE_PMC = "profiles/k_solve_grid_dense_coherent_pmc.md"
 
 
 def sources_sha256(paths):
+    """Hash of the code in `paths`: comments, blank lines and surrounding
+    whitespace are left out, so only a change of code marks counters taken
+    on an earlier build as stale."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for p in paths:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, p), "r") as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for line in text.splitlines():
+            code = line.split("//", 1)[0].strip()
+            if code:
+                h.update(code.encode() + b"\n")
     return h.hexdigest()
 
 

@@ -11,11 +11,11 @@
 //      |r_i| / ||At^(i)||, same argmax), best row of the workgroup through
 //      wavefront butterflies and LDS;
 //   3. (grid path) each workgroup publishes its best row (score, step length
-//      alpha = r / ||At^(i)||^2, index), partial ||r||^2 and partial
-//      ||x - x_ref||^2 in its own record, release-stored with the iteration
-//      as tag; every workgroup polls all tags in parallel and reduces the
-//      records in the same fixed order, so all agree on i_k and on the stop
-//      decision.  No shared read-modify-write counter is contended.
+//      alpha = r / ||At^(i)||^2, index), partial ||r||^2 or ||x - x_ref||^2
+//      and flags in its own record of device-coherent words, each tagged
+//      with the iteration; every workgroup polls all records in parallel and
+//      reduces them in the same fixed order, so all agree on i_k and on the
+//      stop decision.  No shared read-modify-write counter is contended.
 //   4. stop test (Section 3's RES, or the sketched residual), then the
 //      projection x += alpha At^(i_k)^T, applied by every workgroup to its
 //      own copy of x (each thread owns fixed columns).
@@ -23,7 +23,10 @@
 // kept beside it.  Every `refresh_every` iterations the exact FP64 residual
 // r_ref = bt - At64 x is formed and x_ref = x saved; in between the residual
 // is r_ref - At (x - x_ref) with FP32 accumulation, so each inner iteration
-// streams 2-4x fewer bytes.  Scores and projections use the FP64 rows.
+// streams 2-4x fewer bytes.  For the 16-bit types x - x_ref is also kept in
+// LDS in that type (FP16 scaled by a power of two per refresh window), and
+// the product uses two-element dot instructions.  Scores and projections
+// use the FP64 rows.
 // Small systems run the same loop in one workgroup (no exchange); the
 // batched kernel hands whole systems to workgroups from an atomic queue.
 #include "csk_grid.h"
