@@ -51,6 +51,13 @@ def _load():
     lib.orc_mwrk.restype = ctypes.c_int
     lib.orc_mwrk.argtypes = [_p, _i64, _i64, _i64, _p, _p, _p, ctypes.c_double, _i64, ctypes.c_int,
                              _p, _p, _p, _p, _p]
+    lib.orc_rgrk.restype = ctypes.c_int
+    lib.orc_rgrk.argtypes = [_p, _i64, _i64, _i64, _p, _p, _p, ctypes.c_double, _i64, ctypes.c_int,
+                             ctypes.c_double, _u64, _p, _p, _p, _p, _p]
+    lib.orc_rk.restype = ctypes.c_int
+    lib.orc_rk.argtypes = [_p, _i64, _i64, _i64, _p, _p, _p, ctypes.c_double, _i64, _u64,
+                           _p, _p, _p, _p, _p]
+    lib.orc_uniform_stream.argtypes = [_u64, _i64, _i64, _p]
     _lib = lib
     return lib
 
@@ -210,6 +217,61 @@ def mwrk(At, bt, *, x0=None, xref=None, tol=1e-10, maxit=100000, stop_mode=None,
     if trace:
         return MwrkResult(x, k, st, tidx[:k], terr[:k + 1], tr[:k])
     return MwrkResult(x, k, st)
+
+
+def _traces(trace, maxit):
+    if not trace:
+        return None, None, None
+    return (np.full(maxit + 1, -1, np.int64), np.full(maxit + 1, np.nan, np.float64),
+            np.full(maxit + 1, np.nan, np.float64))
+
+
+def rgrk(At, bt, *, theta, sel_seed, x0=None, xref=None, tol=1e-10, maxit=100000, stop_mode=None,
+         trace=False):
+    """Relaxed greedy randomized Kaczmarz (theta = 1/2: greedy randomized
+    Kaczmarz); see orc_rgrk in csk_oracle.c."""
+    At = _c(At, np.float64)
+    bt = _c(bt, np.float64)
+    d, n = At.shape
+    if stop_mode is None:
+        stop_mode = STOP_REL_ERR if xref is not None else STOP_REL_RESID
+    x = np.empty(n, np.float64)
+    iters = np.zeros(1, np.int64)
+    x0c = _c(x0, np.float64) if x0 is not None else None
+    xrc = _c(xref, np.float64) if xref is not None else None
+    tidx, terr, tr = _traces(trace, maxit)
+    st = _load().orc_rgrk(_ptr(At), d, n, n, _ptr(bt), _ptr(x0c), _ptr(xrc), float(tol), int(maxit),
+                          int(stop_mode), float(theta), int(sel_seed) & (2**64 - 1), _ptr(x), _ptr(iters),
+                          _ptr(tidx), _ptr(terr), _ptr(tr))
+    k = int(iters[0])
+    if trace:
+        return MwrkResult(x, k, st, tidx[:k], terr[:k + 1], tr[:k])
+    return MwrkResult(x, k, st)
+
+
+def rk(At, bt, *, sel_seed, xref, x0=None, tol=1e-10, maxit=100000, trace=False):
+    """Randomized Kaczmarz (relative-error stop only); see orc_rk."""
+    At = _c(At, np.float64)
+    bt = _c(bt, np.float64)
+    d, n = At.shape
+    x = np.empty(n, np.float64)
+    iters = np.zeros(1, np.int64)
+    x0c = _c(x0, np.float64) if x0 is not None else None
+    xrc = _c(xref, np.float64)
+    tidx, terr, tr = _traces(trace, maxit)
+    st = _load().orc_rk(_ptr(At), d, n, n, _ptr(bt), _ptr(x0c), _ptr(xrc), float(tol), int(maxit),
+                        int(sel_seed) & (2**64 - 1), _ptr(x), _ptr(iters), _ptr(tidx), _ptr(terr), _ptr(tr))
+    k = int(iters[0])
+    if trace:
+        return MwrkResult(x, k, st, tidx[:k], terr[:k + 1], tr[:k])
+    return MwrkResult(x, k, st)
+
+
+def uniforms(sel_seed: int, first: int, count: int) -> np.ndarray:
+    """Uniforms first .. first+count-1 of the selection stream (orc_uniform)."""
+    out = np.empty(count, np.float64)
+    _load().orc_uniform_stream(int(sel_seed) & (2**64 - 1), first, count, _ptr(out))
+    return out
 
 
 def csk(A, b, d, seed, *, x0=None, xref=None, tol=1e-10, maxit=100000, stop_mode=None):

@@ -27,6 +27,12 @@
  *   orc_mwrk             the loop of Algorithm 1 (greedy selection of the row
  *                        with the largest weighted residual, then projection
  *                        onto that row), with the stopping rule of Section 3.
+ *   orc_rgrk, orc_rk     the randomized selection rules the introduction puts
+ *                        Algorithm 1's loop among (relaxed greedy randomized
+ *                        Kaczmarz, with greedy randomized Kaczmarz at
+ *                        theta = 1/2; randomized Kaczmarz), compared against
+ *                        in Section 3; written from their published
+ *                        definitions (Bai & Wu; Strohmer & Vershynin).
  *   orc_round_*          precision reduction of a finished FP64 sketch (not in
  *                        the paper; round-to-nearest-even, two steps).
  *
@@ -399,4 +405,201 @@ int orc_mwrk(const double* At, int64_t d, int64_t n, int64_t ldat, const double*
     free(nu);
     free(r);
     return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Randomized row selection: the relaxed greedy randomized Kaczmarz rule     */
+/* (Bai & Wu; its parameter theta = 1/2 gives their greedy randomized rule   */
+/* and theta = 1 the maximal weighted residual rule of Algorithm 1) and the  */
+/* randomized Kaczmarz rule of Strohmer & Vershynin.  The introduction       */
+/* places Algorithm 1's loop in this family and Section 3 compares against   */
+/* its members.  The stopping test and the projection are those of orc_mwrk; */
+/* only the choice of i_k differs, and its random numbers come from a        */
+/* SplitMix64 counter stream of the caller's selection seed.                 */
+/* ------------------------------------------------------------------------ */
+
+/* The k-th (0-based) uniform of the selection stream: the top 52 bits of the
+ * k-th SplitMix64 output plus one half, times 2^-52.  Every operation is
+ * exact, and the value lies strictly inside (0, 1). */
+static double orc_uniform(uint64_t seed, uint64_t k)
+{
+    uint64_t w = orc_row_word(seed, k);
+    return ((double)(w >> 12) + 0.5) * 0x1p-52;
+}
+
+/* Shared by the two rules: the relative-error or residual stop test of
+ * orc_mwrk on x_k.  r (d) must hold bt - At x_k when stop_mode is REL_RESID. */
+static int orc_stop_met(int stop_mode, double err2, double xref2, double r2, double bt2, double tol)
+{
+    if (stop_mode == ORC_STOP_REL_ERR)
+        return xref2 > 0.0 ? (err2 / xref2 <= tol * tol) : (err2 <= tol * tol);
+    return r2 <= tol * tol * bt2;
+}
+
+/* Relaxed greedy randomized Kaczmarz on (At, bt), d x n, from x0 (NULL: 0).
+ *
+ * Iteration k (stop test first, exactly as in orc_mwrk):
+ *   1. r_i = bt_i - At^(i) x_k (column order), R = ||r||^2 (row order);
+ *      F = ||At||_F^2 = sum of the squared row norms (row order, once);
+ *   2. M = max of r_i^2 / ||At^(i)||^2 over rows of nonzero norm (none:
+ *      DEGENERATE; a NaN or infinite value: NONFINITE);
+ *   3. the working set: rows of nonzero norm with
+ *        |r_i|^2 >= eps_k R ||At^(i)||^2,  eps_k = theta M / R + (1 - theta) / F,
+ *      tested in the equivalent form r_i^2 / ||At^(i)||^2 >= t_k with
+ *      t_k = theta M + (1 - theta) (R / F) (multiply eps_k by R, divide by
+ *      the row's squared norm).  In exact arithmetic t_k <= M, because M is
+ *      at least R / F, the norm-weighted mean of the scores; t_k is capped at
+ *      M so that rounding never empties the set;
+ *   4. i_k is drawn from the set with probability r_i^2 over the sum of r_j^2
+ *      in the set: with E_i = -log(u_i), u_i the (k d + i)-th uniform of the
+ *      selection stream (a unit exponential per row), i_k is the member with
+ *      the largest r_i^2 / E_i, the lowest index on ties (the smallest of
+ *      independent exponential clocks with rates r_i^2 falls on row i with
+ *      probability r_i^2 over their sum; Efraimidis & Spirakis);
+ *   5. x_{k+1} = x_k + (r_{i_k} / ||At^(i_k)||^2) At^(i_k)^T.
+ * theta must lie in [0, 1].  Traces as in orc_mwrk. */
+int orc_rgrk(const double* At, int64_t d, int64_t n, int64_t ldat, const double* bt,
+             const double* x0, const double* xref, double tol, int64_t maxit, int stop_mode,
+             double theta, uint64_t sel_seed,
+             double* x, int64_t* iters, int64_t* trace_idx, double* trace_err2, double* trace_r)
+{
+    if (d < 1 || n < 1 || ldat < n || maxit < 0) return ORC_ERR_INVALID_ARG;
+    if (!(theta >= 0.0 && theta <= 1.0)) return ORC_ERR_INVALID_ARG;
+    if (stop_mode == ORC_STOP_REL_ERR && xref == NULL) return ORC_ERR_INVALID_ARG;
+
+    double* nu2 = (double*)malloc(sizeof(double) * (size_t)d);
+    double* r = (double*)malloc(sizeof(double) * (size_t)d);
+    orc_row_norms2(At, d, n, ldat, nu2);
+    double fro2 = 0.0;
+    for (int64_t i = 0; i < d; ++i) fro2 = fro2 + nu2[i];
+
+    for (int64_t c = 0; c < n; ++c) x[c] = x0 ? x0[c] : 0.0;
+    double xref2 = 0.0, bt2 = 0.0;
+    if (xref)
+        for (int64_t c = 0; c < n; ++c) xref2 = xref2 + xref[c] * xref[c];
+    for (int64_t i = 0; i < d; ++i) bt2 = bt2 + bt[i] * bt[i];
+
+    int status = ORC_NOT_CONVERGED;
+    int64_t k = 0;
+    for (;; ++k) {
+        double err2 = 0.0;
+        if (xref) {
+            for (int64_t c = 0; c < n; ++c) {
+                double e = x[c] - xref[c];
+                err2 = err2 + e * e;
+            }
+            if (trace_err2) trace_err2[k] = err2;
+        }
+        double r2 = 0.0;
+        for (int64_t i = 0; i < d; ++i) {
+            double dot = 0.0;
+            for (int64_t c = 0; c < n; ++c) dot = dot + At[i * ldat + c] * x[c];
+            r[i] = bt[i] - dot;
+            r2 = r2 + r[i] * r[i];
+        }
+        if (orc_stop_met(stop_mode, err2, xref2, r2, bt2, tol)) { status = ORC_OK; break; }
+        if (k == maxit) { status = ORC_NOT_CONVERGED; break; }
+
+        /* step 2 */
+        int found = 0, nonfinite = 0;
+        double M = 0.0;
+        for (int64_t i = 0; i < d; ++i) {
+            if (!(nu2[i] > 0.0)) {
+                if (isnan(nu2[i])) nonfinite = 1;
+                continue;
+            }
+            double s = (r[i] * r[i]) / nu2[i];
+            if (!isfinite(s)) { nonfinite = 1; break; }
+            if (!found || s > M) M = s;
+            found = 1;
+        }
+        if (nonfinite) { status = ORC_ERR_NONFINITE; break; }
+        if (!found) { status = ORC_ERR_DEGENERATE; break; }
+        /* step 3 */
+        double t = theta * M + (1.0 - theta) * (r2 / fro2);
+        if (t > M) t = M;
+        /* step 4 */
+        int64_t best = -1;
+        double best_key = 0.0;
+        for (int64_t i = 0; i < d; ++i) {
+            if (!(nu2[i] > 0.0)) continue;
+            if (!((r[i] * r[i]) / nu2[i] >= t)) continue;
+            double e = -log(orc_uniform(sel_seed, (uint64_t)k * (uint64_t)d + (uint64_t)i));
+            double key = (r[i] * r[i]) / e;
+            if (best < 0 || key > best_key) { best = i; best_key = key; }
+        }
+        if (trace_idx) trace_idx[k] = best;
+        if (trace_r) trace_r[k] = r[best];
+        /* step 5 */
+        double alpha = r[best] / nu2[best];
+        for (int64_t c = 0; c < n; ++c) x[c] = x[c] + alpha * At[best * ldat + c];
+    }
+    *iters = k;
+    free(nu2);
+    free(r);
+    return status;
+}
+
+/* Randomized Kaczmarz on (At, bt): each iteration draws row i with
+ * probability ||At^(i)||^2 / ||At||_F^2, independently of x, and projects
+ * onto it.  The draw inverts the cumulative distribution: C_i = sum of the
+ * squared norms of rows 0..i (in index order, once), t_k = u_k C_{d-1} with
+ * u_k the k-th uniform of the selection stream, and i_k the smallest i with
+ * C_i > t_k (rows of zero norm never qualify; C_{d-1} = 0: DEGENERATE).
+ * Only the selected row's residual r_{i_k} = bt_i - At^(i) x_k is formed, so
+ * the stop test is the relative error (stop_mode REL_ERR) alone; the other
+ * arguments and the traces are as in orc_mwrk. */
+int orc_rk(const double* At, int64_t d, int64_t n, int64_t ldat, const double* bt,
+           const double* x0, const double* xref, double tol, int64_t maxit, uint64_t sel_seed,
+           double* x, int64_t* iters, int64_t* trace_idx, double* trace_err2, double* trace_r)
+{
+    if (d < 1 || n < 1 || ldat < n || maxit < 0 || xref == NULL) return ORC_ERR_INVALID_ARG;
+
+    double* nu2 = (double*)malloc(sizeof(double) * (size_t)d);
+    double* cum = (double*)malloc(sizeof(double) * (size_t)d);
+    orc_row_norms2(At, d, n, ldat, nu2);
+    double acc = 0.0;
+    for (int64_t i = 0; i < d; ++i) {
+        acc = acc + nu2[i];
+        cum[i] = acc;
+    }
+    for (int64_t c = 0; c < n; ++c) x[c] = x0 ? x0[c] : 0.0;
+    double xref2 = 0.0;
+    for (int64_t c = 0; c < n; ++c) xref2 = xref2 + xref[c] * xref[c];
+
+    int status = ORC_NOT_CONVERGED;
+    int64_t k = 0;
+    for (;; ++k) {
+        double err2 = 0.0;
+        for (int64_t c = 0; c < n; ++c) {
+            double e = x[c] - xref[c];
+            err2 = err2 + e * e;
+        }
+        if (trace_err2) trace_err2[k] = err2;
+        if (orc_stop_met(ORC_STOP_REL_ERR, err2, xref2, 0.0, 0.0, tol)) { status = ORC_OK; break; }
+        if (k == maxit) { status = ORC_NOT_CONVERGED; break; }
+        if (!isfinite(cum[d - 1])) { status = ORC_ERR_NONFINITE; break; }
+        if (!(cum[d - 1] > 0.0)) { status = ORC_ERR_DEGENERATE; break; }
+        double t = orc_uniform(sel_seed, (uint64_t)k) * cum[d - 1];
+        int64_t i = 0;
+        while (!(cum[i] > t)) ++i;  /* terminates: t < cum[d-1] */
+        double dot = 0.0;
+        for (int64_t c = 0; c < n; ++c) dot = dot + At[i * ldat + c] * x[c];
+        double ri = bt[i] - dot;
+        if (!isfinite(ri)) { status = ORC_ERR_NONFINITE; break; }
+        if (trace_idx) trace_idx[k] = i;
+        if (trace_r) trace_r[k] = ri;
+        double alpha = ri / nu2[i];
+        for (int64_t c = 0; c < n; ++c) x[c] = x[c] + alpha * At[i * ldat + c];
+    }
+    *iters = k;
+    free(nu2);
+    free(cum);
+    return status;
+}
+
+/* The uniforms themselves, for the tests of the draws. */
+void orc_uniform_stream(uint64_t sel_seed, int64_t first, int64_t count, double* out)
+{
+    for (int64_t k = 0; k < count; ++k) out[k] = orc_uniform(sel_seed, (uint64_t)(first + k));
 }
