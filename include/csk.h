@@ -227,6 +227,50 @@ csk_status csk_solve(const void* At, csk_dtype at_dtype, int64_t ldat,
                      const csk_solve_opts* opts /*host*/, csk_solve_result* res,
                      void* ws, size_t ws_bytes, void* stream);
 
+/* ---- Randomized selection rules on the FP64 sketch --------------------- *
+ * The introduction places Algorithm 1's loop in a family of row-selection
+ * rules and Section 3 compares it with two of them; these calls run the loop
+ * with such a rule in place of the greedy one.  Both take the FP64 At (d x n,
+ * leading dimension ldat), bt, nu2 (nullable: computed into ws), x0
+ * (nullable: zero), x and opts as csk_solve does (refresh_every, grid and
+ * single_wg of opts apply as there; the memory contract on At is csk_solve's),
+ * and draw their random numbers from the selection stream of sel_seed: its
+ * k-th uniform is (top 52 bits of the k-th SplitMix64 output of sel_seed
+ * + 1/2) * 2^-52, strictly inside (0, 1).  Same seed, same inputs and same
+ * launch shape give the same result.
+ *
+ * csk_solve_rgrk: the relaxed greedy randomized rule of Bai & Wu (theta in
+ *   [0, 1]; theta = 1/2 is their greedy randomized Kaczmarz, theta = 1 the
+ *   greedy rule up to exact ties).  At iteration k, with r = bt - At x_k,
+ *   M the largest r_i^2 / ||At^(i)||^2 over rows of nonzero norm,
+ *   R = ||r||^2 and F = ||At||_F^2 (the sum of nu2), the working set is
+ *   the rows of nonzero norm with r_i^2 / ||At^(i)||^2 >= t_k,
+ *   t_k = min(M, theta M + (1 - theta) R / F) (the published test
+ *   |r_i|^2 >= eps_k ||r||^2 ||At^(i)||^2 rewritten; the cap keeps the best
+ *   row in the set under rounding), and i_k is the member with the largest
+ *   r_i^2 / E_i, E_i = -log(uniform k d + i), lowest index on ties: row i
+ *   with probability r_i^2 over the members' sum.  Requires 1 <= n <= 8192,
+ *   d < 2^31; each workgroup keeps its rows' residuals in LDS (too many rows
+ *   per workgroup: CSK_ERR_UNSUPPORTED, ask for a larger grid).
+ * csk_solve_rk: randomized Kaczmarz (Strohmer & Vershynin): row i with
+ *   probability ||At^(i)||^2 / ||At||_F^2 each iteration, i_k the smallest i
+ *   with C_i > u_k C_{d-1}, C the cumulative sums of nu2 in index order and
+ *   u_k the k-th uniform.  Only the drawn row's residual is formed, so the
+ *   stop mode must be CSK_STOP_REL_ERR (else CSK_ERR_INVALID_ARG).  One
+ *   workgroup; requires 1 <= n <= 8192, d < 2^31.                           */
+csk_status csk_solve_rgrk_workspace_size(int64_t d, int64_t n, size_t* bytes /*host*/);
+csk_status csk_solve_rgrk(const double* At, int64_t ldat, int64_t d, int64_t n,
+                          const double* bt, const double* nu2, const double* x0, double* x,
+                          double theta, uint64_t sel_seed,
+                          const csk_solve_opts* opts /*host*/, csk_solve_result* res,
+                          void* ws, size_t ws_bytes, void* stream);
+csk_status csk_solve_rk_workspace_size(int64_t d, int64_t n, size_t* bytes /*host*/);
+csk_status csk_solve_rk(const double* At, int64_t ldat, int64_t d, int64_t n,
+                        const double* bt, const double* nu2, const double* x0, double* x,
+                        uint64_t sel_seed,
+                        const csk_solve_opts* opts /*host*/, csk_solve_result* res,
+                        void* ws, size_t ws_bytes, void* stream);
+
 /* ---- The MWRK loop on a CSR sketch (Algorithm 1, loop) ------------------ *
  * The loop of csk_solve in FP64 with At given as CSR (at_row_ptr d + 1
  * int64 with at_row_ptr[0] = 0 and at_row_ptr[d] = nnz, at_col int32 in

@@ -37,6 +37,8 @@ EXPORTED = [
     "csk_sketch_csr_sparse_workspace_size", "csk_sketch_csr_sparse",
     "csk_solve_workspace_size", "csk_solve",
     "csk_solve_csr_workspace_size", "csk_solve_csr",
+    "csk_solve_rgrk_workspace_size", "csk_solve_rgrk",
+    "csk_solve_rk_workspace_size", "csk_solve_rk",
     "csk_solve_batched_workspace_size", "csk_solve_batched",
     "csk_solve_mrhs_workspace_size", "csk_solve_mrhs",
     "csk_tune_solve_workspace_size", "csk_tune_solve", "csk_tune_lookup", "csk_tune_clear",
@@ -126,6 +128,16 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.csk_solve_csr.restype = I32
     lib.csk_solve_csr.argtypes = [P, P, P, I64, I64, I64, P, P, P, P,
                                   ctypes.POINTER(SolveOpts), P, P, SZ, P]
+    lib.csk_solve_rgrk_workspace_size.restype = I32
+    lib.csk_solve_rgrk_workspace_size.argtypes = [I64, I64, PSZ]
+    lib.csk_solve_rgrk.restype = I32
+    lib.csk_solve_rgrk.argtypes = [P, I64, I64, I64, P, P, P, P, ctypes.c_double, U64,
+                                   ctypes.POINTER(SolveOpts), P, P, SZ, P]
+    lib.csk_solve_rk_workspace_size.restype = I32
+    lib.csk_solve_rk_workspace_size.argtypes = [I64, I64, PSZ]
+    lib.csk_solve_rk.restype = I32
+    lib.csk_solve_rk.argtypes = [P, I64, I64, I64, P, P, P, P, U64,
+                                 ctypes.POINTER(SolveOpts), P, P, SZ, P]
     lib.csk_solve_workspace_size.restype = I32
     lib.csk_solve_workspace_size.argtypes = [I64, I64, I32, PSZ]
     lib.csk_solve.restype = I32

@@ -362,6 +362,61 @@ def csk_solve(At: torch.Tensor, bt: torch.Tensor, *, At64: Optional[torch.Tensor
     return SolveResult(x, it, st, fb, meas, nref)
 
 
+def _solve_fp64_select(name, At, bt, extra, nu2, x0, x_ref, tol, maxit, stop_mode, cancel, check_every, grid,
+                       single_wg, out, result, workspace, sync, stream):
+    _need_cuda(At, "At")
+    if At.dtype != torch.float64:
+        raise ValueError("the randomized selection rules run on the FP64 sketch")
+    ldat = _rowmajor(At, "At")
+    d, n = At.shape
+    dev = At.device
+    x = out if out is not None else torch.empty(n, dtype=torch.float64, device=dev)
+    res = result if result is not None else torch.zeros(_abi.RESULT_BYTES, dtype=torch.uint8, device=dev)
+    if workspace is None:
+        nbytes = ctypes.c_size_t(0)
+        _check(getattr(_lib, name + "_workspace_size")(d, n, ctypes.byref(nbytes)), name + "_workspace_size")
+        workspace = _workspace(nbytes.value, dev)
+    o = _opts(tol, maxit, stop_mode, 0, x_ref, cancel, check_every, grid, single_wg)
+    _check(getattr(_lib, name)(_ptr(At), ldat, d, n, _ptr(bt), _ptr(nu2), _ptr(x0), _ptr(x), *extra,
+                               ctypes.byref(o), _ptr(res), _ptr(workspace), workspace.numel(), _stream(stream)),
+           name)
+    if not sync:
+        return x, res
+    (stream or torch.cuda.current_stream()).synchronize()
+    it, st, fb, meas, nref = parse_results(res)[0]
+    return SolveResult(x, it, st, fb, meas, nref)
+
+
+def csk_solve_rgrk(At: torch.Tensor, bt: torch.Tensor, *, theta: float = 0.5, sel_seed: int = 0,
+                   nu2: Optional[torch.Tensor] = None, x0: Optional[torch.Tensor] = None,
+                   x_ref: Optional[torch.Tensor] = None, tol: float = 1e-10, maxit: int = 100000,
+                   stop_mode: Optional[int] = None, cancel: Optional[int] = None, check_every: int = 256,
+                   grid: int = 0, single_wg: int = -1, out: Optional[torch.Tensor] = None,
+                   result: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
+                   sync: bool = True, stream=None):
+    """The loop on the FP64 (At, bt) with the relaxed greedy randomized rule
+    (theta = 1/2: greedy randomized Kaczmarz; theta = 1: the greedy rule).
+
+    Returns a SolveResult when sync=True, else (x, raw_result_tensor)."""
+    if stop_mode is None:
+        stop_mode = CSK_STOP_REL_ERR if x_ref is not None else CSK_STOP_REL_RESID
+    return _solve_fp64_select("csk_solve_rgrk", At, bt, (float(theta), int(sel_seed) & (2**64 - 1)), nu2, x0,
+                              x_ref, tol, maxit, stop_mode, cancel, check_every, grid, single_wg, out, result,
+                              workspace, sync, stream)
+
+
+def csk_solve_rk(At: torch.Tensor, bt: torch.Tensor, *, x_ref: torch.Tensor, sel_seed: int = 0,
+                 nu2: Optional[torch.Tensor] = None, x0: Optional[torch.Tensor] = None, tol: float = 1e-10,
+                 maxit: int = 1000000, cancel: Optional[int] = None, check_every: int = 256,
+                 out: Optional[torch.Tensor] = None, result: Optional[torch.Tensor] = None,
+                 workspace: Optional[torch.Tensor] = None, sync: bool = True, stream=None):
+    """Randomized Kaczmarz on the FP64 (At, bt), stopped on the relative
+    error against x_ref.  Returns a SolveResult when sync=True, else
+    (x, raw_result_tensor)."""
+    return _solve_fp64_select("csk_solve_rk", At, bt, (int(sel_seed) & (2**64 - 1),), nu2, x0, x_ref, tol, maxit,
+                              CSK_STOP_REL_ERR, cancel, check_every, 0, -1, out, result, workspace, sync, stream)
+
+
 def csk_solve_batched(systems: Sequence[dict], *, lp_dtype: torch.dtype = torch.float32, tol: float = 1e-8,
                       maxit: int = 200000, refresh_every: int = 64, sync: bool = True, stream=None):
     """Sketch and solve many independent systems in one pass.

@@ -16,7 +16,7 @@ OBJDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libcsk.so")
 ARCH = os.environ.get("CSK_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["csk_api.hip", "sketch.hip", "solve.hip", "solve_csr.hip", "mrhs.hip"]
+SOURCES = ["csk_api.hip", "sketch.hip", "solve.hip", "solve_csr.hip", "solve_rk.hip", "mrhs.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -454,6 +454,91 @@ csk_status csk_solve(const void* At, csk_dtype at_dtype, int64_t ldat, const dou
     return solve_run(S, at_dtype, opts, ws, ws_bytes, as_stream(stream));
 }
 
+// ---- randomized selection rules ----------------------------------------------
+
+namespace {
+csk_status check_fp64_solve(const double* At, int64_t ldat, int64_t d, int64_t n, const double* bt, double* x,
+                            const csk_solve_opts* opts, csk_solve_result* res, const void* ws)
+{
+    csk_status st = check_opts(opts);
+    if (st != CSK_OK) return st;
+    if (d < 1 || n < 1 || d > INT32_MAX) { set_error("need 1 <= d < 2^31, n >= 1"); return CSK_ERR_INVALID_ARG; }
+    if (n > kMaxN) { set_error("n=%lld exceeds %lld", (long long)n, (long long)kMaxN); return CSK_ERR_UNSUPPORTED; }
+    if (!At || !bt || !x || !res) { set_error("At, bt, x and res are required"); return CSK_ERR_INVALID_ARG; }
+    if (ldat < n) { set_error("ldat < n"); return CSK_ERR_INVALID_ARG; }
+    if (opts->stop_mode == CSK_STOP_REL_ERR && !opts->x_ref) {
+        set_error("CSK_STOP_REL_ERR needs opts->x_ref");
+        return CSK_ERR_INVALID_ARG;
+    }
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u)) { set_error("workspace NULL or unaligned"); return CSK_ERR_INVALID_ARG; }
+    return CSK_OK;
+}
+}  // namespace
+
+csk_status csk_solve_rgrk_workspace_size(int64_t d, int64_t n, size_t* bytes)
+{
+    g_err[0] = 0;
+    if (!bytes || d < 1 || n < 1) { set_error("bad sizes"); return CSK_ERR_INVALID_ARG; }
+    *bytes = solve_rgrk_ws_bytes(d, n, 65536);
+    return CSK_OK;
+}
+
+csk_status csk_solve_rgrk(const double* At, int64_t ldat, int64_t d, int64_t n, const double* bt, const double* nu2,
+                          const double* x0, double* x, double theta, uint64_t sel_seed, const csk_solve_opts* opts,
+                          csk_solve_result* res, void* ws, size_t ws_bytes, void* stream)
+{
+    g_err[0] = 0;
+    csk_status st = check_fp64_solve(At, ldat, d, n, bt, x, opts, res, ws);
+    if (st != CSK_OK) return st;
+    if (!(theta >= 0.0 && theta <= 1.0)) { set_error("theta must lie in [0, 1]"); return CSK_ERR_INVALID_ARG; }
+    const SolvePlan plan = solve_plan(d, n, CSK_F64, ldat, At, opts);
+    if (ws_bytes < solve_rgrk_ws_bytes(d, n, plan.grid)) {
+        set_error("workspace: need %zu bytes, got %zu", solve_rgrk_ws_bytes(d, n, plan.grid), ws_bytes);
+        return CSK_ERR_WORKSPACE;
+    }
+    SolveSys S{};
+    S.At = At;
+    S.At64 = At;
+    S.bt = bt;
+    S.nu2 = nu2;
+    S.x0 = x0;
+    S.xref = opts->x_ref;
+    S.x = x;
+    S.res = res;
+    S.ldat = ldat;
+    S.ldat64 = ldat;
+    S.d = (int32_t)d;
+    S.n = (int32_t)n;
+    S.stop_mode = opts->stop_mode;
+    return solve_rgrk_run(S, opts, theta, sel_seed, ws, ws_bytes, as_stream(stream));
+}
+
+csk_status csk_solve_rk_workspace_size(int64_t d, int64_t n, size_t* bytes)
+{
+    g_err[0] = 0;
+    if (!bytes || d < 1 || n < 1) { set_error("bad sizes"); return CSK_ERR_INVALID_ARG; }
+    *bytes = solve_rk_ws_bytes(d);
+    return CSK_OK;
+}
+
+csk_status csk_solve_rk(const double* At, int64_t ldat, int64_t d, int64_t n, const double* bt, const double* nu2,
+                        const double* x0, double* x, uint64_t sel_seed, const csk_solve_opts* opts,
+                        csk_solve_result* res, void* ws, size_t ws_bytes, void* stream)
+{
+    g_err[0] = 0;
+    csk_status st = check_fp64_solve(At, ldat, d, n, bt, x, opts, res, ws);
+    if (st != CSK_OK) return st;
+    if (opts->stop_mode != CSK_STOP_REL_ERR) {
+        set_error("randomized Kaczmarz forms one residual per iteration: stop_mode must be CSK_STOP_REL_ERR");
+        return CSK_ERR_INVALID_ARG;
+    }
+    if (ws_bytes < solve_rk_ws_bytes(d)) {
+        set_error("workspace: need %zu bytes, got %zu", solve_rk_ws_bytes(d), ws_bytes);
+        return CSK_ERR_WORKSPACE;
+    }
+    return solve_rk_run(At, ldat, d, n, bt, nu2, x0, x, opts, sel_seed, res, ws, ws_bytes, as_stream(stream));
+}
+
 // ---- tuning of the persistent solve's launch shape --------------------------
 
 csk_status csk_tune_solve_workspace_size(int64_t d, int64_t n, csk_dtype at_dtype, size_t* bytes)

@@ -238,7 +238,8 @@ struct alignas(64) XRec {
 // eight tags match: no acknowledgement wait on the writer, no second read,
 // and no cache write-back or invalidation (the workgroup's rows of At stay
 // in L2).  Payload: score, alpha, the stop measure (||x - x_ref||^2 part or
-// ||r||^2 part), row index, flags.
+// ||r||^2 part), row index, flags; with `both`, ||r||^2 and ||x - x_ref||^2
+// in place of alpha and the stop measure (alpha then reads zero).
 __device__ __forceinline__ double join_f64(uint64_t lo, uint64_t hi)
 {
     return __longlong_as_double((long long)((hi << 32) | (lo & 0xFFFFFFFFull)));
@@ -246,13 +247,15 @@ __device__ __forceinline__ double join_f64(uint64_t lo, uint64_t hi)
 
 template <int NT>
 __device__ __forceinline__ GridRed exchange(const GridRed& mine, XRec* exch, int wg, int G, int64_t k, GridRed* slots,
-                                            bool rel_err)  // slots: reduced with block_red1
+                                            bool rel_err, bool both = false)  // slots: reduced with block_red1
 {
     XRec* slot = exch + (size_t)(k & 1) * G;
     const uint64_t tag = static_cast<uint64_t>(static_cast<uint32_t>(k + 1)) << 32;
     if (threadIdx.x < 8) {
         const int f = threadIdx.x;
-        const double dv = f < 2 ? mine.score : f < 4 ? mine.r : (rel_err ? mine.e2 : mine.r2);
+        const double dv = f < 2 ? mine.score
+                          : f < 4 ? (both ? mine.r2 : mine.r)
+                                  : ((rel_err || both) ? mine.e2 : mine.r2);
         const uint64_t bits = static_cast<uint64_t>(__double_as_longlong(dv));
         const uint32_t p = f < 6 ? static_cast<uint32_t>((f & 1) ? (bits >> 32) : bits)
                                  : (f == 6 ? mine.idx : mine.flags);
@@ -264,7 +267,8 @@ __device__ __forceinline__ GridRed exchange(const GridRed& mine, XRec* exch, int
         GridRed o;
         if (w == wg) {
             o = mine;  // this workgroup's own record needs no round trip
-            if (rel_err) o.r2 = 0.0;
+            if (both) o.r = 0.0;
+            else if (rel_err) o.r2 = 0.0;
             else o.e2 = 0.0;
         } else {
             // Poll one word of the record (one request per record and round:
@@ -292,10 +296,11 @@ __device__ __forceinline__ GridRed exchange(const GridRed& mine, XRec* exch, int
             }
             if (!ok) break;
             o.score = join_f64(v[0], v[1]);
-            o.r = join_f64(v[2], v[3]);
-            const double meas = join_f64(v[4], v[5]);
-            o.r2 = rel_err ? 0.0 : meas;
-            o.e2 = rel_err ? meas : 0.0;
+            const double w23 = join_f64(v[2], v[3]);
+            const double w45 = join_f64(v[4], v[5]);
+            o.r = both ? 0.0 : w23;
+            o.r2 = both ? w23 : (rel_err ? 0.0 : w45);
+            o.e2 = (both || rel_err) ? w45 : 0.0;
             o.idx = static_cast<uint32_t>(v[6]);
             o.flags = static_cast<uint32_t>(v[7]);
         }

@@ -25,6 +25,14 @@ __host__ __device__ __forceinline__ uint64_t draw_word(uint64_t seed, uint64_t r
     return z ^ (z >> 31);
 }
 
+// Uniforms of the randomized selection rules: the k-th of a stream is the
+// top 52 bits of the k-th SplitMix64 output of its seed plus one half, times
+// 2^-52 (every step exact; strictly inside (0, 1)).
+__device__ __forceinline__ double select_uniform(uint64_t seed, uint64_t k)
+{
+    return (static_cast<double>(draw_word(seed, k) >> 12) + 0.5) * 0x1p-52;
+}
+
 __device__ __forceinline__ uint32_t draw_bucket(uint64_t w, uint32_t d)
 {
     return __umulhi(static_cast<uint32_t>(w >> 32), d);

@@ -41,6 +41,18 @@ int solve_batch_lpr();
 csk_status solve_run(const SolveSys& sys, csk_dtype at_dtype, const csk_solve_opts* o,
                      void* ws, size_t ws_bytes, hipStream_t st, const SolvePlan* forced = nullptr);
 
+// The relaxed greedy randomized selection rule (FP64 At64 only; theta in
+// [0, 1], selection stream seed sel_seed) in place of the greedy one.
+size_t solve_rgrk_ws_bytes(int64_t d, int64_t n, int grid);
+csk_status solve_rgrk_run(const SolveSys& sys, const csk_solve_opts* o, double theta, uint64_t sel_seed,
+                          void* ws, size_t ws_bytes, hipStream_t st);
+
+// Randomized Kaczmarz (one workgroup; stop mode REL_ERR; n <= 8192).
+size_t solve_rk_ws_bytes(int64_t d);
+csk_status solve_rk_run(const double* At, int64_t ldat, int64_t d, int64_t n, const double* bt, const double* nu2,
+                        const double* x0, double* x, const csk_solve_opts* o, uint64_t sel_seed,
+                        csk_solve_result* res, void* ws, size_t ws_bytes, hipStream_t st);
+
 // Lanes per row with the least padded coverage, vector width of the
 // working matrix, and the cache of tuned launch shapes.
 int pick_lpr(int64_t n, int64_t per_lane);

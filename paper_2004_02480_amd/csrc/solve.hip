@@ -72,7 +72,9 @@ struct Ctl {
     int32_t nsys;
     int32_t res_layers;    // LDS-resident chunks per lane group (capacity)
     int32_t xslice;        // LDS doubles for the workgroup's slice of x_ref
-    int32_t pad_;
+    int32_t rres;          // relaxed greedy randomized rule: LDS residuals per workgroup
+    double theta;          // ... its relaxation parameter
+    uint64_t sel_seed;     // ... and the seed of its selection stream
 };
 
 // Element access.  A chunk slot holds one 16-byte vector per k (VW elements)
@@ -328,7 +330,7 @@ __device__ __forceinline__ void stream_rows(const typename Elem<Tag>::S* __restr
         if constexpr (std::is_same<Tag, tag_f16>::value) r = pr - static_cast<double>(s) * dscale;  // scaled operand
         else r = pr - static_cast<double>(s);
         if constexpr (ROUT) {
-            rout[row] = r;
+            if (rout) rout[row] = r;
             if (crow < nrow_out) lrout[crow * NG + g] = r;
         }
         if (q == 0) loc.r2 += r * r;
@@ -434,17 +436,18 @@ __device__ void fill_resident(const typename Elem<Tag>::S* __restrict__ A, int64
 }
 
 // LDS carve of the solve: x (FP64), x - x_ref in the accumulation type
-// (mixed), this workgroup's slice of x_ref, then the resident right-hand
-// sides and norms and the resident chunks (16-byte aligned).
+// (mixed), this workgroup's slice of x_ref, the residuals of its rows (the
+// relaxed greedy randomized rule), then the resident right-hand sides and
+// norms and the resident chunks (16-byte aligned).
 struct SolveLds {
-    size_t sx, sd, sdb, sxr, lrhs, lnn, chunks, total;
+    size_t sx, sd, sdb, sxr, sres, lrhs, lnn, chunks, total;
 };
 
 __host__ __device__ inline size_t al_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // mixed: x - x_ref in FP32 (4 bytes per element); op16: also its 16-bit copy
 __host__ __device__ inline SolveLds solve_lds(int npad, bool mixed, int xslice, int L, int ng, int layer_bytes,
-                                              bool op16 = false)
+                                              bool op16 = false, int rres = 0)
 {
     SolveLds o;
     size_t at = 0;
@@ -458,6 +461,8 @@ __host__ __device__ inline SolveLds solve_lds(int npad, bool mixed, int xslice, 
     at = al_up(at, 8);
     o.sxr = at;
     at += (size_t)xslice * 8;
+    o.sres = at;
+    at += (size_t)rres * 8;
     o.lrhs = at;
     at += (size_t)L * ng * 8;
     o.lnn = at;
@@ -469,10 +474,28 @@ __host__ __device__ inline SolveLds solve_lds(int npad, bool mixed, int xslice, 
     return o;
 }
 
-template <class Tag, bool VEC, int LPR, bool GRID, bool M>
+// The relaxed greedy randomized rule's threshold t_k = theta M + (1 - theta)
+// (R / F), capped at M, as separate IEEE operations (no fused multiply-add).
+__device__ __forceinline__ double rgrk_threshold(double theta, double M, double R, double F)
+{
+#pragma clang fp contract(off)
+    const double t = theta * M + (1.0 - theta) * (R / F);
+    return t > M ? M : t;
+}
+
+// SEL 0: the greedy rule of Algorithm 1 (largest weighted residual).
+// SEL 1: the relaxed greedy randomized rule (FP64 only): after the first
+// reduction (largest score M, ||r||^2 = R, stop measure) every workgroup
+// forms its rows' working-set test r_i^2 / ||At^(i)||^2 >= t_k from the
+// residuals it kept in LDS, gives each member the key r_i^2 / E_i with E_i
+// = -log(u) a unit exponential from the selection stream (position k d + i),
+// and a second reduction picks the largest key: row i wins with probability
+// r_i^2 over the members' sum.
+template <class Tag, bool VEC, int LPR, bool GRID, bool M, int SEL = 0>
 __device__ __forceinline__ void solve_loop(const SolveSys& S, const Ctl& C, XRec* exch, int wg, int G, char* smem)
 {
     constexpr bool MIXED = !std::is_same<Tag, tag_f64>::value;
+    static_assert(SEL == 0 || !MIXED, "the randomized rule runs on the FP64 sketch");
     using LPS = typename Elem<Tag>::S;
     using LAcc = typename Elem<Tag>::Acc;
     constexpr int SW64 = LPR * (VEC ? 2 : 1) * kK;
@@ -502,11 +525,12 @@ __device__ __forceinline__ void solve_loop(const SolveSys& S, const Ctl& C, XRec
     const int L = min(C.res_layers, gmax_rows * nseg_res);
 
     constexpr bool OP16 = op16<Tag>();
-    const SolveLds lay = solve_lds(npad, MIXED, C.xslice, C.res_layers, NG, LAYER, OP16);
+    const SolveLds lay = solve_lds(npad, MIXED, C.xslice, C.res_layers, NG, LAYER, OP16, SEL ? C.rres : 0);
     double* sx = reinterpret_cast<double*>(smem + lay.sx);   // x, FP64, zero past n
     LAcc* sd = reinterpret_cast<LAcc*>(smem + lay.sd);       // x - x_ref (mixed), zero past n
     uint16_t* sdb = reinterpret_cast<uint16_t*>(smem + lay.sdb);  // its 16-bit copy (OP16)
     double* sxr = reinterpret_cast<double*>(smem + lay.sxr); // x_ref[e0 .. e1)
+    double* sres = reinterpret_cast<double*>(smem + lay.sres);  // r_i of rows r0 + j (SEL 1)
     double* lrhs = reinterpret_cast<double*>(smem + lay.lrhs);
     double* lnn = reinterpret_cast<double*>(smem + lay.lnn);
     uint4* lchunks = reinterpret_cast<uint4*>(smem + lay.chunks);
@@ -538,6 +562,12 @@ __device__ __forceinline__ void solve_loop(const SolveSys& S, const Ctl& C, XRec
     q = block_red<kNT>(q, slots);
     const double xref2 = q.e2;
     const double bt2 = q.r2;
+    double fro2 = 0.0;  // ||At||_F^2 (SEL 1)
+    if constexpr (SEL == 1) {
+        Red f = red_identity();
+        for (int i = tid; i < d; i += kNT) f.r2 += S.nu2[i];
+        fro2 = block_red<kNT>(f, slots).r2;
+    }
     const double tol2 = C.tol2;
     const bool rel_err = S.stop_mode == CSK_STOP_REL_ERR;
 
@@ -567,6 +597,10 @@ __device__ __forceinline__ void solve_loop(const SolveSys& S, const Ctl& C, XRec
         } else if (MIXED && exact) {
             stream_rows<tag_f64, VEC, LPR, 2, false, M>(S.At64, S.ldat64, n, nseg64, r0, r1, sx, S.bt, nullptr, S.nu2,
                                                      loc, none, nullptr, 0);
+        } else if constexpr (!MIXED && SEL == 1) {
+            stream_rows<tag_f64, VEC, LPR, ring_depth<tag_f64>(), true, M>(S.At64, S.ldat64, n, nseg64, r0, r1, sx,
+                                                                        S.bt, nullptr, S.nu2, loc, res, sres,
+                                                                        gmax_rows);
         } else if constexpr (!MIXED) {
             stream_rows<tag_f64, VEC, LPR, ring_depth<tag_f64>(), false, M>(S.At64, S.ldat64, n, nseg64, r0, r1, sx,
                                                                          S.bt, nullptr, S.nu2, loc, res, nullptr, 0);
@@ -583,7 +617,7 @@ __device__ __forceinline__ void solve_loop(const SolveSys& S, const Ctl& C, XRec
         if (wg == 0 && tid == 0 && C.cancel && (k % C.check_every) == 0 && *C.cancel != 0)
             loc.flags |= kFlagCancel;
         Red tot = block_red1<kNT>(loc, slots);
-        if constexpr (GRID) tot = exchange<kNT>(tot, exch, wg, G, k, slots2, rel_err);
+        if constexpr (GRID) tot = exchange<kNT>(tot, exch, wg, G, k, slots2, rel_err, SEL == 1);
 
         // Stop test on x_k (top of iteration k).
         bool conv;
@@ -613,9 +647,37 @@ __device__ __forceinline__ void solve_loop(const SolveSys& S, const Ctl& C, XRec
             hist1 = m_now;
         }
 
+        double alpha = tot.r;
+        uint32_t pick = tot.idx;
+        if constexpr (SEL == 1) {
+            const double thr = rgrk_threshold(C.theta, tot.score, tot.r2, fro2);
+            const uint64_t base = static_cast<uint64_t>(k) * static_cast<uint64_t>(d);
+            Red cand = red_identity();
+            for (int j = tid; j < r1 - r0; j += kNT) {
+                const double nn = S.nu2[r0 + j];
+                if (!(nn > 0.0)) continue;
+                const double r = sres[j];
+                const double w = r * r;
+                if (!(w / nn >= thr)) continue;
+                const double e = -log(select_uniform(C.sel_seed, base + static_cast<uint64_t>(r0 + j)));
+                const double key = w / e;
+                if (cand_better(key, static_cast<uint32_t>(r0 + j), cand.score, cand.idx)) {
+                    cand.score = key;
+                    cand.r = r / nn;
+                    cand.idx = static_cast<uint32_t>(r0 + j);
+                }
+            }
+            // slot arrays alternate with the reductions before (one barrier each)
+            Red t2 = block_red1<kNT>(cand, GRID ? slots : slots2);
+            if constexpr (GRID) t2 = exchange<kNT>(t2, exch + 2 * (size_t)G, wg, G, k, slots2, false);
+            if (t2.flags & kFlagTimeout) { status = CSK_ERR_DEVICE; break; }
+            if (t2.idx >= (uint32_t)d) { status = CSK_ERR_DEVICE; break; }  // the best row is always a member
+            alpha = t2.r;
+            pick = t2.idx;
+        }
+
         // Projection onto row i_k, on this workgroup's copy of x.
-        const double alpha = tot.r;
-        const double* __restrict__ arow = S.At64 + (int64_t)tot.idx * S.ldat64;
+        const double* __restrict__ arow = S.At64 + (int64_t)pick * S.ldat64;
         if (std::is_same<Tag, tag_f16>::value && refresh) {
             // ||alpha a|| = |r| / ||a|| = sqrt(score), identical in every workgroup
             int ex = 0;
@@ -669,6 +731,22 @@ __global__ __launch_bounds__(kNT) void k_solve_single(SolveSys S, Ctl C)
 {
     extern __shared__ __align__(16) char smem[];
     solve_loop<Tag, VEC, LPR, false, M>(S, C, nullptr, 0, 1, smem);
+}
+
+// The relaxed greedy randomized rule on the FP64 sketch (exchange records:
+// two sets of [2][grid]).
+template <bool VEC, int LPR, bool M>
+__global__ __launch_bounds__(kNT) void k_solve_rgrk_grid(SolveSys S, Ctl C)
+{
+    extern __shared__ __align__(16) char smem[];
+    solve_loop<tag_f64, VEC, LPR, true, M, 1>(S, C, C.exch, blockIdx.x, gridDim.x, smem);
+}
+
+template <bool VEC, int LPR, bool M>
+__global__ __launch_bounds__(kNT) void k_solve_rgrk_single(SolveSys S, Ctl C)
+{
+    extern __shared__ __align__(16) char smem[];
+    solve_loop<tag_f64, VEC, LPR, false, M, 1>(S, C, nullptr, 0, 1, smem);
 }
 
 // The batch's sketches live in the library's own layout, rows padded to 64
@@ -733,7 +811,7 @@ constexpr size_t kLdsReserve = 2048;  // static LDS of the kernels, rounded up
 // Sizes the LDS of a solve launch: the operand vectors, the x_ref slice,
 // then as many resident chunk layers as fit (never more than `want`).
 template <class Tag, int LPR>
-SolveLds plan_lds(int npad, int& xslice, int want, int& layers)
+SolveLds plan_lds(int npad, int& xslice, int want, int& layers, int rres = 0)
 {
     const bool mixed = !std::is_same<Tag, tag_f64>::value;
     constexpr bool o16 = op16<Tag>();
@@ -741,14 +819,14 @@ SolveLds plan_lds(int npad, int& xslice, int want, int& layers)
     constexpr int LAYER = kNT * chunk_k<Tag>() * 16;
     const size_t cap = (size_t)device_max_lds() - kLdsReserve;
     // the x_ref slice is a convenience: without room it is read from memory
-    if (xslice > 0 && solve_lds(npad, mixed, xslice, 0, NG, LAYER, o16).total > cap) xslice = 0;
+    if (xslice > 0 && solve_lds(npad, mixed, xslice, 0, NG, LAYER, o16, rres).total > cap) xslice = 0;
     int L = std::max(0, std::min(want, kMaxResLayers));
-    while (L > 0 && solve_lds(npad, mixed, xslice, L, NG, LAYER, o16).total > cap) --L;
+    while (L > 0 && solve_lds(npad, mixed, xslice, L, NG, LAYER, o16, rres).total > cap) --L;
     layers = L;
-    return solve_lds(npad, mixed, xslice, L, NG, LAYER, o16);
+    return solve_lds(npad, mixed, xslice, L, NG, LAYER, o16, rres);
 }
 
-template <class Tag, bool VEC, int LPR, bool M>
+template <class Tag, bool VEC, int LPR, bool M, int SEL>
 csk_status launch_solve(const SolveSys& S, Ctl C, int grid, hipStream_t st)
 {
     constexpr bool mixed = !std::is_same<Tag, tag_f64>::value;
@@ -759,14 +837,17 @@ csk_status launch_solve(const SolveSys& S, Ctl C, int grid, hipStream_t st)
     const int rows_per = (S.d + g - 1) / g;
     const int want = ((rows_per + NG - 1) / NG) * nseg;
     C.xslice = S.xref ? (S.n + g - 1) / g : 0;
-    const SolveLds lay = plan_lds<Tag, LPR>(S.npad, C.xslice, want, C.res_layers);
+    C.rres = SEL ? ((rows_per + NG - 1) / NG) * NG : 0;
+    const SolveLds lay = plan_lds<Tag, LPR>(S.npad, C.xslice, want, C.res_layers, C.rres);
     const size_t shm = lay.total;
     if (shm > (size_t)device_max_lds() - kLdsReserve) {
-        set_error("the solve needs %zu bytes of LDS per workgroup (n = %d too large)", shm, S.n);
+        set_error("the solve needs %zu bytes of LDS per workgroup (n = %d, or rows per workgroup, too large)", shm,
+                  S.n);
         return CSK_ERR_UNSUPPORTED;
     }
     if (grid <= 1) {
         auto kern = k_solve_single<Tag, VEC, LPR, M>;
+        if constexpr (SEL == 1) kern = k_solve_rgrk_single<VEC, LPR, M>;
         CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
         kern<<<1, kNT, shm, st>>>(S, C);
@@ -774,6 +855,7 @@ csk_status launch_solve(const SolveSys& S, Ctl C, int grid, hipStream_t st)
         return CSK_OK;
     }
     auto kern = k_solve_grid<Tag, VEC, LPR, M>;
+    if constexpr (SEL == 1) kern = k_solve_rgrk_grid<VEC, LPR, M>;
     CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
     int per_cu = 0;
@@ -791,24 +873,24 @@ csk_status launch_solve(const SolveSys& S, Ctl C, int grid, hipStream_t st)
     return CSK_OK;
 }
 
-template <class Tag, bool VEC, bool M>
+template <class Tag, bool VEC, bool M, int SEL>
 csk_status dispatch_lpr(const SolveSys& S, const Ctl& C, const SolvePlan& p, hipStream_t st)
 {
     switch (p.lpr) {
-    case 4: return launch_solve<Tag, VEC, 4, M>(S, C, p.grid, st);
-    case 16: return launch_solve<Tag, VEC, 16, M>(S, C, p.grid, st);
-    default: return launch_solve<Tag, VEC, 64, M>(S, C, p.grid, st);
+    case 4: return launch_solve<Tag, VEC, 4, M, SEL>(S, C, p.grid, st);
+    case 16: return launch_solve<Tag, VEC, 16, M, SEL>(S, C, p.grid, st);
+    default: return launch_solve<Tag, VEC, 64, M, SEL>(S, C, p.grid, st);
     }
 }
 
-template <class Tag>
+template <class Tag, int SEL = 0>
 csk_status dispatch_solve(const SolveSys& S, const Ctl& C, const SolvePlan& p, hipStream_t st)
 {
     // whole vectors: n a multiple of the working type's vector width (and
     // so of FP64's, for the refresh product)
-    if (p.vw > 1 && S.n % Elem<Tag>::kVec == 0) return dispatch_lpr<Tag, true, false>(S, C, p, st);
-    if (p.vw > 1) return dispatch_lpr<Tag, true, true>(S, C, p, st);
-    return dispatch_lpr<Tag, false, true>(S, C, p, st);
+    if (p.vw > 1 && S.n % Elem<Tag>::kVec == 0) return dispatch_lpr<Tag, true, false, SEL>(S, C, p, st);
+    if (p.vw > 1) return dispatch_lpr<Tag, true, true, SEL>(S, C, p, st);
+    return dispatch_lpr<Tag, false, true, SEL>(S, C, p, st);
 }
 
 constexpr int kBatchLPR = 16;
@@ -1108,6 +1190,46 @@ csk_status solve_run(const SolveSys& sys_in, csk_dtype at_dtype, const csk_solve
     case CSK_BF16: return dispatch_solve<tag_bf16>(S, C, plan, st);
     default: return CSK_ERR_UNSUPPORTED;
     }
+}
+
+size_t solve_rgrk_ws_bytes(int64_t d, int64_t n, int grid)
+{
+    (void)n;
+    Carve c(nullptr);
+    c.take<XRec>(4 * (size_t)std::max(grid, 1));
+    c.take<double>(d);  // nu2 when not supplied
+    return c.bytes();
+}
+
+csk_status solve_rgrk_run(const SolveSys& sys_in, const csk_solve_opts* o, double theta, uint64_t sel_seed,
+                          void* ws, size_t ws_bytes, hipStream_t st)
+{
+    SolveSys S = sys_in;
+    const SolvePlan plan = solve_plan(S.d, S.n, CSK_F64, S.ldat64, S.At64, o);
+    S.npad = (int32_t)solve_npad(S.n, CSK_F64, plan.lpr, plan.vw > 1);
+    S.rref = nullptr;
+    Carve c(ws);
+    Ctl C = make_ctl(o);
+    C.theta = theta;
+    C.sel_seed = sel_seed;
+    C.exch = c.take<XRec>(4 * (size_t)std::max(plan.grid, 1));
+    double* nu2_ws = c.take<double>(S.d);
+    if (c.bytes() > ws_bytes) {
+        set_error("solve workspace too small: need %zu bytes, got %zu", c.bytes(), ws_bytes);
+        return CSK_ERR_WORKSPACE;
+    }
+    if (S.nu2 == nullptr) {
+        k_row_norms2<<<std::min(4096, (S.d + 3) / 4), 256, 0, st>>>(S.At64, S.ldat64, S.d, S.n, nu2_ws);
+        CSK_LAUNCH_CHECK("k_row_norms2");
+        S.nu2 = nu2_ws;
+    }
+    if (plan.grid > 1) {
+        const int64_t words = (int64_t)4 * plan.grid * (int64_t)sizeof(XRec) / 4;
+        k_zero_words<<<(int)std::min<int64_t>(64, (words + 255) / 256), 256, 0, st>>>(
+            reinterpret_cast<uint32_t*>(C.exch), words);
+        CSK_LAUNCH_CHECK("k_zero_words");
+    }
+    return dispatch_solve<tag_f64, 1>(S, C, plan, st);
 }
 
 size_t solve_exch_record_bytes() { return sizeof(XRec); }

@@ -1,0 +1,263 @@
+// solve_rk.hip -- randomized Kaczmarz (Strohmer & Vershynin), the simplest
+// member of the row-selection family that the introduction places
+// Algorithm 1's loop in: each iteration draws row i with probability
+// ||At^(i)||^2 / ||At||_F^2, independently of x, and projects onto it.  Only
+// the drawn row's residual is formed, so an iteration reads one row.
+//
+// One workgroup runs the whole loop (one row per iteration leaves nothing to
+// spread over the chip; the cost is latency):
+//   * setup: the cumulative squared norms C_i, summed in index order by one
+//     thread over blocks staged in LDS, stored to the workspace;
+//   * the draws do not depend on x, so the rows of 512 iterations are found
+//     at once, one binary search per thread for the smallest i with
+//     C_i > u_k C_{d-1} (u_k the k-th uniform of the selection stream), and
+//     kept in LDS a batch ahead;
+//   * each thread owns columns tid + 512 j of x, x_ref and the current row
+//     (registers; the next row is loaded an iteration ahead), so an
+//     iteration is one workgroup reduction (the row's dot product with x_k
+//     and ||x_k - x_ref||^2), the stop test on x_k, and the update of the
+//     thread's own columns.
+#include "csk_grid.h"
+#include "csk_solve.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace csk {
+namespace {
+
+constexpr int kRkNT = 512;
+constexpr int kRkNW = kRkNT / kWave;
+constexpr int kRkBatch = kRkNT;     // iterations whose rows are drawn together
+constexpr int kRkStage = 4096;      // squared norms staged per block of the prefix sum
+
+struct RkArgs {
+    const double* At;
+    const double* bt;
+    const double* nu2;
+    const double* x0;
+    const double* xref;
+    double* x;
+    double* cum;  // d, workspace
+    csk_solve_result* res;
+    const volatile int32_t* cancel;
+    int64_t ldat;
+    int64_t maxit;
+    uint64_t seed;
+    double tol2;
+    int32_t d, n;
+    int32_t check_every;
+};
+
+// Smallest i with cum[i] > t; cum is non-decreasing and cum[d-1] > t when the
+// distribution is valid (otherwise the result is d - 1, never used).
+__device__ __forceinline__ int rk_search(const double* __restrict__ cum, int d, double t)
+{
+    int lo = 0, hi = d - 1;
+    while (lo < hi) {
+        const int mid = lo + ((hi - lo) >> 1);
+        if (cum[mid] > t) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+template <int J>
+__global__ __launch_bounds__(kRkNT) void k_solve_rk(RkArgs P)
+{
+    __shared__ double stage[kRkStage];
+    __shared__ int32_t pick[2][kRkBatch];
+    __shared__ double red[2][kRkNW][2];
+    __shared__ int32_t s_cancel[2];
+    __shared__ double s_total;
+    const int tid = threadIdx.x;
+    const int wave = tid / kWave;
+    const int lane = tid & (kWave - 1);
+    const int d = P.d, n = P.n;
+
+    // C_i in index order: the block is staged by every thread, summed by one
+    double acc = 0.0;
+    for (int base = 0; base < d; base += kRkStage) {
+        const int cnt = min(kRkStage, d - base);
+        for (int i = tid; i < cnt; i += kRkNT) stage[i] = P.nu2[base + i];
+        __syncthreads();
+        if (tid == 0) {
+            for (int i = 0; i < cnt; ++i) {
+                acc = acc + stage[i];
+                stage[i] = acc;
+            }
+        }
+        __syncthreads();
+        for (int i = tid; i < cnt; i += kRkNT) P.cum[base + i] = stage[i];
+        __syncthreads();
+    }
+    if (tid == 0) s_total = acc;
+    __syncthreads();
+    const double total = s_total;
+    const bool valid = isfinite(total) && total > 0.0;
+
+    auto draw_batch = [&](int64_t b) {
+        const int64_t k = b * kRkBatch + tid;
+        pick[b & 1][tid] = valid ? rk_search(P.cum, d, select_uniform(P.seed, static_cast<uint64_t>(k)) * total) : 0;
+    };
+    draw_batch(0);
+    draw_batch(1);
+
+    double x[J], xr[J], a[J];
+    for (int j = 0; j < J; ++j) {
+        const int c = tid + j * kRkNT;
+        x[j] = (c < n && P.x0) ? P.x0[c] : 0.0;
+        xr[j] = c < n ? P.xref[c] : 0.0;
+    }
+    double q = 0.0;
+    for (int j = 0; j < J; ++j) q += xr[j] * xr[j];
+    q = group_sum_t<double, kWave>(q);
+    if (lane == 0) red[1][wave][0] = q;
+    __syncthreads();
+    double xref2 = 0.0;
+    for (int w = 0; w < kRkNW; ++w) xref2 += red[1][w][0];
+
+    auto load_row = [&](int i, double (&v)[J], double& bi, double& ni) {
+        const double* __restrict__ row = P.At + (int64_t)i * P.ldat;
+        for (int j = 0; j < J; ++j) {
+            const int c = tid + j * kRkNT;
+            v[j] = c < n ? row[c] : 0.0;
+        }
+        bi = P.bt[i];
+        ni = P.nu2[i];
+    };
+    double bi, ni;
+    load_row(pick[0][0], a, bi, ni);
+
+    int32_t status = CSK_NOT_CONVERGED;
+    double meas = NAN;
+    int64_t k = 0;
+    for (;; ++k) {
+        const int par = static_cast<int>(k & 1);
+        // draw the batch after next once this batch starts
+        if (k >= kRkBatch && (k % kRkBatch) == 0) draw_batch(k / kRkBatch + 1);
+        double pd = 0.0, pe = 0.0;
+        for (int j = 0; j < J; ++j) {
+            pd += a[j] * x[j];
+            const double e = x[j] - xr[j];
+            pe += e * e;
+        }
+        // the next row, an iteration ahead
+        double an[J], bn = 0.0, nn = 0.0;
+        const int64_t k1 = k + 1;
+        const int nxt = pick[(k1 / kRkBatch) & 1][k1 % kRkBatch];
+        if (k < P.maxit) load_row(nxt, an, bn, nn);
+        else
+            for (int j = 0; j < J; ++j) an[j] = 0.0;
+        pd = group_sum_t<double, kWave>(pd);
+        pe = group_sum_t<double, kWave>(pe);
+        if (lane == 0) {
+            red[par][wave][0] = pd;
+            red[par][wave][1] = pe;
+        }
+        if (tid == 0) s_cancel[par] = (P.cancel && (k % P.check_every) == 0 && *P.cancel != 0) ? 1 : 0;
+        __syncthreads();
+        double dot = 0.0, e2 = 0.0;
+        for (int w = 0; w < kRkNW; ++w) {
+            dot += red[par][w][0];
+            e2 += red[par][w][1];
+        }
+        // stop test on x_k
+        meas = xref2 > 0.0 ? e2 / xref2 : e2;
+        if (xref2 > 0.0 ? (e2 / xref2 <= P.tol2) : (e2 <= P.tol2)) { status = CSK_OK; break; }
+        if (k == P.maxit) { status = CSK_NOT_CONVERGED; break; }
+        if (s_cancel[par]) { status = CSK_CANCELLED; break; }
+        if (!isfinite(total)) { status = CSK_ERR_NONFINITE; break; }
+        if (!(total > 0.0)) { status = CSK_ERR_DEGENERATE; break; }
+        const double r = bi - dot;
+        if (!isfinite(r)) { status = CSK_ERR_NONFINITE; break; }
+        const double alpha = r / ni;
+        for (int j = 0; j < J; ++j) {
+            x[j] = x[j] + alpha * a[j];
+            a[j] = an[j];
+        }
+        bi = bn;
+        ni = nn;
+    }
+    for (int j = 0; j < J; ++j) {
+        const int c = tid + j * kRkNT;
+        if (c < n) P.x[c] = x[j];
+    }
+    if (tid == 0 && P.res) {
+        P.res->iters = k;
+        P.res->status = status;
+        P.res->fp64_fallback = 0;
+        P.res->final_measure = meas;
+        P.res->refreshes = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_rk_norms2(const double* __restrict__ A, int64_t lda, int d, int n,
+                                                  double* __restrict__ nu2)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    for (int64_t i = blockIdx.x * 4 + threadIdx.x / kWave; i < d; i += (int64_t)gridDim.x * 4) {
+        double s = 0.0;
+        for (int c = lane; c < n; c += kWave) s += A[i * lda + c] * A[i * lda + c];
+        s = wave_sum(s);
+        if (lane == 0) nu2[i] = s;
+    }
+}
+
+}  // namespace
+
+size_t solve_rk_ws_bytes(int64_t d)
+{
+    Carve c(nullptr);
+    c.take<double>(d);  // cumulative squared norms
+    c.take<double>(d);  // nu2 when not supplied
+    return c.bytes();
+}
+
+csk_status solve_rk_run(const double* At, int64_t ldat, int64_t d, int64_t n, const double* bt, const double* nu2,
+                        const double* x0, double* x, const csk_solve_opts* o, uint64_t sel_seed,
+                        csk_solve_result* res, void* ws, size_t ws_bytes, hipStream_t st)
+{
+    Carve c(ws);
+    RkArgs P{};
+    P.cum = c.take<double>(d);
+    double* nu2_ws = c.take<double>(d);
+    if (c.bytes() > ws_bytes) {
+        set_error("solve workspace too small: need %zu bytes, got %zu", c.bytes(), ws_bytes);
+        return CSK_ERR_WORKSPACE;
+    }
+    if (nu2 == nullptr) {
+        k_rk_norms2<<<(int)std::min<int64_t>(4096, (d + 3) / 4), 256, 0, st>>>(At, ldat, (int)d, (int)n, nu2_ws);
+        CSK_LAUNCH_CHECK("k_rk_norms2");
+        nu2 = nu2_ws;
+    }
+    P.At = At;
+    P.bt = bt;
+    P.nu2 = nu2;
+    P.x0 = x0;
+    P.xref = o->x_ref;
+    P.x = x;
+    P.res = res;
+    P.cancel = o->cancel;
+    P.ldat = ldat;
+    P.maxit = o->maxit;
+    P.seed = sel_seed;
+    P.tol2 = o->tol * o->tol;
+    P.d = (int32_t)d;
+    P.n = (int32_t)n;
+    P.check_every = o->check_every > 0 ? o->check_every : 256;
+    const int64_t per = (n + kRkNT - 1) / kRkNT;
+    if (per <= 1) k_solve_rk<1><<<1, kRkNT, 0, st>>>(P);
+    else if (per <= 2) k_solve_rk<2><<<1, kRkNT, 0, st>>>(P);
+    else if (per <= 4) k_solve_rk<4><<<1, kRkNT, 0, st>>>(P);
+    else if (per <= 8) k_solve_rk<8><<<1, kRkNT, 0, st>>>(P);
+    else if (per <= 16) k_solve_rk<16><<<1, kRkNT, 0, st>>>(P);
+    else {
+        set_error("n=%lld exceeds %d", (long long)n, 16 * kRkNT);
+        return CSK_ERR_UNSUPPORTED;
+    }
+    CSK_LAUNCH_CHECK("k_solve_rk");
+    return CSK_OK;
+}
+
+}  // namespace csk

@@ -89,6 +89,19 @@ def test_invalid_arguments_rejected_on_host(lib):
                          ctypes.byref(o), P(256), P(256), 1 << 20, None) == _abi.CSK_ERR_INVALID_ARG
     msg = lib.csk_last_error().decode()
     assert "At64" in msg
+    # randomized rules: theta outside [0, 1]; randomized Kaczmarz needs the relative-error stop
+    for th in (-0.5, 1.5, float("nan")):
+        assert lib.csk_solve_rgrk(P(256), 4, 8, 4, P(256), None, None, P(256), th, 1, ctypes.byref(o), P(256),
+                                  P(256), 1 << 20, None) == _abi.CSK_ERR_INVALID_ARG
+    assert "theta" in lib.csk_last_error().decode()
+    o.stop_mode = _abi.CSK_STOP_REL_RESID
+    assert lib.csk_solve_rk(P(256), 4, 8, 4, P(256), None, None, P(256), 1, ctypes.byref(o), P(256), P(256),
+                            1 << 20, None) == _abi.CSK_ERR_INVALID_ARG
+    o.stop_mode = _abi.CSK_STOP_REL_ERR
+    assert lib.csk_solve_rk(P(256), 4, 8, 4, P(256), None, None, P(256), 1, ctypes.byref(o), P(256), P(256),
+                            16, None) == _abi.CSK_ERR_WORKSPACE
+    assert lib.csk_solve_rk(P(256), 3, 8, 4, P(256), None, None, P(256), 1, ctypes.byref(o), P(256), P(256),
+                            1 << 20, None) == _abi.CSK_ERR_INVALID_ARG
 
 
 def test_workspace_queries(lib):
@@ -101,6 +114,10 @@ def test_workspace_queries(lib):
     assert sz.value >= 20000 * 16
     assert lib.csk_sketch_csr_workspace_size(1000000, 5000, 50000, ctypes.byref(sz)) == 0
     assert lib.csk_solve_mrhs_workspace_size(10000, 500, 256, ctypes.byref(sz)) == 0
+    assert lib.csk_solve_rgrk_workspace_size(20000, 1000, ctypes.byref(sz)) == 0
+    assert sz.value >= 20000 * 8
+    assert lib.csk_solve_rk_workspace_size(20000, 1000, ctypes.byref(sz)) == 0
+    assert sz.value >= 20000 * 16
 
 
 def test_binding_fails_loudly_without_library(tmp_path):

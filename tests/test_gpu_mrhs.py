@@ -28,8 +28,7 @@ def test_mrhs_matches_oracle(gpu, orc, lp, m, n, nrhs, d):
     X, res = gpu.csk_solve_mrhs(sk.At_lp, sk.At64, sk.bt, sk.nu2, Xref=s.X_star, tol=1e-8, maxit=200000)
     Xs = s.X_star.cpu().numpy()
     Xg = X.cpu().numpy()
-    At = sk.At64.cpu().numpy()
-    Bt = sk.bt.cpu().numpy()
+    At, Bt = orc.sketch_dense(s.A.cpu().numpy(), s.B.cpu().numpy(), d, 5)
     for j in range(nrhs):
         it, st, fb, meas, nref = res[j]
         assert st == gpu.CSK_OK, (j, st)
@@ -49,8 +48,7 @@ def test_mrhs_first_iterates_match_oracle(gpu, orc):
     # step of every column is the oracle's first step
     s, sk = setup(8000, 40, 20, 700, seed=3, sketch_seed=4)
     X, res = gpu.csk_solve_mrhs(sk.At_lp, sk.At64, sk.bt, sk.nu2, Xref=s.X_star, tol=0.0, maxit=1)
-    At = sk.At64.cpu().numpy()
-    Bt = sk.bt.cpu().numpy()
+    At, Bt = orc.sketch_dense(s.A.cpu().numpy(), s.B.cpu().numpy(), 700, 4)
     for j in range(20):
         assert res[j][1] == gpu.CSK_NOT_CONVERGED and res[j][0] == 1
         o = orc.mwrk(At, Bt[:, j], xref=s.X_star[:, j].cpu().numpy(), tol=0.0, maxit=1)

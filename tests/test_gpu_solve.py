@@ -54,7 +54,8 @@ def test_iterates_match_oracle_step_by_step(gpu, orc, path, K):
     kw = dict(single_wg=1) if path == "single" else dict(single_wg=0, grid=16)
     r = gpu.csk_solve(sk.At64, sk.bt, nu2=sk.nu2, x_ref=s.x_star, tol=0.0, maxit=K, **kw)
     assert r.status == gpu.CSK_NOT_CONVERGED and r.iters == K
-    o = orc.mwrk(sk.At64.cpu().numpy(), sk.bt.cpu().numpy(), xref=s.x_star.cpu().numpy(), tol=0.0, maxit=K)
+    At, bt = orc.sketch_dense(s.A.cpu().numpy(), s.b.cpu().numpy(), 1100, 22)
+    o = orc.mwrk(At, bt, xref=s.x_star.cpu().numpy(), tol=0.0, maxit=K)
     assert np.linalg.norm(r.x.cpu().numpy() - o.x) <= 1e-12 * np.linalg.norm(o.x)
 
 
@@ -65,7 +66,8 @@ def test_full_size_dense_coherent(gpu, orc):
     s = W.uniform01(c["m"], c["n"], c["seed"], device=DEV)
     sk = sketched(gpu, s, c["d"], c["sketch_seed"])
     r3 = gpu.csk_solve(sk.At64, sk.bt, nu2=sk.nu2, x_ref=s.x_star, tol=0.0, maxit=3)
-    o3 = orc.mwrk(sk.At64.cpu().numpy(), sk.bt.cpu().numpy(), xref=s.x_star.cpu().numpy(), tol=0.0, maxit=3)
+    At, bt = orc.sketch_dense(s.A.cpu().numpy(), s.b.cpu().numpy(), c["d"], c["sketch_seed"])
+    o3 = orc.mwrk(At, bt, xref=s.x_star.cpu().numpy(), tol=0.0, maxit=3)
     assert np.linalg.norm(r3.x.cpu().numpy() - o3.x) <= 1e-12 * np.linalg.norm(o3.x)
     r = gpu.csk_solve(sk.At64, sk.bt, nu2=sk.nu2, x_ref=s.x_star, tol=c["tol"], maxit=c["maxit"])
     assert r.status == gpu.CSK_OK, r.status_name

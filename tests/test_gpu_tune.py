@@ -23,7 +23,8 @@ def test_tune_then_solve(gpu, orc):
     assert r.status == gpu.CSK_OK
     xs = s.x_star.cpu().numpy()
     assert np.linalg.norm(r.x.cpu().numpy() - xs) <= 1e-10 * np.linalg.norm(xs)
-    o = orc.mwrk(sk.At64.cpu().numpy(), sk.bt.cpu().numpy(), xref=xs, tol=1e-10, maxit=200000)
+    At, bt = orc.sketch_dense(s.A.cpu().numpy(), s.b.cpu().numpy(), 6000, 32)
+    o = orc.mwrk(At, bt, xref=xs, tol=1e-10, maxit=200000)
     assert o.status == 0
     assert np.linalg.norm(r.x.cpu().numpy() - o.x) <= 2e-10 * np.linalg.norm(xs)
     gpu.csk_tune_clear()
