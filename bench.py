@@ -343,6 +343,49 @@ def table1_workload(P, W, torch, trials=5):
     return dict(trials=trials, rows=rows)
 
 
+def figure_workload(P, W, torch, trials=3):
+    """Section 3's figure on this GPU: randomized Kaczmarz, greedy randomized
+    Kaczmarz (the relaxed rule at theta = 1/2) and MWRK on the full (A, b),
+    and CSK (sketch with d = n^2, then MWRK on the sketch), A 200000 x 200,
+    to RES <= 1e-6; mean iterations and times over seeded draws."""
+    c = W.config("figure")
+    dev = "cuda:0"
+    names = ("rk", "grk", "mwrk", "csk")
+    its = {k: [] for k in names}
+    secs = {k: [] for k in names}
+    for t in range(trials):
+        s = W.gaussian(c["m"], c["n"], c["seed"] + t, device=dev)
+        torch.cuda.synchronize()
+        kw = dict(x_ref=s.x_star, tol=c["tol"], maxit=c["maxit"], sync=False)
+        runs = {
+            "rk": lambda: P.csk_solve_rk(s.A, s.b, sel_seed=c["sel_seed"] + t, **kw),
+            "grk": lambda: P.csk_solve_rgrk(s.A, s.b, theta=0.5, sel_seed=c["sel_seed"] + t, **kw),
+            "mwrk": lambda: P.csk_solve(s.A, s.b, **kw),
+            "csk": lambda: (lambda sk: P.csk_solve(sk.At64, sk.bt, nu2=sk.nu2, **kw))(
+                P.csk_sketch(s.A, s.b, c["d"], c["sketch_seed"] + t)),
+        }
+        for k in names:
+            if t == 0:
+                runs[k]()
+            sec, (_, raw) = timed(runs[k])
+            it, st = P.parse_results(raw)[0][:2]
+            if st != P.CSK_OK:
+                raise SystemExit(f"figure trial {t}: {k} {P.csk_status_string(st)}")
+            its[k].append(it)
+            secs[k].append(sec)
+        del s
+    mean = lambda v: sum(v) / len(v)
+    out = dict(trials=trials, m=c["m"], n=c["n"], d=c["d"], res=c["tol"] ** 2)
+    for k in names:
+        out[k] = dict(iters=mean(its[k]), ms=mean(secs[k]) * 1e3, us_per_iter=mean(secs[k]) / mean(its[k]) * 1e6)
+    grk_bytes = c["m"] * c["n"] * 8 + 16 * c["m"]
+    out["grk"]["alg_TBps"] = grk_bytes / (out["grk"]["us_per_iter"] * 1e-6) / 1e12
+    log("[bench] figure 200000x200: " + ", ".join(
+        f"{k.upper()} {out[k]['iters']:.0f} it {out[k]['ms']:.2f} ms" for k in names))
+    torch.cuda.empty_cache()
+    return out
+
+
 def csr_workload(P, W, torch, solve=True):
     """CSR A 1e6 x 5000 at 0.1%, d = 50000: the sketch kept sparse and the FP64
     loop on it, beside the dense sketch and its mixed FP32 solve, to 1e-8."""
@@ -435,6 +478,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--quick", action="store_true", help="main workload only (for profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--extra", default="all",
+                    help="comma-separated extra workloads after the main one (default all; see EXTRAS)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration for profiling)")
     args = ap.parse_args()
@@ -460,12 +505,20 @@ def main():
             log(f"[bench] cpu_baseline ~{cpu['value']:.1f} s ({cpu['sample']})")
         del s
         torch.cuda.empty_cache()
-        extra["row_scaled_mixed"] = mixed_workload(P, W, torch)
-        extra["sparse_csr"] = csr_workload(P, W, torch)
-        extra["batched_512"] = batched_workload(P, W, torch)
-        extra["multi_rhs_256"] = mrhs_workload(P, W, torch)
-        extra["table1"] = table1_workload(P, W, torch)
-        extra["memory_rates"] = memory_rates(torch)
+        extras = {
+            "row_scaled_mixed": lambda: mixed_workload(P, W, torch),
+            "sparse_csr": lambda: csr_workload(P, W, torch),
+            "batched_512": lambda: batched_workload(P, W, torch),
+            "multi_rhs_256": lambda: mrhs_workload(P, W, torch),
+            "table1": lambda: table1_workload(P, W, torch),
+            "figure_selection_rules": lambda: figure_workload(P, W, torch),
+            "memory_rates": lambda: memory_rates(torch),
+        }
+        want = list(extras) if args.extra == "all" else [e for e in args.extra.split(",") if e]
+        for name in want:
+            if name not in extras:
+                raise SystemExit(f"unknown extra workload {name!r}; choose from {', '.join(extras)}")
+            extra[name] = extras[name]()
 
     traffic, note = measured_traffic()
     log(f"[bench] k_solve_grid measured traffic per launch: {traffic} ({note})")

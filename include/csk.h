@@ -254,8 +254,10 @@ csk_status csk_solve(const void* At, csk_dtype at_dtype, int64_t ldat,
  *   per workgroup: CSK_ERR_UNSUPPORTED, ask for a larger grid).
  * csk_solve_rk: randomized Kaczmarz (Strohmer & Vershynin): row i with
  *   probability ||At^(i)||^2 / ||At||_F^2 each iteration, i_k the smallest i
- *   with C_i > u_k C_{d-1}, C the cumulative sums of nu2 in index order and
- *   u_k the k-th uniform.  Only the drawn row's residual is formed, so the
+ *   with C_i > u_k C_{d-1}, C the cumulative sums of nu2 and u_k the k-th
+ *   uniform (C is summed in 512 segments, so it can differ from one running
+ *   sum in index order in the last bits; a row of zero norm is never
+ *   drawn).  Only the drawn row's residual is formed, so the
  *   stop mode must be CSK_STOP_REL_ERR (else CSK_ERR_INVALID_ARG).  One
  *   workgroup; requires 1 <= n <= 8192, d < 2^31.                           */
 csk_status csk_solve_rgrk_workspace_size(int64_t d, int64_t n, size_t* bytes /*host*/);

@@ -6,17 +6,21 @@
 //
 // One workgroup runs the whole loop (one row per iteration leaves nothing to
 // spread over the chip; the cost is latency):
-//   * setup: the cumulative squared norms C_i, summed in index order by one
-//     thread over blocks staged in LDS, stored to the workspace;
+//   * setup: the cumulative squared norms C_i into the workspace, each
+//     thread summing its own contiguous segment of rows, thread 0 the
+//     segment totals, then each thread its segment from its offset (the
+//     rounding differs from one running sum in index order only by where the
+//     partial sums meet);
 //   * the draws do not depend on x, so the rows of 512 iterations are found
 //     at once, one binary search per thread for the smallest i with
 //     C_i > u_k C_{d-1} (u_k the k-th uniform of the selection stream), and
 //     kept in LDS a batch ahead;
-//   * each thread owns columns tid + 512 j of x, x_ref and the current row
-//     (registers; the next row is loaded an iteration ahead), so an
-//     iteration is one workgroup reduction (the row's dot product with x_k
-//     and ||x_k - x_ref||^2), the stop test on x_k, and the update of the
-//     thread's own columns.
+//   * each thread owns columns tid + 512 j of x, x_ref and the rows
+//     (registers), so an iteration is one workgroup reduction (the row's dot
+//     product with x_k and ||x_k - x_ref||^2), the stop test on x_k, and the
+//     update of the thread's own columns.  Rows are loaded up to four
+//     iterations ahead (a ring of registers), which hides the latency of a
+//     row read from HBM behind the iterations before it.
 #include "csk_grid.h"
 #include "csk_solve.h"
 
@@ -29,7 +33,9 @@ namespace {
 constexpr int kRkNT = 512;
 constexpr int kRkNW = kRkNT / kWave;
 constexpr int kRkBatch = kRkNT;     // iterations whose rows are drawn together
-constexpr int kRkStage = 4096;      // squared norms staged per block of the prefix sum
+// Iterations between a row's load and its use: 4, fewer where the ring
+// would not fit the registers (columns per thread J of 8 and 16).
+template <int J> constexpr int rk_ahead() { return J >= 16 ? 1 : J >= 8 ? 2 : 4; }
 
 struct RkArgs {
     const double* At;
@@ -49,9 +55,13 @@ struct RkArgs {
     int32_t check_every;
 };
 
-// Smallest i with cum[i] > t; cum is non-decreasing and cum[d-1] > t when the
-// distribution is valid (otherwise the result is d - 1, never used).
-__device__ __forceinline__ int rk_search(const double* __restrict__ cum, int d, double t)
+// Smallest i with cum[i] > t (cum[d-1] > t when the distribution is valid;
+// otherwise the result is d - 1, never used).  Where two segments of the
+// prefix sum meet, cum may step back by a few units in the last place; a
+// draw landing in such a sliver could reach a row of zero norm, which is
+// then replaced by the nearest row of nonzero norm before it (or after it).
+__device__ __forceinline__ int rk_search(const double* __restrict__ cum, const double* __restrict__ nu2, int d,
+                                         double t)
 {
     int lo = 0, hi = d - 1;
     while (lo < hi) {
@@ -59,13 +69,20 @@ __device__ __forceinline__ int rk_search(const double* __restrict__ cum, int d, 
         if (cum[mid] > t) hi = mid;
         else lo = mid + 1;
     }
+    if (!(nu2[lo] > 0.0)) {
+        int i = lo;
+        while (i > 0 && !(nu2[i] > 0.0)) --i;
+        if (!(nu2[i] > 0.0))
+            for (i = lo; i + 1 < d && !(nu2[i] > 0.0);) ++i;
+        lo = i;
+    }
     return lo;
 }
 
 template <int J>
 __global__ __launch_bounds__(kRkNT) void k_solve_rk(RkArgs P)
 {
-    __shared__ double stage[kRkStage];
+    __shared__ double seg[kRkNT];
     __shared__ int32_t pick[2][kRkBatch];
     __shared__ double red[2][kRkNW][2];
     __shared__ int32_t s_cancel[2];
@@ -75,35 +92,61 @@ __global__ __launch_bounds__(kRkNT) void k_solve_rk(RkArgs P)
     const int lane = tid & (kWave - 1);
     const int d = P.d, n = P.n;
 
-    // C_i in index order: the block is staged by every thread, summed by one
-    double acc = 0.0;
-    for (int base = 0; base < d; base += kRkStage) {
-        const int cnt = min(kRkStage, d - base);
-        for (int i = tid; i < cnt; i += kRkNT) stage[i] = P.nu2[base + i];
-        __syncthreads();
-        if (tid == 0) {
-            for (int i = 0; i < cnt; ++i) {
-                acc = acc + stage[i];
-                stage[i] = acc;
-            }
-        }
-        __syncthreads();
-        for (int i = tid; i < cnt; i += kRkNT) P.cum[base + i] = stage[i];
-        __syncthreads();
+    // C_i: segment sums, their exclusive prefix (thread 0, in order), then
+    // the running sum of each segment from its offset
+    const int span = (d + kRkNT - 1) / kRkNT;
+    const int i0 = min(d, tid * span), i1 = min(d, i0 + span);
+    // 16 loads in flight per thread (one cache line), the adds in order
+    double part = 0.0;
+    int i = i0;
+    for (; i + 16 <= i1; i += 16) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = P.nu2[i + u];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) part += v[u];
     }
-    if (tid == 0) s_total = acc;
+    for (; i < i1; ++i) part += P.nu2[i];
+    seg[tid] = part;
+    __syncthreads();
+    if (tid == 0) {
+        double run = 0.0;
+        for (int t = 0; t < kRkNT; ++t) {
+            const double v = seg[t];
+            seg[t] = run;
+            run += v;
+        }
+        s_total = run;
+    }
+    __syncthreads();
+    double acc = seg[tid];
+    for (i = i0; i + 16 <= i1; i += 16) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = P.nu2[i + u];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            acc += v[u];
+            P.cum[i + u] = acc;
+        }
+    }
+    for (; i < i1; ++i) {
+        acc += P.nu2[i];
+        P.cum[i] = acc;
+    }
+    if (i1 == d && i0 < i1) s_total = acc;  // the last element's running sum, as the search sees it
     __syncthreads();
     const double total = s_total;
     const bool valid = isfinite(total) && total > 0.0;
 
     auto draw_batch = [&](int64_t b) {
         const int64_t k = b * kRkBatch + tid;
-        pick[b & 1][tid] = valid ? rk_search(P.cum, d, select_uniform(P.seed, static_cast<uint64_t>(k)) * total) : 0;
+        pick[b & 1][tid] = valid ? rk_search(P.cum, P.nu2, d, select_uniform(P.seed, static_cast<uint64_t>(k)) * total) : 0;
     };
     draw_batch(0);
     draw_batch(1);
 
-    double x[J], xr[J], a[J];
+    double x[J], xr[J];
     for (int j = 0; j < J; ++j) {
         const int c = tid + j * kRkNT;
         x[j] = (c < n && P.x0) ? P.x0[c] : 0.0;
@@ -126,58 +169,66 @@ __global__ __launch_bounds__(kRkNT) void k_solve_rk(RkArgs P)
         bi = P.bt[i];
         ni = P.nu2[i];
     };
-    double bi, ni;
-    load_row(pick[0][0], a, bi, ni);
+    // ring slot u holds the row of every iteration k with k % AH == u
+    constexpr int AH = rk_ahead<J>();
+    double ring[AH][J], rb[AH], rn[AH];
+#pragma unroll
+    for (int u = 0; u < AH; ++u) {
+        if (u <= P.maxit) load_row(pick[0][u], ring[u], rb[u], rn[u]);
+        else {
+            for (int j = 0; j < J; ++j) ring[u][j] = 0.0;
+            rb[u] = rn[u] = 0.0;
+        }
+    }
 
     int32_t status = CSK_NOT_CONVERGED;
     double meas = NAN;
     int64_t k = 0;
-    for (;; ++k) {
-        const int par = static_cast<int>(k & 1);
-        // draw the batch after next once this batch starts
-        if (k >= kRkBatch && (k % kRkBatch) == 0) draw_batch(k / kRkBatch + 1);
-        double pd = 0.0, pe = 0.0;
-        for (int j = 0; j < J; ++j) {
-            pd += a[j] * x[j];
-            const double e = x[j] - xr[j];
-            pe += e * e;
+    bool done = false;
+    while (!done) {
+#pragma unroll
+        for (int u = 0; u < AH; ++u) {
+            const int par = static_cast<int>(k & 1);
+            // draw the batch after next once this batch starts
+            if (k >= kRkBatch && (k % kRkBatch) == 0) draw_batch(k / kRkBatch + 1);
+            double a[J];
+            for (int j = 0; j < J; ++j) a[j] = ring[u][j];
+            const double bi = rb[u], ni = rn[u];
+            // the row of iteration k + AH into the freed slot
+            const int64_t kn = k + AH;
+            if (kn <= P.maxit) load_row(pick[(kn / kRkBatch) & 1][kn % kRkBatch], ring[u], rb[u], rn[u]);
+            double pd = 0.0, pe = 0.0;
+            for (int j = 0; j < J; ++j) {
+                pd += a[j] * x[j];
+                const double e = x[j] - xr[j];
+                pe += e * e;
+            }
+            pd = group_sum_t<double, kWave>(pd);
+            pe = group_sum_t<double, kWave>(pe);
+            if (lane == 0) {
+                red[par][wave][0] = pd;
+                red[par][wave][1] = pe;
+            }
+            if (tid == 0) s_cancel[par] = (P.cancel && (k % P.check_every) == 0 && *P.cancel != 0) ? 1 : 0;
+            __syncthreads();
+            double dot = 0.0, e2 = 0.0;
+            for (int w = 0; w < kRkNW; ++w) {
+                dot += red[par][w][0];
+                e2 += red[par][w][1];
+            }
+            // stop test on x_k
+            meas = xref2 > 0.0 ? e2 / xref2 : e2;
+            if (xref2 > 0.0 ? (e2 / xref2 <= P.tol2) : (e2 <= P.tol2)) { status = CSK_OK; done = true; break; }
+            if (k == P.maxit) { status = CSK_NOT_CONVERGED; done = true; break; }
+            if (s_cancel[par]) { status = CSK_CANCELLED; done = true; break; }
+            if (!isfinite(total)) { status = CSK_ERR_NONFINITE; done = true; break; }
+            if (!(total > 0.0)) { status = CSK_ERR_DEGENERATE; done = true; break; }
+            const double r = bi - dot;
+            if (!isfinite(r)) { status = CSK_ERR_NONFINITE; done = true; break; }
+            const double alpha = r / ni;
+            for (int j = 0; j < J; ++j) x[j] = x[j] + alpha * a[j];
+            ++k;
         }
-        // the next row, an iteration ahead
-        double an[J], bn = 0.0, nn = 0.0;
-        const int64_t k1 = k + 1;
-        const int nxt = pick[(k1 / kRkBatch) & 1][k1 % kRkBatch];
-        if (k < P.maxit) load_row(nxt, an, bn, nn);
-        else
-            for (int j = 0; j < J; ++j) an[j] = 0.0;
-        pd = group_sum_t<double, kWave>(pd);
-        pe = group_sum_t<double, kWave>(pe);
-        if (lane == 0) {
-            red[par][wave][0] = pd;
-            red[par][wave][1] = pe;
-        }
-        if (tid == 0) s_cancel[par] = (P.cancel && (k % P.check_every) == 0 && *P.cancel != 0) ? 1 : 0;
-        __syncthreads();
-        double dot = 0.0, e2 = 0.0;
-        for (int w = 0; w < kRkNW; ++w) {
-            dot += red[par][w][0];
-            e2 += red[par][w][1];
-        }
-        // stop test on x_k
-        meas = xref2 > 0.0 ? e2 / xref2 : e2;
-        if (xref2 > 0.0 ? (e2 / xref2 <= P.tol2) : (e2 <= P.tol2)) { status = CSK_OK; break; }
-        if (k == P.maxit) { status = CSK_NOT_CONVERGED; break; }
-        if (s_cancel[par]) { status = CSK_CANCELLED; break; }
-        if (!isfinite(total)) { status = CSK_ERR_NONFINITE; break; }
-        if (!(total > 0.0)) { status = CSK_ERR_DEGENERATE; break; }
-        const double r = bi - dot;
-        if (!isfinite(r)) { status = CSK_ERR_NONFINITE; break; }
-        const double alpha = r / ni;
-        for (int j = 0; j < J; ++j) {
-            x[j] = x[j] + alpha * a[j];
-            a[j] = an[j];
-        }
-        bi = bn;
-        ni = nn;
     }
     for (int j = 0; j < J; ++j) {
         const int c = tid + j * kRkNT;

@@ -18,6 +18,9 @@ below follow that recipe with the distributions named for each workload:
   multi_rhs      A 200000 x 500 FP32 N(0,1), 256 right-hand sides,
                  d = 10000                                          (seed 6, sketch 106)
   table1         A m x n N(0,1) FP64, d = n^2 (Section 3, Table 1)  (seed 10000+t, sketch 20000+t)
+  figure         A 200000 x 200 N(0,1) FP64, d = n^2 = 40000 (Section 3's figure:
+                 RK, GRK and MWRK on A, CSK on the sketch)          (seed 11000+t, sketch 21000+t,
+                                                                     selection 31000+t)
 
 b is always formed in FP64 from the exact (already rounded) entries of A, so
 the system stays consistent to FP64 rounding even when A is stored in FP32.
@@ -45,6 +48,10 @@ CONFIGS = {
     # error) or 20000 iterations; trial t uses seeds seed + t, sketch_seed + t
     "table1": dict(ms=(300000, 400000, 500000, 600000, 700000), ns=(50, 100, 150), seed=10000,
                    sketch_seed=20000, tol=1e-3, maxit=20000),
+    # Section 3's figure: the four methods on A 200000 x 200 with the same
+    # stopping rule as Table 1
+    "figure": dict(m=200000, n=200, d=40000, seed=11000, sketch_seed=21000, sel_seed=31000, tol=1e-3,
+                   maxit=200000),
 }
 
 
