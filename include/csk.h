@@ -362,6 +362,35 @@ csk_status csk_solve_mrhs(const void* At_lp, csk_dtype lp_dtype, int64_t ldat_lp
                           const csk_solve_opts* opts /*host*/, csk_solve_result* res,
                           void* ws, size_t ws_bytes, void* stream);
 
+/* ---- Algorithm 1 as one HIP graph ---------------------------------------- *
+ * csk_pipeline_capture records csk_sketch (A, b -> At64 [, At_lp], bt, nu2;
+ * Algorithm 1, Initialize) followed by csk_solve (the loop; mixed precision
+ * when At_lp is given, on lp_dtype) on `stream` into a HIP graph, without
+ * running them, and instantiates it.  csk_pipeline_launch replays the whole
+ * pipeline on a stream: one launch instead of the chain of dependent kernel
+ * launches, with every pointer, size and option fixed at capture (update the
+ * contents of A, b, x0 and opts->x_ref between launches, never their
+ * addresses).  Arguments mean what they mean for csk_sketch (b a vector,
+ * nrhs 1) and csk_solve; the two workspaces are those calls' own and must
+ * stay allocated, like every other buffer, until the last launch has
+ * finished.  `stream` must be a created stream (not the null stream) with
+ * no capture in progress; a failure of either call ends the capture and is
+ * returned (nothing is recorded or run).  csk_pipeline_destroy releases the
+ * graph (NULL is accepted).  Launches of one pipeline that overlap in time
+ * race on its buffers.                                                      */
+typedef struct csk_pipeline_s* csk_pipeline;
+csk_status csk_pipeline_capture(const void* A, csk_dtype a_dtype, int64_t m, int64_t n, int64_t lda,
+                                const double* b, int64_t d, uint64_t seed,
+                                double* At64, int64_t ldat64,
+                                void* At_lp, csk_dtype lp_dtype, int64_t ldat_lp,
+                                double* bt, double* nu2, const double* x0, double* x,
+                                const csk_solve_opts* opts /*host*/, csk_solve_result* res,
+                                void* ws_sketch, size_t ws_sketch_bytes,
+                                void* ws_solve, size_t ws_solve_bytes,
+                                void* stream, csk_pipeline* out /*host*/);
+csk_status csk_pipeline_launch(csk_pipeline p, void* stream);
+csk_status csk_pipeline_destroy(csk_pipeline p);
+
 #ifdef __cplusplus
 }
 #endif

@@ -39,6 +39,7 @@ EXPORTED = [
     "csk_solve_csr_workspace_size", "csk_solve_csr",
     "csk_solve_rgrk_workspace_size", "csk_solve_rgrk",
     "csk_solve_rk_workspace_size", "csk_solve_rk",
+    "csk_pipeline_capture", "csk_pipeline_launch", "csk_pipeline_destroy",
     "csk_solve_batched_workspace_size", "csk_solve_batched",
     "csk_solve_mrhs_workspace_size", "csk_solve_mrhs",
     "csk_tune_solve_workspace_size", "csk_tune_solve", "csk_tune_lookup", "csk_tune_clear",
@@ -138,6 +139,14 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.csk_solve_rk.restype = I32
     lib.csk_solve_rk.argtypes = [P, I64, I64, I64, P, P, P, P, U64,
                                  ctypes.POINTER(SolveOpts), P, P, SZ, P]
+    lib.csk_pipeline_capture.restype = I32
+    lib.csk_pipeline_capture.argtypes = [P, I32, I64, I64, I64, P, I64, U64, P, I64, P, I32, I64, P, P, P, P,
+                                         ctypes.POINTER(SolveOpts), P, P, SZ, P, SZ, P,
+                                         ctypes.POINTER(ctypes.c_void_p)]
+    lib.csk_pipeline_launch.restype = I32
+    lib.csk_pipeline_launch.argtypes = [P, P]
+    lib.csk_pipeline_destroy.restype = I32
+    lib.csk_pipeline_destroy.argtypes = [P]
     lib.csk_solve_workspace_size.restype = I32
     lib.csk_solve_workspace_size.argtypes = [I64, I64, I32, PSZ]
     lib.csk_solve.restype = I32

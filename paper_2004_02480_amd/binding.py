@@ -417,6 +417,82 @@ def csk_solve_rk(At: torch.Tensor, bt: torch.Tensor, *, x_ref: torch.Tensor, sel
                               CSK_STOP_REL_ERR, cancel, check_every, 0, -1, out, result, workspace, sync, stream)
 
 
+class Pipeline:
+    """Algorithm 1 (sketch, then the loop) captured once into a HIP graph by
+    csk_pipeline_capture; launch() replays it.  Holds every buffer the graph
+    reads or writes: refill A, b, x0 and x_ref in place between launches."""
+
+    def __init__(self, handle, keep, x, result, sketch):
+        self._h = handle
+        self._keep = keep
+        self.x = x
+        self.result = result
+        self.sketch = sketch
+
+    def launch(self, stream=None):
+        if self._h is None:
+            raise CskError(CSK_ERR_INVALID_ARG, "pipeline destroyed")
+        _check(_lib.csk_pipeline_launch(self._h, _stream(stream)), "csk_pipeline_launch")
+
+    def results(self) -> "SolveResult":
+        torch.cuda.synchronize()
+        it, st, fb, meas, nref = parse_results(self.result)[0]
+        return SolveResult(self.x, it, st, fb, meas, nref)
+
+    def close(self):
+        if self._h is not None:
+            _check(_lib.csk_pipeline_destroy(self._h), "csk_pipeline_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def csk_pipeline_capture(A: torch.Tensor, b: torch.Tensor, d: int, seed: int, *,
+                         lp_dtype: Optional[torch.dtype] = None, x0: Optional[torch.Tensor] = None,
+                         x_ref: Optional[torch.Tensor] = None, tol: float = 1e-10, maxit: int = 100000,
+                         stop_mode: Optional[int] = None, refresh_every: int = 64, grid: int = 0,
+                         single_wg: int = -1, capture_stream=None) -> Pipeline:
+    """Capture csk_sketch then csk_solve (mixed precision when lp_dtype is
+    given) into one HIP graph through the C ABI; returns a Pipeline."""
+    _need_cuda(A, "A")
+    _need_cuda(b, "b")
+    if A.dtype not in (torch.float64, torch.float32) or b.dtype != torch.float64 or b.dim() != 1:
+        raise ValueError("A float64/float32 (m x n), b float64 (m) expected")
+    lda = _rowmajor(A, "A")
+    m, n = A.shape
+    dev = A.device
+    At64 = _padded_rows(d, n, torch.float64, dev)
+    At_lp = _padded_rows(d, n, lp_dtype, dev) if lp_dtype is not None else None
+    bt = torch.empty(d, dtype=torch.float64, device=dev)
+    nu2 = torch.empty(d, dtype=torch.float64, device=dev)
+    x = torch.empty(n, dtype=torch.float64, device=dev)
+    res = torch.zeros(_abi.RESULT_BYTES, dtype=torch.uint8, device=dev)
+    a_code = _TORCH_TO_CSK[A.dtype]
+    lp_code = _TORCH_TO_CSK[lp_dtype] if lp_dtype is not None else CSK_F64
+    nb = ctypes.c_size_t(0)
+    _check(_lib.csk_sketch_workspace_size(m, n, d, a_code, ctypes.byref(nb)), "csk_sketch_workspace_size")
+    ws_sk = _workspace(nb.value, dev)
+    _check(_lib.csk_solve_workspace_size(d, n, lp_code, ctypes.byref(nb)), "csk_solve_workspace_size")
+    ws_so = _workspace(nb.value, dev)
+    if stop_mode is None:
+        stop_mode = CSK_STOP_REL_ERR if x_ref is not None else CSK_STOP_REL_RESID
+    o = _opts(tol, maxit, stop_mode, refresh_every, x_ref, None, 256, grid, single_wg)
+    cs = capture_stream if capture_stream is not None else torch.cuda.Stream(device=dev)
+    cs.wait_stream(torch.cuda.current_stream(dev))
+    h = ctypes.c_void_p()
+    _check(_lib.csk_pipeline_capture(_ptr(A), a_code, m, n, lda, _ptr(b), d, int(seed) & (2**64 - 1), _ptr(At64),
+                                     At64.stride(0), _ptr(At_lp), lp_code, _ld(At_lp, n), _ptr(bt), _ptr(nu2),
+                                     _ptr(x0), _ptr(x), ctypes.byref(o), _ptr(res), _ptr(ws_sk), ws_sk.numel(),
+                                     _ptr(ws_so), ws_so.numel(), ctypes.c_void_p(cs.cuda_stream), ctypes.byref(h)),
+           "csk_pipeline_capture")
+    keep = (A, b, x0, x_ref, ws_sk, ws_so, cs)
+    return Pipeline(h, keep, x, res, SketchOut(At64, At_lp, bt, nu2, None, None))
+
+
 def csk_solve_batched(systems: Sequence[dict], *, lp_dtype: torch.dtype = torch.float32, tol: float = 1e-8,
                       maxit: int = 200000, refresh_every: int = 64, sync: bool = True, stream=None):
     """Sketch and solve many independent systems in one pass.

@@ -454,6 +454,71 @@ csk_status csk_solve(const void* At, csk_dtype at_dtype, int64_t ldat, const dou
     return solve_run(S, at_dtype, opts, ws, ws_bytes, as_stream(stream));
 }
 
+// ---- Algorithm 1 as one HIP graph -------------------------------------------
+
+struct csk_pipeline_s {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+csk_status csk_pipeline_capture(const void* A, csk_dtype a_dtype, int64_t m, int64_t n, int64_t lda, const double* b,
+                                int64_t d, uint64_t seed, double* At64, int64_t ldat64, void* At_lp,
+                                csk_dtype lp_dtype, int64_t ldat_lp, double* bt, double* nu2, const double* x0,
+                                double* x, const csk_solve_opts* opts, csk_solve_result* res, void* ws_sketch,
+                                size_t ws_sketch_bytes, void* ws_solve, size_t ws_solve_bytes, void* stream,
+                                csk_pipeline* out)
+{
+    g_err[0] = 0;
+    if (!out) { set_error("out is NULL"); return CSK_ERR_INVALID_ARG; }
+    *out = nullptr;
+    if (!stream) { set_error("capture needs a created stream, not the null stream"); return CSK_ERR_INVALID_ARG; }
+    if (!b || !bt || !nu2 || !At64) { set_error("b, bt, nu2 and At64 are required"); return CSK_ERR_INVALID_ARG; }
+    csk_status st = check_opts(opts);
+    if (st != CSK_OK) return st;
+    hipStream_t hs = as_stream(stream);
+    CSK_HIP(hipStreamBeginCapture(hs, hipStreamCaptureModeThreadLocal));
+    st = csk_sketch(A, a_dtype, m, n, lda, b, 1, 1, d, seed, At64, ldat64, At_lp, At_lp ? lp_dtype : CSK_F64,
+                    ldat_lp, bt, 1, nu2, nullptr, nullptr, ws_sketch, ws_sketch_bytes, stream);
+    if (st == CSK_OK)
+        st = csk_solve(At_lp ? At_lp : At64, At_lp ? lp_dtype : CSK_F64, At_lp ? ldat_lp : ldat64, At64, ldat64, d, n,
+                       bt, nu2, x0, x, opts, res, ws_solve, ws_solve_bytes, stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t he = hipStreamEndCapture(hs, &graph);
+    if (st != CSK_OK || he != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        if (st != CSK_OK) return st;  // the failing call's message stays
+        return hip_fail(he, "hipStreamEndCapture");
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return hip_fail(ie, "hipGraphInstantiate");
+    }
+    *out = new csk_pipeline_s{graph, exec};
+    return CSK_OK;
+}
+
+csk_status csk_pipeline_launch(csk_pipeline p, void* stream)
+{
+    g_err[0] = 0;
+    if (!p) { set_error("pipeline is NULL"); return CSK_ERR_INVALID_ARG; }
+    CSK_HIP(hipGraphLaunch(p->exec, as_stream(stream)));
+    return CSK_OK;
+}
+
+csk_status csk_pipeline_destroy(csk_pipeline p)
+{
+    g_err[0] = 0;
+    if (!p) return CSK_OK;
+    const hipError_t e1 = hipGraphExecDestroy(p->exec);
+    const hipError_t e2 = hipGraphDestroy(p->graph);
+    delete p;
+    if (e1 != hipSuccess) return hip_fail(e1, "hipGraphExecDestroy");
+    if (e2 != hipSuccess) return hip_fail(e2, "hipGraphDestroy");
+    return CSK_OK;
+}
+
 // ---- randomized selection rules ----------------------------------------------
 
 namespace {
@@ -637,20 +702,24 @@ csk_status csk_tune_solve(const void* At, csk_dtype at_dtype, int64_t ldat, cons
             // one untimed run (first launch of the shape), then one timed
             r = solve_run(S, at_dtype, &o, sws, solve_ws_bytes(d, n, 65536), stm, &plan);
             if (r != CSK_OK) break;
-            hipEventRecord(e0, stm);
+            if (hipEventRecord(e0, stm) != hipSuccess) { set_error("hipEventRecord failed"); r = CSK_ERR_DEVICE; break; }
             r = solve_run(S, at_dtype, &o, sws, solve_ws_bytes(d, n, 65536), stm, &plan);
-            hipEventRecord(e1, stm);
             if (r != CSK_OK) break;
+            if (hipEventRecord(e1, stm) != hipSuccess) { set_error("hipEventRecord failed"); r = CSK_ERR_DEVICE; break; }
             if (hipEventSynchronize(e1) != hipSuccess) { set_error("tuning run failed"); r = CSK_ERR_DEVICE; break; }
             float ms = 0.f;
-            hipEventElapsedTime(&ms, e0, e1);
+            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                set_error("hipEventElapsedTime failed");
+                r = CSK_ERR_DEVICE;
+                break;
+            }
             const double us = 1e3 * ms / trial_iters;
             if (pick.grid == 0 || us < pick.us_per_iter) pick = csk_tune_entry{g, l, us};
         }
         if (r != CSK_OK) break;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (r != CSK_OK) return r;
     tune_store(d, n, at_dtype, vw, pick.grid, pick.lanes_per_row, pick.us_per_iter);
     if (best) *best = pick;

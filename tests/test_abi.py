@@ -102,6 +102,16 @@ def test_invalid_arguments_rejected_on_host(lib):
                             16, None) == _abi.CSK_ERR_WORKSPACE
     assert lib.csk_solve_rk(P(256), 3, 8, 4, P(256), None, None, P(256), 1, ctypes.byref(o), P(256), P(256),
                             1 << 20, None) == _abi.CSK_ERR_INVALID_ARG
+    # pipeline capture: no handle pointer, the null stream, missing outputs
+    h = ctypes.c_void_p()
+    cap = lambda stream, out, bt=P(256): lib.csk_pipeline_capture(
+        P(256), _abi.CSK_F64, 10, 4, 4, P(256), 5, 1, P(256), 4, None, _abi.CSK_F64, 4, bt, P(256), None, P(256),
+        ctypes.byref(o), P(256), P(256), 1 << 20, P(256), 1 << 20, stream, out)
+    assert cap(P(512), None) == _abi.CSK_ERR_INVALID_ARG
+    assert cap(None, ctypes.byref(h)) == _abi.CSK_ERR_INVALID_ARG and not h.value
+    assert cap(P(512), ctypes.byref(h), bt=None) == _abi.CSK_ERR_INVALID_ARG and not h.value
+    assert lib.csk_pipeline_launch(None, None) == _abi.CSK_ERR_INVALID_ARG
+    assert lib.csk_pipeline_destroy(None) == _abi.CSK_OK
 
 
 def test_workspace_queries(lib):
