@@ -59,6 +59,23 @@ def test_iterates_match_oracle_step_by_step(gpu, orc, path, K):
     assert np.linalg.norm(r.x.cpu().numpy() - o.x) <= 1e-12 * np.linalg.norm(o.x)
 
 
+@pytest.mark.parametrize("path,m,n,d,grid", [("single", 8000, 60, 1500, 1), ("grid", 60000, 90, 9000, 8),
+                                              ("grid", 40000, 1000, 20000, 16)])
+def test_alternating_walk_iterates_match_oracle(gpu, orc, path, m, n, d, grid):
+    # shapes whose workgroups stream rows past the LDS-resident ones, with one
+    # or two segments per row and lane groups of unequal row counts: the odd
+    # iterations walk those rows backwards
+    s = W.gaussian(m, n, seed=m + n, device=DEV)
+    sk = sketched(gpu, s, d, 5)
+    kw = dict(single_wg=1) if path == "single" else dict(single_wg=0, grid=grid)
+    At, bt = orc.sketch_dense(s.A.cpu().numpy(), s.b.cpu().numpy(), d, 5)
+    for K in (1, 2, 25):
+        r = gpu.csk_solve(sk.At64, sk.bt, nu2=sk.nu2, x_ref=s.x_star, tol=0.0, maxit=K, **kw)
+        assert r.status == gpu.CSK_NOT_CONVERGED and r.iters == K
+        o = orc.mwrk(At, bt, xref=s.x_star.cpu().numpy(), tol=0.0, maxit=K)
+        assert np.linalg.norm(r.x.cpu().numpy() - o.x) <= 1e-12 * np.linalg.norm(o.x), (path, K)
+
+
 def test_full_size_dense_coherent(gpu, orc):
     # the benchmark workload end to end: every output checked against x*
     # (any size) and the first iterates against the oracle
