@@ -71,6 +71,21 @@ def test_batched_residual_mode_without_reference(gpu):
         del A
 
 
+@pytest.mark.parametrize("lp", [torch.float32, torch.bfloat16], ids=["f32", "bf16"])
+def test_batched_deterministic(gpu, lp):
+    # systems from the full recipe's range, some long enough to be split over
+    # several workgroups: two runs give the same bits whatever workgroup
+    # claims which work item
+    shapes, _ = W.batched_shapes(48, base_seed=21, sketch_base=22)
+    systems = make_batch(shapes, torch.float32)
+    xa, ra = gpu.csk_solve_batched(systems, lp_dtype=lp, tol=1e-8)
+    xb, rb = gpu.csk_solve_batched(systems, lp_dtype=lp, tol=1e-8)
+    assert ra == rb
+    for a, b in zip(xa, xb):
+        assert torch.equal(a, b)
+    assert all(r[1] == gpu.CSK_OK for r in ra)
+
+
 def test_batched_shapes_recipe():
     shapes, redraws = W.batched_shapes(512)
     assert len(shapes) == 512

@@ -152,3 +152,14 @@ def test_select_status_paths(gpu):
     assert r.status == gpu.CSK_NOT_CONVERGED and r.iters == 0 and torch.count_nonzero(r.x) == 0
     with pytest.raises(gpu.CskError):
         gpu.csk_solve_rgrk(A, b, theta=2.0, x_ref=xs)
+    # a NaN in the right-hand side reaches a weighted residual; a NaN norm
+    # makes the row distribution undefined
+    bn = b.clone()
+    bn[1] = float("nan")
+    assert gpu.csk_solve_rgrk(A, bn, x_ref=xs, tol=1e-12, maxit=100).status == gpu.CSK_ERR_NONFINITE
+    for single in (0, 1):
+        r = gpu.csk_solve_rgrk(A, bn, x_ref=xs, tol=1e-12, maxit=100, single_wg=single)
+        assert r.status == gpu.CSK_ERR_NONFINITE
+    nun = (A * A).sum(1)
+    nun[2] = float("nan")
+    assert gpu.csk_solve_rk(A, b, nu2=nun, x_ref=xs, tol=1e-12, maxit=100).status == gpu.CSK_ERR_NONFINITE
