@@ -47,6 +47,9 @@ size_t solve_rgrk_ws_bytes(int64_t d, int64_t n, int grid);
 csk_status solve_rgrk_run(const SolveSys& sys, const csk_solve_opts* o, double theta, uint64_t sel_seed,
                           void* ws, size_t ws_bytes, hipStream_t st);
 
+// nu2[i] = ||A^(i)||^2 for the d x n FP64 rows of A (leading dimension lda).
+csk_status launch_row_norms2(const double* A, int64_t lda, int64_t d, int64_t n, double* nu2, hipStream_t st);
+
 // Randomized Kaczmarz (one workgroup; stop mode REL_ERR; n <= 8192).
 size_t solve_rk_ws_bytes(int64_t d);
 csk_status solve_rk_run(const double* At, int64_t ldat, int64_t d, int64_t n, const double* bt, const double* nu2,

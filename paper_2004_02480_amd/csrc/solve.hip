@@ -1187,8 +1187,8 @@ csk_status solve_run(const SolveSys& sys_in, csk_dtype at_dtype, const csk_solve
         return CSK_ERR_WORKSPACE;
     }
     if (S.nu2 == nullptr) {
-        k_row_norms2<<<std::min(4096, (S.d + 3) / 4), 256, 0, st>>>(S.At64, S.ldat64, S.d, S.n, nu2_ws);
-        CSK_LAUNCH_CHECK("k_row_norms2");
+        const csk_status e = launch_row_norms2(S.At64, S.ldat64, S.d, S.n, nu2_ws, st);
+        if (e != CSK_OK) return e;
         S.nu2 = nu2_ws;
     }
     if (plan.grid > 1) {
@@ -1233,8 +1233,8 @@ csk_status solve_rgrk_run(const SolveSys& sys_in, const csk_solve_opts* o, doubl
         return CSK_ERR_WORKSPACE;
     }
     if (S.nu2 == nullptr) {
-        k_row_norms2<<<std::min(4096, (S.d + 3) / 4), 256, 0, st>>>(S.At64, S.ldat64, S.d, S.n, nu2_ws);
-        CSK_LAUNCH_CHECK("k_row_norms2");
+        const csk_status e = launch_row_norms2(S.At64, S.ldat64, S.d, S.n, nu2_ws, st);
+        if (e != CSK_OK) return e;
         S.nu2 = nu2_ws;
     }
     if (plan.grid > 1) {
@@ -1247,6 +1247,13 @@ csk_status solve_rgrk_run(const SolveSys& sys_in, const csk_solve_opts* o, doubl
 }
 
 size_t solve_exch_record_bytes() { return sizeof(XRec); }
+
+csk_status launch_row_norms2(const double* A, int64_t lda, int64_t d, int64_t n, double* nu2, hipStream_t st)
+{
+    k_row_norms2<<<(int)std::min<int64_t>(4096, (d + 3) / 4), 256, 0, st>>>(A, lda, (int)d, (int)n, nu2);
+    CSK_LAUNCH_CHECK("k_row_norms2");
+    return CSK_OK;
+}
 
 csk_status solve_batched_run(const SolveSys* sys_dev, int32_t nsys, const BatchedPlan& bp, csk_dtype at_dtype,
                              const csk_solve_opts* o, hipStream_t st)

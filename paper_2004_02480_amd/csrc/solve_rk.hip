@@ -243,18 +243,6 @@ __global__ __launch_bounds__(kRkNT) void k_solve_rk(RkArgs P)
     }
 }
 
-__global__ __launch_bounds__(256) void k_rk_norms2(const double* __restrict__ A, int64_t lda, int d, int n,
-                                                  double* __restrict__ nu2)
-{
-    const int lane = threadIdx.x & (kWave - 1);
-    for (int64_t i = blockIdx.x * 4 + threadIdx.x / kWave; i < d; i += (int64_t)gridDim.x * 4) {
-        double s = 0.0;
-        for (int c = lane; c < n; c += kWave) s += A[i * lda + c] * A[i * lda + c];
-        s = wave_sum(s);
-        if (lane == 0) nu2[i] = s;
-    }
-}
-
 }  // namespace
 
 size_t solve_rk_ws_bytes(int64_t d)
@@ -278,8 +266,8 @@ csk_status solve_rk_run(const double* At, int64_t ldat, int64_t d, int64_t n, co
         return CSK_ERR_WORKSPACE;
     }
     if (nu2 == nullptr) {
-        k_rk_norms2<<<(int)std::min<int64_t>(4096, (d + 3) / 4), 256, 0, st>>>(At, ldat, (int)d, (int)n, nu2_ws);
-        CSK_LAUNCH_CHECK("k_rk_norms2");
+        const csk_status e = launch_row_norms2(At, ldat, d, n, nu2_ws, st);
+        if (e != CSK_OK) return e;
         nu2 = nu2_ws;
     }
     P.At = At;
