@@ -291,10 +291,26 @@ def table1_paper():
     return {(r["m"], r["n"]): (r["csk_it"], r["mwrk_it"], r["csk_cpu_s"], r["mwrk_cpu_s"]) for r in rows}
 
 
+def graph_of(fn, torch):
+    """fn's launches captured once into a HIP graph (through torch's stream
+    capture); returns (graph, fn's return value from the capture)."""
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        out = fn()
+    torch.cuda.synchronize()
+    return g, out
+
+
 def table1_workload(P, W, torch, trials=5):
     """Section 3's experiment on this GPU: CSK (sketch with d = n^2, then
     MWRK on the sketch) against MWRK on the full (A, b), mean iterations
-    and times over `trials` seeded draws per shape."""
+    and times over `trials` seeded draws per shape.  Each method is timed
+    twice: as eager library calls, and as one replay of a HIP graph holding
+    the same calls (no launch gaps between the sketch's kernels and the
+    solve)."""
     c = W.config("table1")
     dev = "cuda:0"
     paper = table1_paper()
@@ -302,7 +318,7 @@ def table1_workload(P, W, torch, trials=5):
     for m in c["ms"]:
         for n in c["ns"]:
             d = n * n
-            it_c, it_m, t_c, t_m = [], [], [], []
+            it_c, it_m, t_c, t_m, g_c, g_m = [], [], [], [], [], []
             for t in range(trials):
                 s = W.gaussian(m, n, c["seed"] + t, device=dev)
                 torch.cuda.synchronize()
@@ -329,16 +345,29 @@ def table1_workload(P, W, torch, trials=5):
                 it_m.append(im)
                 t_c.append(tc)
                 t_m.append(tm)
-                del s
+                gc, (_, rgc) = graph_of(csk, torch)
+                gm, (_, rgm) = graph_of(mwrk, torch)
+                gc.replay()
+                gm.replay()
+                tgc, _ = timed(gc.replay)
+                tgm, _ = timed(gm.replay)
+                if P.parse_results(rgc)[0][:2] != (ic, sc) or P.parse_results(rgm)[0][:2] != (im, sm):
+                    raise SystemExit(f"table1 {m}x{n} trial {t}: graph replay differs from the eager run")
+                g_c.append(tgc)
+                g_m.append(tgm)
+                del gc, gm, s
             mean = lambda v: sum(v) / len(v)
             pc, pm, pct, pmt = paper[(m, n)]
             row = dict(m=m, n=n, d=d, csk_it=mean(it_c), mwrk_it=mean(it_m), csk_s=mean(t_c), mwrk_s=mean(t_m),
                        it_speedup=mean(it_m) / mean(it_c), time_speedup=mean(t_m) / mean(t_c),
+                       csk_graph_s=mean(g_c), mwrk_graph_s=mean(g_m), time_speedup_graph=mean(g_m) / mean(g_c),
                        paper_csk_it=pc, paper_mwrk_it=pm, paper_time_speedup=pmt / pct)
             rows.append(row)
             log(f"[bench] table1 {m}x{n}: CSK {row['csk_it']:.1f} it {row['csk_s'] * 1e3:.2f} ms, "
                 f"MWRK {row['mwrk_it']:.1f} it {row['mwrk_s'] * 1e3:.2f} ms, time speedup "
-                f"{row['time_speedup']:.1f} (paper: CSK {pc} it, MWRK {pm} it, speedup {pmt / pct:.1f})")
+                f"{row['time_speedup']:.1f}; graphs: CSK {row['csk_graph_s'] * 1e3:.2f} ms, MWRK "
+                f"{row['mwrk_graph_s'] * 1e3:.2f} ms, speedup {row['time_speedup_graph']:.1f} "
+                f"(paper: CSK {pc} it, MWRK {pm} it, speedup {pmt / pct:.1f})")
     torch.cuda.empty_cache()
     return dict(trials=trials, rows=rows)
 

@@ -220,6 +220,55 @@ __global__ __launch_bounds__(256) void k_scatter(Batch b)
     }
 }
 
+// The same two steps for one system with at most kHistCap buckets, with the
+// contention of the global counters taken out: each block owns a contiguous
+// range of rows, counts them per bucket in LDS, and touches a global counter
+// once per bucket it holds (a few dozen blocks, so a counter sees a few
+// dozen updates instead of one per row).  The scatter reserves each bucket's
+// slots for the block in one update and hands them out from LDS; the order
+// inside a segment is fixed by the sort, as before.
+constexpr int kHistCap = 32768;  // buckets counted in LDS (128 KB, dynamic)
+constexpr int kHistNT = 1024;
+
+__device__ __forceinline__ void block_hist(const SketchSys& S, int64_t r0, int64_t r1, uint32_t* h)
+{
+    const uint32_t d = static_cast<uint32_t>(S.d);
+    for (uint32_t j = threadIdx.x; j < d; j += kHistNT) h[j] = 0u;
+    __syncthreads();
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kHistNT)
+        atomicAdd(&h[draw_bucket(draw_word(S.seed, static_cast<uint64_t>(i)), d)], 1u);
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kHistNT) void k_hash_hist_lds(Batch b, int64_t rows_per_block)
+{
+    extern __shared__ uint32_t h[];  // d counters
+    const SketchSys& S = b.one;
+    const int64_t r0 = min(b.M, blockIdx.x * rows_per_block), r1 = min(b.M, r0 + rows_per_block);
+    block_hist(S, r0, r1, h);
+    for (uint32_t j = threadIdx.x; j < static_cast<uint32_t>(S.d); j += kHistNT)
+        if (h[j]) atomicAdd(&b.cnt[j], h[j]);
+}
+
+__global__ __launch_bounds__(kHistNT) void k_scatter_lds(Batch b, int64_t rows_per_block)
+{
+    extern __shared__ uint32_t h[];  // d counters, then the block's next slot per bucket
+    const SketchSys& S = b.one;
+    const uint32_t d = static_cast<uint32_t>(S.d);
+    const int64_t r0 = min(b.M, blockIdx.x * rows_per_block), r1 = min(b.M, r0 + rows_per_block);
+    block_hist(S, r0, r1, h);
+    // counting down through cnt (it ends at zero): this block's slots of
+    // bucket j are [old - h[j], old)
+    for (uint32_t j = threadIdx.x; j < d; j += kHistNT)
+        if (h[j]) h[j] = atomicSub(&b.cnt[j], h[j]) - h[j];
+    __syncthreads();
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kHistNT) {
+        const uint32_t j = draw_bucket(draw_word(S.seed, static_cast<uint64_t>(i)), d);
+        const uint32_t pos = atomicAdd(&h[j], 1u);
+        b.perm[b.ptr[j] + pos] = static_cast<uint32_t>(i);
+    }
+}
+
 // Four wavefronts per block, one bucket each per round; rank sort in LDS
 // (row indices within a segment are distinct).
 __global__ __launch_bounds__(256) void k_sort_segments(Batch b)
@@ -781,11 +830,25 @@ csk_status group_rows(const Batch& b, hipStream_t st)
     const int64_t M = b.M, D = b.D;
     k_fill_u32<<<grid_for(D, 256, 4096), 256, 0, st>>>(b.cnt, D, 0u);
     CSK_LAUNCH_CHECK("k_fill_u32");
-    k_hash_hist<<<grid_for(M, 256, 16384), 256, 0, st>>>(b);
+    // one system with few buckets: block-aggregated counters (at most 64
+    // blocks of at least 8192 rows each)
+    const bool lds = b.nsys == 1 && D <= kHistCap;
+    const int64_t hblocks = std::max<int64_t>(1, std::min<int64_t>(64, (M + 8191) / 8192));
+    const int64_t hrows = (M + hblocks - 1) / hblocks;
+    const size_t hshm = (size_t)D * sizeof(uint32_t);
+    if (lds && hshm > (size_t)48 * 1024) {
+        CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_hash_hist_lds),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)hshm));
+        CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_scatter_lds),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)hshm));
+    }
+    if (lds) k_hash_hist_lds<<<(int)hblocks, kHistNT, hshm, st>>>(b, hrows);
+    else k_hash_hist<<<grid_for(M, 256, 16384), 256, 0, st>>>(b);
     CSK_LAUNCH_CHECK("k_hash_hist");
     csk_status r = exclusive_scan(b.cnt, D, b.scan_part, b.ptr, st);
     if (r != CSK_OK) return r;
-    k_scatter<<<grid_for(M, 256, 16384), 256, 0, st>>>(b);
+    if (lds) k_scatter_lds<<<(int)hblocks, kHistNT, hshm, st>>>(b, hrows);
+    else k_scatter<<<grid_for(M, 256, 16384), 256, 0, st>>>(b);
     CSK_LAUNCH_CHECK("k_scatter");
     k_sort_segments<<<grid_for(D, 4, 8192), 256, 0, st>>>(b);
     CSK_LAUNCH_CHECK("k_sort_segments");
