@@ -156,32 +156,35 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__
     }
 }
 
-// The whole exclusive scan in one block when the counts are few: wave w of
-// 16 holds a contiguous segment of ceil(D / 16) counts in registers (lane l
-// has elements l, l + 64, ...), so every load is issued at once and
-// coalesced; the wave totals are scanned in LDS, then each wave scans its
-// 64-element slices in order with a running carry.
+// The whole exclusive scan in one block when the counts are few (at most
+// 1024 x kScanRegs): the counts are staged in LDS with coalesced loads, each
+// thread sums and then rewrites a contiguous run of at most kScanRegs of
+// them, one wave scan (plus the 16 wave totals) turns the run totals into
+// run offsets, and the result leaves with coalesced stores.  (A per-wave
+// scan of 64-element slices in registers cost six cross-lane shuffles per
+// slice: about 13 us at 2500 to 22500 counts.)
 constexpr int kScanRegs = 32;
 constexpr int64_t kScanSingleMax = 16 * 64 * kScanRegs;
 __global__ __launch_bounds__(1024) void k_scan_single(const uint32_t* __restrict__ cnt, int64_t D,
                                                      uint32_t* __restrict__ ptr)
 {
+    extern __shared__ uint32_t sc[];  // D counts, then their exclusive prefixes
     __shared__ uint32_t wtot[16];
     const int lane = threadIdx.x & (kWave - 1);
     const int w = threadIdx.x / kWave;
-    const int64_t seg = (D + 15) / 16;
-    const int64_t lo = min<int64_t>(D, w * seg), hi = min<int64_t>(D, lo + seg);
-    uint32_t v[kScanRegs];
+    for (int64_t j = threadIdx.x; j < D; j += 1024) sc[j] = cnt[j];
+    __syncthreads();
+    const int64_t per = (D + 1023) / 1024;
+    const int64_t lo = min<int64_t>(D, threadIdx.x * per), hi = min<int64_t>(D, lo + per);
     uint32_t sum = 0;
+    for (int64_t j = lo; j < hi; ++j) sum += sc[j];
+    uint32_t x = sum;
 #pragma unroll
-    for (int i = 0; i < kScanRegs; ++i) {
-        const int64_t j = lo + i * kWave + lane;
-        v[i] = j < hi ? cnt[j] : 0u;
-        sum += v[i];
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t t = __shfl_up(x, off, kWave);
+        if (lane >= off) x += t;
     }
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, kWave);
-    if (lane == 0) wtot[w] = sum;
+    if (lane == kWave - 1) wtot[w] = x;
     __syncthreads();
     uint32_t carry = 0, total = 0;
 #pragma unroll
@@ -190,18 +193,14 @@ __global__ __launch_bounds__(1024) void k_scan_single(const uint32_t* __restrict
         if (k < w) carry += t;
         total += t;
     }
-#pragma unroll
-    for (int i = 0; i < kScanRegs; ++i) {
-        uint32_t x = v[i];
-#pragma unroll
-        for (int off = 1; off < kWave; off <<= 1) {
-            const uint32_t t = __shfl_up(x, off, kWave);
-            if (lane >= off) x += t;
-        }
-        const int64_t j = lo + i * kWave + lane;
-        if (j < hi) ptr[j] = carry + x - v[i];
-        carry += __shfl(x, kWave - 1, kWave);
+    uint32_t run = carry + x - sum;
+    for (int64_t j = lo; j < hi; ++j) {
+        const uint32_t v = sc[j];
+        sc[j] = run;
+        run += v;
     }
+    __syncthreads();
+    for (int64_t j = threadIdx.x; j < D; j += 1024) ptr[j] = sc[j];
     if (threadIdx.x == 0) ptr[D] = total;
 }
 
@@ -809,7 +808,11 @@ void launch_segsum(const Batch& b, csk_dtype a_dtype, Geometry g, csk_dtype lp, 
 csk_status exclusive_scan(const uint32_t* cnt, int64_t D, uint32_t* part, uint32_t* ptr, hipStream_t st)
 {
     if (D <= kScanSingleMax) {
-        k_scan_single<<<1, 1024, 0, st>>>(cnt, D, ptr);
+        const size_t shm = (size_t)D * sizeof(uint32_t);
+        if (shm > (size_t)48 * 1024)
+            CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_scan_single),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+        k_scan_single<<<1, 1024, shm, st>>>(cnt, D, ptr);
         CSK_LAUNCH_CHECK("k_scan_single");
         return CSK_OK;
     }
