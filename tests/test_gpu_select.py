@@ -118,6 +118,22 @@ def test_rk_iterates_match_oracle(gpu, orc, n, K):
     assert np.linalg.norm(r.x.cpu().numpy() - o.x) <= 1e-12 * np.linalg.norm(o.x)
 
 
+@pytest.mark.parametrize("n", [900, 3000, 8192])
+def test_rk_wide_rows_match_oracle(gpu, orc, n):
+    # 2, 8 and 16 columns per thread (ring depths 4, 2 and 1), on a plain
+    # random system (the rule takes any matrix); 600 steps cross a draw batch
+    d, K = 1500, 600
+    g = torch.Generator().manual_seed(n)
+    A = torch.randn(d, n, dtype=torch.float64, generator=g)
+    xs = torch.randn(n, dtype=torch.float64, generator=g)
+    b = A @ xs
+    An, bn, xn = A.numpy(), b.numpy(), xs.numpy()
+    r = gpu.csk_solve_rk(A.to(DEV), b.to(DEV), sel_seed=12, x_ref=xs.to(DEV), tol=0.0, maxit=K)
+    assert r.status == gpu.CSK_NOT_CONVERGED and r.iters == K
+    o = orc.rk(An, bn, sel_seed=12, xref=xn, tol=0.0, maxit=K)
+    assert np.linalg.norm(r.x.cpu().numpy() - o.x) <= 1e-12 * np.linalg.norm(o.x)
+
+
 def test_rk_converges_with_library_norms_and_x0(gpu, orc):
     s, sk, At, bt = _setup(gpu, orc, 8000, 60, 900, 81, 82)
     xs = s.x_star.cpu().numpy()
