@@ -5,17 +5,18 @@
 // the drawn row's residual is formed, so an iteration reads one row.
 //
 // One workgroup runs the whole loop (one row per iteration leaves nothing to
-// spread over the chip; the cost is latency):
-//   * setup: the cumulative squared norms C_i into the workspace, each
-//     thread summing its own contiguous segment of rows, thread 0 the
-//     segment totals, then each thread its segment from its offset (the
-//     rounding differs from one running sum in index order only by where the
-//     partial sums meet);
+// spread over the chip; the cost is latency), a single wavefront for rows of
+// up to 1024 columns, so an iteration needs no barrier between waves:
+//   * setup (a kernel of its own, 512 threads): the cumulative squared norms
+//     C_i into the workspace, each thread summing its own contiguous segment
+//     of rows, thread 0 the segment totals, then each thread its segment
+//     from its offset (the rounding differs from one running sum in index
+//     order only by where the partial sums meet);
 //   * the draws do not depend on x, so the rows of 512 iterations are found
 //     at once, one binary search per thread for the smallest i with
 //     C_i > u_k C_{d-1} (u_k the k-th uniform of the selection stream), and
 //     kept in LDS a batch ahead;
-//   * each thread owns columns tid + 512 j of x, x_ref and the rows
+//   * each thread owns columns tid + NT j of x, x_ref and the rows
 //     (registers), so an iteration is one workgroup reduction (the row's dot
 //     product with x_k and ||x_k - x_ref||^2), the stop test on x_k, and the
 //     update of the thread's own columns.  Rows are loaded up to four
@@ -30,9 +31,8 @@
 namespace csk {
 namespace {
 
-constexpr int kRkNT = 512;
-constexpr int kRkNW = kRkNT / kWave;
-constexpr int kRkBatch = kRkNT;     // iterations whose rows are drawn together
+constexpr int kRkNT = 512;          // threads of the setup, and of the loop for wide rows
+constexpr int kRkBatch = 512;       // iterations whose rows are drawn together
 // Iterations between a row's load and its use: 4, fewer where the ring
 // would not fit the registers (columns per thread J of 8 and 16).
 template <int J> constexpr int rk_ahead() { return J >= 16 ? 1 : J >= 8 ? 2 : 4; }
@@ -56,42 +56,57 @@ struct RkArgs {
 };
 
 // Smallest i with cum[i] > t (cum[d-1] > t when the distribution is valid;
-// otherwise the result is d - 1, never used).  Where two segments of the
-// prefix sum meet, cum may step back by a few units in the last place; a
-// draw landing in such a sliver could reach a row of zero norm, which is
-// then replaced by the nearest row of nonzero norm before it (or after it).
-__device__ __forceinline__ int rk_search(const double* __restrict__ cum, const double* __restrict__ nu2, int d,
-                                         double t)
+// otherwise the result is d - 1, never used), for K draws at once: the
+// searches run in lockstep with unconditional loads (mid = lo once a search
+// has ended), so their loads overlap.  Where two segments of the prefix sum
+// meet, cum may step back by a few units in the last place; a draw landing
+// in such a sliver could reach a row of zero norm, which is then replaced by
+// the nearest row of nonzero norm before it (or after it).
+template <int K>
+__device__ __forceinline__ void rk_search(const double* __restrict__ cum, const double* __restrict__ nu2, int d,
+                                          const double (&t)[K], int (&out)[K])
 {
-    int lo = 0, hi = d - 1;
-    while (lo < hi) {
-        const int mid = lo + ((hi - lo) >> 1);
-        if (cum[mid] > t) hi = mid;
-        else lo = mid + 1;
+    int lo[K], hi[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        lo[k] = 0;
+        hi[k] = d - 1;
     }
-    if (!(nu2[lo] > 0.0)) {
-        int i = lo;
-        while (i > 0 && !(nu2[i] > 0.0)) --i;
-        if (!(nu2[i] > 0.0))
-            for (i = lo; i + 1 < d && !(nu2[i] > 0.0);) ++i;
-        lo = i;
+    // each round halves every open interval: bit length of d rounds suffice
+    for (int span = d; span > 0; span >>= 1) {
+        double c[K];
+        int mid[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            mid[k] = lo[k] + ((hi[k] - lo[k]) >> 1);
+            c[k] = cum[mid[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (lo[k] < hi[k]) {
+                if (c[k] > t[k]) hi[k] = mid[k];
+                else lo[k] = mid[k] + 1;
+            }
+        }
     }
-    return lo;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        int i = lo[k];
+        if (!(nu2[i] > 0.0)) {
+            while (i > 0 && !(nu2[i] > 0.0)) --i;
+            if (!(nu2[i] > 0.0))
+                for (i = lo[k]; i + 1 < d && !(nu2[i] > 0.0);) ++i;
+        }
+        out[k] = i;
+    }
 }
 
-template <int J>
-__global__ __launch_bounds__(kRkNT) void k_solve_rk(RkArgs P)
+// C_i for i < d into P.cum.
+__global__ __launch_bounds__(kRkNT) void k_rk_prefix(RkArgs P)
 {
     __shared__ double seg[kRkNT];
-    __shared__ int32_t pick[2][kRkBatch];
-    __shared__ double red[2][kRkNW][2];
-    __shared__ int32_t s_cancel[2];
-    __shared__ double s_total;
     const int tid = threadIdx.x;
-    const int wave = tid / kWave;
-    const int lane = tid & (kWave - 1);
-    const int d = P.d, n = P.n;
-
+    const int d = P.d;
     // C_i: segment sums, their exclusive prefix (thread 0, in order), then
     // the running sum of each segment from its offset
     const int span = (d + kRkNT - 1) / kRkNT;
@@ -116,7 +131,6 @@ __global__ __launch_bounds__(kRkNT) void k_solve_rk(RkArgs P)
             seg[t] = run;
             run += v;
         }
-        s_total = run;
     }
     __syncthreads();
     double acc = seg[tid];
@@ -134,21 +148,42 @@ __global__ __launch_bounds__(kRkNT) void k_solve_rk(RkArgs P)
         acc += P.nu2[i];
         P.cum[i] = acc;
     }
-    if (i1 == d && i0 < i1) s_total = acc;  // the last element's running sum, as the search sees it
-    __syncthreads();
-    const double total = s_total;
+}
+
+// NT threads (64: one wavefront; or 512), J columns per thread.
+template <int NT, int J>
+__global__ __launch_bounds__(NT) void k_solve_rk(RkArgs P)
+{
+    constexpr int NW = NT / kWave;
+    __shared__ int32_t pick[2][kRkBatch];
+    __shared__ double red[2][NW][2];
+    __shared__ int32_t s_cancel[2];
+    const int tid = threadIdx.x;
+    const int wave = tid / kWave;
+    const int lane = tid & (kWave - 1);
+    const int d = P.d, n = P.n;
+
+    const double total = P.cum[d - 1];  // the last running sum, as the search sees it
     const bool valid = isfinite(total) && total > 0.0;
 
+    // this thread's draws of a batch: iterations b * kRkBatch + tid + NT q
+    constexpr int KD = kRkBatch / NT;
     auto draw_batch = [&](int64_t b) {
-        const int64_t k = b * kRkBatch + tid;
-        pick[b & 1][tid] = valid ? rk_search(P.cum, P.nu2, d, select_uniform(P.seed, static_cast<uint64_t>(k)) * total) : 0;
+        double t[KD];
+        int r[KD];
+#pragma unroll
+        for (int q = 0; q < KD; ++q)
+            t[q] = select_uniform(P.seed, static_cast<uint64_t>(b * kRkBatch + tid + NT * q)) * total;
+        if (valid) rk_search<KD>(P.cum, P.nu2, d, t, r);
+#pragma unroll
+        for (int q = 0; q < KD; ++q) pick[b & 1][tid + NT * q] = valid ? r[q] : 0;
     };
     draw_batch(0);
     draw_batch(1);
 
     double x[J], xr[J];
     for (int j = 0; j < J; ++j) {
-        const int c = tid + j * kRkNT;
+        const int c = tid + j * NT;
         x[j] = (c < n && P.x0) ? P.x0[c] : 0.0;
         xr[j] = c < n ? P.xref[c] : 0.0;
     }
@@ -158,12 +193,12 @@ __global__ __launch_bounds__(kRkNT) void k_solve_rk(RkArgs P)
     if (lane == 0) red[1][wave][0] = q;
     __syncthreads();
     double xref2 = 0.0;
-    for (int w = 0; w < kRkNW; ++w) xref2 += red[1][w][0];
+    for (int w = 0; w < NW; ++w) xref2 += red[1][w][0];
 
     auto load_row = [&](int i, double (&v)[J], double& bi, double& ni) {
         const double* __restrict__ row = P.At + (int64_t)i * P.ldat;
         for (int j = 0; j < J; ++j) {
-            const int c = tid + j * kRkNT;
+            const int c = tid + j * NT;
             v[j] = c < n ? row[c] : 0.0;
         }
         bi = P.bt[i];
@@ -212,7 +247,7 @@ __global__ __launch_bounds__(kRkNT) void k_solve_rk(RkArgs P)
             if (tid == 0) s_cancel[par] = (P.cancel && (k % P.check_every) == 0 && *P.cancel != 0) ? 1 : 0;
             __syncthreads();
             double dot = 0.0, e2 = 0.0;
-            for (int w = 0; w < kRkNW; ++w) {
+            for (int w = 0; w < NW; ++w) {
                 dot += red[par][w][0];
                 e2 += red[par][w][1];
             }
@@ -231,7 +266,7 @@ __global__ __launch_bounds__(kRkNT) void k_solve_rk(RkArgs P)
         }
     }
     for (int j = 0; j < J; ++j) {
-        const int c = tid + j * kRkNT;
+        const int c = tid + j * NT;
         if (c < n) P.x[c] = x[j];
     }
     if (tid == 0 && P.res) {
@@ -285,15 +320,25 @@ csk_status solve_rk_run(const double* At, int64_t ldat, int64_t d, int64_t n, co
     P.d = (int32_t)d;
     P.n = (int32_t)n;
     P.check_every = o->check_every > 0 ? o->check_every : 256;
-    const int64_t per = (n + kRkNT - 1) / kRkNT;
-    if (per <= 1) k_solve_rk<1><<<1, kRkNT, 0, st>>>(P);
-    else if (per <= 2) k_solve_rk<2><<<1, kRkNT, 0, st>>>(P);
-    else if (per <= 4) k_solve_rk<4><<<1, kRkNT, 0, st>>>(P);
-    else if (per <= 8) k_solve_rk<8><<<1, kRkNT, 0, st>>>(P);
-    else if (per <= 16) k_solve_rk<16><<<1, kRkNT, 0, st>>>(P);
-    else {
-        set_error("n=%lld exceeds %d", (long long)n, 16 * kRkNT);
-        return CSK_ERR_UNSUPPORTED;
+    k_rk_prefix<<<1, kRkNT, 0, st>>>(P);
+    CSK_LAUNCH_CHECK("k_rk_prefix");
+    // one wavefront up to 16 columns per lane (1024), else 512 threads
+    if (n <= 16 * kWave) {
+        const int64_t per = (n + kWave - 1) / kWave;
+        if (per <= 1) k_solve_rk<kWave, 1><<<1, kWave, 0, st>>>(P);
+        else if (per <= 2) k_solve_rk<kWave, 2><<<1, kWave, 0, st>>>(P);
+        else if (per <= 4) k_solve_rk<kWave, 4><<<1, kWave, 0, st>>>(P);
+        else if (per <= 8) k_solve_rk<kWave, 8><<<1, kWave, 0, st>>>(P);
+        else k_solve_rk<kWave, 16><<<1, kWave, 0, st>>>(P);
+    } else {
+        const int64_t per = (n + kRkNT - 1) / kRkNT;
+        if (per <= 4) k_solve_rk<kRkNT, 4><<<1, kRkNT, 0, st>>>(P);
+        else if (per <= 8) k_solve_rk<kRkNT, 8><<<1, kRkNT, 0, st>>>(P);
+        else if (per <= 16) k_solve_rk<kRkNT, 16><<<1, kRkNT, 0, st>>>(P);
+        else {
+            set_error("n=%lld exceeds %d", (long long)n, 16 * kRkNT);
+            return CSK_ERR_UNSUPPORTED;
+        }
     }
     CSK_LAUNCH_CHECK("k_solve_rk");
     return CSK_OK;
