@@ -7,11 +7,10 @@
 // One workgroup runs the whole loop (one row per iteration leaves nothing to
 // spread over the chip; the cost is latency), a single wavefront for rows of
 // up to 1024 columns, so an iteration needs no barrier between waves:
-//   * setup (a kernel of its own, 512 threads): the cumulative squared norms
-//     C_i into the workspace, each thread summing its own contiguous segment
-//     of rows, thread 0 the segment totals, then each thread its segment
-//     from its offset (the rounding differs from one running sum in index
-//     order only by where the partial sums meet);
+//   * setup (kernels of their own): the cumulative squared norms C_i into
+//     the workspace, by block sums, their prefix and block-local scans (the
+//     rounding differs from one running sum in index order only by where
+//     the partial sums meet);
 //   * the draws do not depend on x, so the rows of 512 iterations are found
 //     at once, one binary search per thread for the smallest i with
 //     C_i > u_k C_{d-1} (u_k the k-th uniform of the selection stream), and
@@ -101,52 +100,73 @@ __device__ __forceinline__ void rk_search(const double* __restrict__ cum, const 
     }
 }
 
-// C_i for i < d into P.cum.
-__global__ __launch_bounds__(kRkNT) void k_rk_prefix(RkArgs P)
+// C_i for i < d into P.cum, over kRkScanBlocks blocks of 256 threads: the
+// blocks' sums (coalesced), their exclusive prefix (one thread, in order),
+// then each block scans its range 256 elements at a time (wave scans, then
+// the four wave totals) from its offset.
+constexpr int kRkScanBlocks = 256;
+constexpr int kRkScanNT = 256;
+
+__device__ __forceinline__ double rk_block_sum(double v, double* wred)
 {
-    __shared__ double seg[kRkNT];
-    const int tid = threadIdx.x;
-    const int d = P.d;
-    // C_i: segment sums, their exclusive prefix (thread 0, in order), then
-    // the running sum of each segment from its offset
-    const int span = (d + kRkNT - 1) / kRkNT;
-    const int i0 = min(d, tid * span), i1 = min(d, i0 + span);
-    // 16 loads in flight per thread (one cache line), the adds in order
-    double part = 0.0;
-    int i = i0;
-    for (; i + 16 <= i1; i += 16) {
-        double v[16];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) v[u] = P.nu2[i + u];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) part += v[u];
-    }
-    for (; i < i1; ++i) part += P.nu2[i];
-    seg[tid] = part;
+    v = group_sum_t<double, kWave>(v);
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) wred[w] = v;
     __syncthreads();
-    if (tid == 0) {
+    const double t = ((wred[0] + wred[1]) + wred[2]) + wred[3];
+    __syncthreads();
+    return t;
+}
+
+__global__ __launch_bounds__(kRkScanNT) void k_rk_blocksum(RkArgs P, double* bsum)
+{
+    __shared__ double wred[kRkScanNT / kWave];
+    const int64_t span = (P.d + kRkScanBlocks - 1) / kRkScanBlocks;
+    const int64_t lo = min<int64_t>(P.d, blockIdx.x * span), hi = min<int64_t>(P.d, lo + span);
+    double v = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kRkScanNT) v += P.nu2[i];
+    const double t = rk_block_sum(v, wred);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = t;
+}
+
+__global__ void k_rk_blockoff(double* bsum)
+{
+    if (threadIdx.x == 0) {
         double run = 0.0;
-        for (int t = 0; t < kRkNT; ++t) {
-            const double v = seg[t];
-            seg[t] = run;
+        for (int b = 0; b < kRkScanBlocks; ++b) {
+            const double v = bsum[b];
+            bsum[b] = run;
             run += v;
         }
     }
-    __syncthreads();
-    double acc = seg[tid];
-    for (i = i0; i + 16 <= i1; i += 16) {
-        double v[16];
+}
+
+__global__ __launch_bounds__(kRkScanNT) void k_rk_prefix(RkArgs P, const double* boff)
+{
+    __shared__ double wtot[kRkScanNT / kWave];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+    const int64_t span = (P.d + kRkScanBlocks - 1) / kRkScanBlocks;
+    const int64_t lo = min<int64_t>(P.d, blockIdx.x * span), hi = min<int64_t>(P.d, lo + span);
+    double carry = boff[blockIdx.x];
+    for (int64_t base = lo; base < hi; base += kRkScanNT) {
+        const int64_t i = base + threadIdx.x;
+        const double v = i < hi ? P.nu2[i] : 0.0;
+        double x = v;
 #pragma unroll
-        for (int u = 0; u < 16; ++u) v[u] = P.nu2[i + u];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            acc += v[u];
-            P.cum[i + u] = acc;
+        for (int off = 1; off < kWave; off <<= 1) {
+            const double t = __shfl_up(x, off, kWave);
+            if (lane >= off) x += t;
         }
-    }
-    for (; i < i1; ++i) {
-        acc += P.nu2[i];
-        P.cum[i] = acc;
+        if (lane == kWave - 1) wtot[w] = x;
+        __syncthreads();
+        double before = carry;
+        for (int k = 0; k < w; ++k) before += wtot[k];
+        if (i < hi) P.cum[i] = before + x;
+        // the same additions as the chunk's last element, so the next chunk
+        // starts exactly where this one ended
+        carry = (((carry + wtot[0]) + wtot[1]) + wtot[2]) + wtot[3];
+        __syncthreads();
     }
 }
 
@@ -285,6 +305,7 @@ size_t solve_rk_ws_bytes(int64_t d)
     Carve c(nullptr);
     c.take<double>(d);  // cumulative squared norms
     c.take<double>(d);  // nu2 when not supplied
+    c.take<double>(kRkScanBlocks);  // block sums of the prefix
     return c.bytes();
 }
 
@@ -296,6 +317,7 @@ csk_status solve_rk_run(const double* At, int64_t ldat, int64_t d, int64_t n, co
     RkArgs P{};
     P.cum = c.take<double>(d);
     double* nu2_ws = c.take<double>(d);
+    double* bsum = c.take<double>(kRkScanBlocks);
     if (c.bytes() > ws_bytes) {
         set_error("solve workspace too small: need %zu bytes, got %zu", c.bytes(), ws_bytes);
         return CSK_ERR_WORKSPACE;
@@ -320,7 +342,11 @@ csk_status solve_rk_run(const double* At, int64_t ldat, int64_t d, int64_t n, co
     P.d = (int32_t)d;
     P.n = (int32_t)n;
     P.check_every = o->check_every > 0 ? o->check_every : 256;
-    k_rk_prefix<<<1, kRkNT, 0, st>>>(P);
+    k_rk_blocksum<<<kRkScanBlocks, kRkScanNT, 0, st>>>(P, bsum);
+    CSK_LAUNCH_CHECK("k_rk_blocksum");
+    k_rk_blockoff<<<1, kWave, 0, st>>>(bsum);
+    CSK_LAUNCH_CHECK("k_rk_blockoff");
+    k_rk_prefix<<<kRkScanBlocks, kRkScanNT, 0, st>>>(P, bsum);
     CSK_LAUNCH_CHECK("k_rk_prefix");
     // one wavefront up to 16 columns per lane (1024), else 512 threads
     if (n <= 16 * kWave) {
