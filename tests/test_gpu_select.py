@@ -179,3 +179,13 @@ def test_select_status_paths(gpu):
     nun = (A * A).sum(1)
     nun[2] = float("nan")
     assert gpu.csk_solve_rk(A, b, nu2=nun, x_ref=xs, tol=1e-12, maxit=100).status == gpu.CSK_ERR_NONFINITE
+    # one workgroup cannot keep the residuals of 30000 rows in LDS: refused
+    # before launch, with a message; the grid path takes the same system
+    big = torch.randn(30000, 8, dtype=torch.float64, device=DEV)
+    bb = big @ xs.new_ones(8)
+    with pytest.raises(gpu.CskError) as ei:
+        gpu.csk_solve_rgrk(big, bb, x_ref=xs.new_ones(8), tol=1e-8, maxit=100, single_wg=1)
+    assert ei.value.status == gpu.CSK_ERR_UNSUPPORTED
+    assert "LDS" in str(ei.value)
+    r = gpu.csk_solve_rgrk(big, bb, x_ref=xs.new_ones(8), tol=1e-8, maxit=100000, single_wg=0)
+    assert r.status == gpu.CSK_OK
