@@ -106,6 +106,14 @@ typedef struct csk_solve_opts {
     int32_t grid;            /* persistent grid size; 0 -> automatic             */
     int32_t block;           /* threads per workgroup; 0 -> automatic            */
     int32_t single_wg;       /* -1 auto, 0 force grid path, 1 force one WG       */
+    int64_t* trace_idx;      /* nullable, device, at least maxit entries: the
+                                solve writes trace_idx[k] = i_k, the row it
+                                projects onto at iteration k, for every k <
+                                iters (Algorithm 1's selected index; entries
+                                from iters on are left as they were).  Read by
+                                csk_solve, csk_solve_csr, csk_solve_rgrk and
+                                csk_solve_rk; the batched and multi-RHS calls
+                                ignore it.                                       */
 } csk_solve_opts;
 
 /* Written by the device at the end of a solve (device memory). */
@@ -341,6 +349,22 @@ csk_status csk_solve_batched(const csk_system_desc* sys /*host*/, int32_t nsys,
                              csk_dtype a_dtype, csk_dtype lp_dtype,
                              const csk_solve_opts* opts /*host*/, csk_solve_result* res,
                              void* ws, size_t ws_bytes, void* stream);
+
+/* Where csk_solve_batched keeps system s's sketch (Definition 1 and
+ * Algorithm 1, Initialize, applied to that system) inside its workspace,
+ * for callers that read the sketch the solve used once the call's work has
+ * finished.  Byte offsets count from the start of ws; at64 holds d x n FP64
+ * with leading dimension ld64, at_lp (-1 when lp_dtype is F64) d x n in
+ * lp_dtype with leading dimension ld_lp, both with zeros past column n; bt
+ * and nu2 hold d FP64 each.  Arguments as csk_solve_batched_workspace_size;
+ * 0 <= s < nsys.  The layout depends only on the descriptors' sizes and the
+ * two dtypes.                                                              */
+typedef struct csk_batched_sketch_loc {
+    int64_t at64, at_lp, bt, nu2;  /* byte offsets into ws                      */
+    int64_t ld64, ld_lp;           /* leading dimensions, in elements            */
+} csk_batched_sketch_loc;
+csk_status csk_solve_batched_sketch_loc(const csk_system_desc* sys /*host*/, int32_t nsys, csk_dtype a_dtype,
+                                        csk_dtype lp_dtype, int32_t s, csk_batched_sketch_loc* out /*host*/);
 
 /* ---- A9: one sketch, many right-hand sides ----------------------------- *
  * Runs the loop of Algorithm 1 independently for each column j of Bt (d x

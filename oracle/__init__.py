@@ -58,8 +58,31 @@ def _load():
     lib.orc_rk.argtypes = [_p, _i64, _i64, _i64, _p, _p, _p, ctypes.c_double, _i64, _u64,
                            _p, _p, _p, _p, _p]
     lib.orc_uniform_stream.argtypes = [_u64, _i64, _i64, _p]
+    lib.orc_set_threads.restype = ctypes.c_int
+    lib.orc_set_threads.argtypes = [ctypes.c_int]
+    lib.orc_set_threads(1)
     _lib = lib
     return lib
+
+
+def set_threads(t: int) -> int:
+    """Threads for the sketch's bucket ranges and the loop's residual rows
+    (bitwise the single-thread results); returns the count in effect."""
+    return int(_load().orc_set_threads(int(t)))
+
+
+class threads:
+    """Context manager: run the oracle on t threads, then go back to one."""
+
+    def __init__(self, t: int):
+        self.t = t
+
+    def __enter__(self):
+        return set_threads(self.t)
+
+    def __exit__(self, *exc):
+        set_threads(1)
+        return False
 
 
 def _ptr(a):

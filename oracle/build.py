@@ -2,7 +2,8 @@
 
 Compiled with plain gcc, -O2 -ffp-contract=off and no fast-math, so each
 floating-point operation of the oracle is one IEEE binary64 operation in
-source order.
+source order.  -fopenmp enables the oracle's two thread-parallel loops
+(bitwise the single-thread results; one thread unless asked).
 """
 import os
 import subprocess
@@ -13,7 +14,7 @@ LIB = os.path.join(HERE, "libcsk_oracle.so")
 
 
 def build(verbose: bool = False) -> str:
-    cmd = ["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math",
+    cmd = ["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
            "-fPIC", "-shared", "-Wall", "-o", LIB + ".tmp", SRC, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)

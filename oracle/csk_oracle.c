@@ -9,9 +9,14 @@
  * the HIP library; the two are written independently from the paper (and,
  * for the hash, from the published definition of SplitMix64).
  *
- * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no fast-math), so every
- * floating-point operation below is one IEEE-754 binary64 operation in the
- * order written.
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared (no fast-math), so
+ * every floating-point operation below is one IEEE-754 binary64 operation in
+ * the order written.  Two loops may run on several threads (orc_set_threads;
+ * one thread unless asked): the sketch over ranges of buckets and the
+ * residual of the MWRK loop over rows.  Each thread still computes whole
+ * entries in the written order (a bucket entry's sum over ascending rows, a
+ * residual's sum over ascending columns), so every result is bitwise the
+ * single-thread one.
  *
  * What each function follows:
  *   orc_hash             Definition 1 (count sketch transform S = Phi D): the
@@ -48,6 +53,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* Status values returned by orc_mwrk.  They carry the same meaning (and, by
  * deliberate interface agreement, the same numbers) as the library's status
@@ -143,6 +151,11 @@ void orc_bucket_sort(const uint32_t* bucket, int64_t m, int64_t d, uint32_t* per
  * entries of its bucket in ascending row order.  B (m x nrhs, leading
  * dimension ldb) is sketched the same way into Bt (d x nrhs).  Either of
  * A/At or B/Bt may be NULL. */
+/* The rows of At (and Bt) are split into ranges of buckets, one per loop
+ * index g; range g visits every row i in ascending order and adds the rows
+ * that land in it.  With one thread this is the plain loop over i. */
+#define ORC_SKETCH_RANGES 64
+
 void orc_sketch_dense_f64(const double* A, int64_t m, int64_t n, int64_t lda,
                           const double* B, int64_t nrhs, int64_t ldb,
                           int64_t d, uint64_t seed,
@@ -154,14 +167,19 @@ void orc_sketch_dense_f64(const double* A, int64_t m, int64_t n, int64_t lda,
     if (Bt)
         for (int64_t j = 0; j < d; ++j)
             for (int64_t c = 0; c < nrhs; ++c) Bt[j * ldbt + c] = 0.0;
-    for (int64_t i = 0; i < m; ++i) {
-        uint64_t w = orc_row_word(seed, (uint64_t)i);
-        int64_t h = (int64_t)orc_bucket_of(w, (uint64_t)d);
-        double s = (double)orc_sign_of(w);
-        if (A && At)
-            for (int64_t c = 0; c < n; ++c) At[h * ldat + c] = At[h * ldat + c] + s * A[i * lda + c];
-        if (B && Bt)
-            for (int64_t c = 0; c < nrhs; ++c) Bt[h * ldbt + c] = Bt[h * ldbt + c] + s * B[i * ldb + c];
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t g = 0; g < ORC_SKETCH_RANGES; ++g) {
+        const int64_t j0 = d * g / ORC_SKETCH_RANGES, j1 = d * (g + 1) / ORC_SKETCH_RANGES;
+        for (int64_t i = 0; i < m; ++i) {
+            uint64_t w = orc_row_word(seed, (uint64_t)i);
+            int64_t h = (int64_t)orc_bucket_of(w, (uint64_t)d);
+            if (h < j0 || h >= j1) continue;
+            double s = (double)orc_sign_of(w);
+            if (A && At)
+                for (int64_t c = 0; c < n; ++c) At[h * ldat + c] = At[h * ldat + c] + s * A[i * lda + c];
+            if (B && Bt)
+                for (int64_t c = 0; c < nrhs; ++c) Bt[h * ldbt + c] = Bt[h * ldbt + c] + s * B[i * ldb + c];
+        }
     }
 }
 
@@ -177,15 +195,20 @@ void orc_sketch_dense_f32(const float* A, int64_t m, int64_t n, int64_t lda,
     if (Bt)
         for (int64_t j = 0; j < d; ++j)
             for (int64_t c = 0; c < nrhs; ++c) Bt[j * ldbt + c] = 0.0;
-    for (int64_t i = 0; i < m; ++i) {
-        uint64_t w = orc_row_word(seed, (uint64_t)i);
-        int64_t h = (int64_t)orc_bucket_of(w, (uint64_t)d);
-        double s = (double)orc_sign_of(w);
-        if (A && At)
-            for (int64_t c = 0; c < n; ++c)
-                At[h * ldat + c] = At[h * ldat + c] + s * (double)A[i * lda + c];
-        if (B && Bt)
-            for (int64_t c = 0; c < nrhs; ++c) Bt[h * ldbt + c] = Bt[h * ldbt + c] + s * B[i * ldb + c];
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t g = 0; g < ORC_SKETCH_RANGES; ++g) {
+        const int64_t j0 = d * g / ORC_SKETCH_RANGES, j1 = d * (g + 1) / ORC_SKETCH_RANGES;
+        for (int64_t i = 0; i < m; ++i) {
+            uint64_t w = orc_row_word(seed, (uint64_t)i);
+            int64_t h = (int64_t)orc_bucket_of(w, (uint64_t)d);
+            if (h < j0 || h >= j1) continue;
+            double s = (double)orc_sign_of(w);
+            if (A && At)
+                for (int64_t c = 0; c < n; ++c)
+                    At[h * ldat + c] = At[h * ldat + c] + s * (double)A[i * lda + c];
+            if (B && Bt)
+                for (int64_t c = 0; c < nrhs; ++c) Bt[h * ldbt + c] = Bt[h * ldbt + c] + s * B[i * ldb + c];
+        }
     }
 }
 
@@ -297,6 +320,19 @@ void orc_round_f32_to_f16(const float* in, uint16_t* out, int64_t count)
     for (int64_t k = 0; k < count; ++k) out[k] = orc_f32_to_f16(in[k]);
 }
 
+/* Threads for the two parallel loops (values < 1 mean 1); returns the
+ * count in effect (1 when built without OpenMP). */
+int orc_set_threads(int t)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(t < 1 ? 1 : t);
+    return omp_get_max_threads();
+#else
+    (void)t;
+    return 1;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Algorithm 1, loop.                                                        */
 /* ------------------------------------------------------------------------ */
@@ -365,13 +401,14 @@ int orc_mwrk(const double* At, int64_t d, int64_t n, int64_t ldat, const double*
             if (trace_err2) trace_err2[k] = err2;
         }
         /* step 2 (computed before the test so the residual mode can use it) */
-        double r2 = 0.0;
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < d; ++i) {
             double dot = 0.0;
             for (int64_t c = 0; c < n; ++c) dot = dot + At[i * ldat + c] * x[c];
             r[i] = bt[i] - dot;
-            r2 = r2 + r[i] * r[i];
         }
+        double r2 = 0.0;
+        for (int64_t i = 0; i < d; ++i) r2 = r2 + r[i] * r[i];
         /* step 1 */
         if (stop_mode == ORC_STOP_REL_ERR) {
             if (xref2 > 0.0 ? (err2 / xref2 <= tol * tol) : (err2 <= tol * tol)) { status = ORC_OK; break; }

@@ -40,7 +40,7 @@ EXPORTED = [
     "csk_solve_rgrk_workspace_size", "csk_solve_rgrk",
     "csk_solve_rk_workspace_size", "csk_solve_rk",
     "csk_pipeline_capture", "csk_pipeline_launch", "csk_pipeline_destroy",
-    "csk_solve_batched_workspace_size", "csk_solve_batched",
+    "csk_solve_batched_workspace_size", "csk_solve_batched", "csk_solve_batched_sketch_loc",
     "csk_solve_mrhs_workspace_size", "csk_solve_mrhs",
     "csk_tune_solve_workspace_size", "csk_tune_solve", "csk_tune_lookup", "csk_tune_clear",
 ]
@@ -58,6 +58,7 @@ class SolveOpts(ctypes.Structure):
         ("grid", ctypes.c_int32),
         ("block", ctypes.c_int32),
         ("single_wg", ctypes.c_int32),
+        ("trace_idx", ctypes.c_void_p),
     ]
 
 
@@ -72,6 +73,17 @@ class SystemDesc(ctypes.Structure):
         ("lda", ctypes.c_int64),
         ("d", ctypes.c_int64),
         ("seed", ctypes.c_uint64),
+    ]
+
+
+class BatchedSketchLoc(ctypes.Structure):
+    _fields_ = [
+        ("at64", ctypes.c_int64),
+        ("at_lp", ctypes.c_int64),
+        ("bt", ctypes.c_int64),
+        ("nu2", ctypes.c_int64),
+        ("ld64", ctypes.c_int64),
+        ("ld_lp", ctypes.c_int64),
     ]
 
 
@@ -154,6 +166,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                               ctypes.POINTER(SolveOpts), P, P, SZ, P]
     lib.csk_solve_batched_workspace_size.restype = I32
     lib.csk_solve_batched_workspace_size.argtypes = [ctypes.POINTER(SystemDesc), I32, I32, I32, PSZ]
+    lib.csk_solve_batched_sketch_loc.restype = I32
+    lib.csk_solve_batched_sketch_loc.argtypes = [ctypes.POINTER(SystemDesc), I32, I32, I32, I32,
+                                                 ctypes.POINTER(BatchedSketchLoc)]
     lib.csk_solve_batched.restype = I32
     lib.csk_solve_batched.argtypes = [ctypes.POINTER(SystemDesc), I32, I32, I32,
                                       ctypes.POINTER(SolveOpts), P, P, SZ, P]

@@ -25,8 +25,8 @@ from ._abi import (CSK_BF16, CSK_CANCELLED, CSK_ERR_DEGENERATE, CSK_ERR_DEVICE, 
 _lib = _abi.load()
 
 __all__ = ["CskError", "SketchOut", "SolveResult", "csk_hash", "csk_sketch", "csk_sketch_csr",
-           "csk_solve", "csk_solve_batched", "csk_solve_mrhs", "csk_tune_solve", "csk_tune_lookup",
-           "csk_tune_clear", "csk_status_string", "lib"]
+           "csk_solve", "csk_solve_batched", "csk_solve_batched_sketches", "csk_solve_mrhs", "csk_tune_solve",
+           "csk_tune_lookup", "csk_tune_clear", "csk_status_string", "lib"]
 
 lib = _lib
 
@@ -248,9 +248,11 @@ def csk_solve_csr(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, n
                   stop_mode: Optional[int] = None, cancel: Optional[int] = None, check_every: int = 256,
                   grid: int = 0, single_wg: int = -1, out: Optional[torch.Tensor] = None,
                   result: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
-                  sync: bool = True, stream=None):
+                  trace_idx: Optional[torch.Tensor] = None, sync: bool = True, stream=None):
     """MWRK (Algorithm 1, loop) on a CSR At (int64 row_ptr, int32 col, float64 val), FP64.
 
+    trace_idx: optional int64 device tensor of at least maxit entries that
+    receives the row projected at each iteration.
     Returns a SolveResult when sync=True, else (x, raw_result_tensor)."""
     for t, nm in ((row_ptr, "row_ptr"), (col, "col"), (val, "val"), (bt, "bt")):
         _need_cuda(t, nm)
@@ -269,7 +271,7 @@ def csk_solve_csr(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, n
         nbytes = ctypes.c_size_t(0)
         _check(_lib.csk_solve_csr_workspace_size(d, n, nnz, ctypes.byref(nbytes)), "csk_solve_csr_workspace_size")
         workspace = _workspace(nbytes.value, dev)
-    o = _opts(tol, maxit, stop_mode, 0, x_ref, cancel, check_every, grid, single_wg)
+    o = _opts(tol, maxit, stop_mode, 0, x_ref, cancel, check_every, grid, single_wg, trace_idx)
     _check(_lib.csk_solve_csr(_ptr(row_ptr), _ptr(col), _ptr(val), d, n, nnz, _ptr(bt), _ptr(nu2), _ptr(x0),
                               _ptr(x), ctypes.byref(o), _ptr(res), _ptr(workspace), workspace.numel(),
                               _stream(stream)), "csk_solve_csr")
@@ -309,7 +311,11 @@ def parse_results(raw: torch.Tensor) -> List[tuple]:
     return out
 
 
-def _opts(tol, maxit, stop_mode, refresh_every, x_ref, cancel, check_every, grid, single_wg):
+def _opts(tol, maxit, stop_mode, refresh_every, x_ref, cancel, check_every, grid, single_wg, trace_idx=None):
+    if trace_idx is not None:
+        _need_cuda(trace_idx, "trace_idx")
+        if trace_idx.dtype != torch.int64 or not trace_idx.is_contiguous() or trace_idx.numel() < int(maxit):
+            raise ValueError("trace_idx must be a contiguous int64 device tensor of at least maxit entries")
     o = _abi.SolveOpts()
     o.tol = float(tol)
     o.maxit = int(maxit)
@@ -321,6 +327,7 @@ def _opts(tol, maxit, stop_mode, refresh_every, x_ref, cancel, check_every, grid
     o.grid = int(grid)
     o.block = 0
     o.single_wg = int(single_wg)
+    o.trace_idx = None if trace_idx is None else trace_idx.data_ptr()
     return o
 
 
@@ -330,10 +337,13 @@ def csk_solve(At: torch.Tensor, bt: torch.Tensor, *, At64: Optional[torch.Tensor
               stop_mode: Optional[int] = None, refresh_every: int = 64, cancel: Optional[int] = None,
               check_every: int = 256, grid: int = 0, single_wg: int = -1,
               out: Optional[torch.Tensor] = None, result: Optional[torch.Tensor] = None,
-              workspace: Optional[torch.Tensor] = None, sync: bool = True, stream=None):
+              workspace: Optional[torch.Tensor] = None, trace_idx: Optional[torch.Tensor] = None,
+              sync: bool = True, stream=None):
     """MWRK on (At, bt) (Algorithm 1, loop).
 
     At: d x n float64 (plain) or float32/float16/bfloat16 (mixed, At64 required).
+    trace_idx: optional int64 device tensor of at least maxit entries that
+    receives the row projected at each iteration.
     Returns a SolveResult when sync=True, else (x, raw_result_tensor)."""
     _need_cuda(At, "At")
     ldat = _rowmajor(At, "At")
@@ -351,7 +361,7 @@ def csk_solve(At: torch.Tensor, bt: torch.Tensor, *, At64: Optional[torch.Tensor
         nbytes = ctypes.c_size_t(0)
         _check(_lib.csk_solve_workspace_size(d, n, at_code, ctypes.byref(nbytes)), "csk_solve_workspace_size")
         workspace = _workspace(nbytes.value, dev)
-    o = _opts(tol, maxit, stop_mode, refresh_every, x_ref, cancel, check_every, grid, single_wg)
+    o = _opts(tol, maxit, stop_mode, refresh_every, x_ref, cancel, check_every, grid, single_wg, trace_idx)
     _check(_lib.csk_solve(_ptr(At), at_code, ldat, _ptr(At64), ldat64, d, n, _ptr(bt), _ptr(nu2), _ptr(x0),
                           _ptr(x), ctypes.byref(o), _ptr(res), _ptr(workspace), workspace.numel(),
                           _stream(stream)), "csk_solve")
@@ -363,7 +373,7 @@ def csk_solve(At: torch.Tensor, bt: torch.Tensor, *, At64: Optional[torch.Tensor
 
 
 def _solve_fp64_select(name, At, bt, extra, nu2, x0, x_ref, tol, maxit, stop_mode, cancel, check_every, grid,
-                       single_wg, out, result, workspace, sync, stream):
+                       single_wg, out, result, workspace, sync, stream, trace_idx=None):
     _need_cuda(At, "At")
     if At.dtype != torch.float64:
         raise ValueError("the randomized selection rules run on the FP64 sketch")
@@ -376,7 +386,7 @@ def _solve_fp64_select(name, At, bt, extra, nu2, x0, x_ref, tol, maxit, stop_mod
         nbytes = ctypes.c_size_t(0)
         _check(getattr(_lib, name + "_workspace_size")(d, n, ctypes.byref(nbytes)), name + "_workspace_size")
         workspace = _workspace(nbytes.value, dev)
-    o = _opts(tol, maxit, stop_mode, 0, x_ref, cancel, check_every, grid, single_wg)
+    o = _opts(tol, maxit, stop_mode, 0, x_ref, cancel, check_every, grid, single_wg, trace_idx)
     _check(getattr(_lib, name)(_ptr(At), ldat, d, n, _ptr(bt), _ptr(nu2), _ptr(x0), _ptr(x), *extra,
                                ctypes.byref(o), _ptr(res), _ptr(workspace), workspace.numel(), _stream(stream)),
            name)
@@ -393,7 +403,7 @@ def csk_solve_rgrk(At: torch.Tensor, bt: torch.Tensor, *, theta: float = 0.5, se
                    stop_mode: Optional[int] = None, cancel: Optional[int] = None, check_every: int = 256,
                    grid: int = 0, single_wg: int = -1, out: Optional[torch.Tensor] = None,
                    result: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
-                   sync: bool = True, stream=None):
+                   trace_idx: Optional[torch.Tensor] = None, sync: bool = True, stream=None):
     """The loop on the FP64 (At, bt) with the relaxed greedy randomized rule
     (theta = 1/2: greedy randomized Kaczmarz; theta = 1: the greedy rule).
 
@@ -402,19 +412,21 @@ def csk_solve_rgrk(At: torch.Tensor, bt: torch.Tensor, *, theta: float = 0.5, se
         stop_mode = CSK_STOP_REL_ERR if x_ref is not None else CSK_STOP_REL_RESID
     return _solve_fp64_select("csk_solve_rgrk", At, bt, (float(theta), int(sel_seed) & (2**64 - 1)), nu2, x0,
                               x_ref, tol, maxit, stop_mode, cancel, check_every, grid, single_wg, out, result,
-                              workspace, sync, stream)
+                              workspace, sync, stream, trace_idx)
 
 
 def csk_solve_rk(At: torch.Tensor, bt: torch.Tensor, *, x_ref: torch.Tensor, sel_seed: int = 0,
                  nu2: Optional[torch.Tensor] = None, x0: Optional[torch.Tensor] = None, tol: float = 1e-10,
                  maxit: int = 1000000, cancel: Optional[int] = None, check_every: int = 256,
                  out: Optional[torch.Tensor] = None, result: Optional[torch.Tensor] = None,
-                 workspace: Optional[torch.Tensor] = None, sync: bool = True, stream=None):
+                 workspace: Optional[torch.Tensor] = None, trace_idx: Optional[torch.Tensor] = None,
+                 sync: bool = True, stream=None):
     """Randomized Kaczmarz on the FP64 (At, bt), stopped on the relative
     error against x_ref.  Returns a SolveResult when sync=True, else
     (x, raw_result_tensor)."""
     return _solve_fp64_select("csk_solve_rk", At, bt, (int(sel_seed) & (2**64 - 1),), nu2, x0, x_ref, tol, maxit,
-                              CSK_STOP_REL_ERR, cancel, check_every, 0, -1, out, result, workspace, sync, stream)
+                              CSK_STOP_REL_ERR, cancel, check_every, 0, -1, out, result, workspace, sync, stream,
+                              trace_idx)
 
 
 class Pipeline:
@@ -474,7 +486,7 @@ def csk_pipeline_capture(A: torch.Tensor, b: torch.Tensor, d: int, seed: int, *,
     a_code = _TORCH_TO_CSK[A.dtype]
     lp_code = _TORCH_TO_CSK[lp_dtype] if lp_dtype is not None else CSK_F64
     nb = ctypes.c_size_t(0)
-    _check(_lib.csk_sketch_workspace_size(m, n, d, a_code, ctypes.byref(nb)), "csk_sketch_workspace_size")
+    _check(_lib.csk_sketch_workspace_size(m, n, d, 1, ctypes.byref(nb)), "csk_sketch_workspace_size")
     ws_sk = _workspace(nb.value, dev)
     _check(_lib.csk_solve_workspace_size(d, n, lp_code, ctypes.byref(nb)), "csk_solve_workspace_size")
     ws_so = _workspace(nb.value, dev)
@@ -538,6 +550,40 @@ def csk_solve_batched(systems: Sequence[dict], *, lp_dtype: torch.dtype = torch.
         return xs, res, ws
     (stream or torch.cuda.current_stream()).synchronize()
     return xs, parse_results(res)
+
+
+def csk_solve_batched_sketches(systems: Sequence[dict], ws: torch.Tensor, *,
+                               lp_dtype: torch.dtype = torch.float32) -> List[SketchOut]:
+    """Views of the per-system sketches csk_solve_batched wrote into its
+    workspace `ws` (the third value it returns with sync=False): At64 and
+    At_lp as d x n views of their padded rows, bt and nu2.  Valid once the
+    call's work has finished and while ws is alive."""
+    nsys = len(systems)
+    a_dtype = systems[0]["A"].dtype
+    descs = (_abi.SystemDesc * nsys)()
+    for k, sysd in enumerate(systems):
+        m, n = sysd["A"].shape
+        dsc = descs[k]
+        dsc.m, dsc.n, dsc.lda, dsc.d = m, n, _rowmajor(sysd["A"], "A"), int(sysd["d"])
+        dsc.A = dsc.b = dsc.x = 1  # sizes only: the layout query reads no buffer
+    out = []
+    for k, sysd in enumerate(systems):
+        loc = _abi.BatchedSketchLoc()
+        _check(_lib.csk_solve_batched_sketch_loc(descs, nsys, _TORCH_TO_CSK[a_dtype], _TORCH_TO_CSK[lp_dtype], k,
+                                                 ctypes.byref(loc)), "csk_solve_batched_sketch_loc")
+        d, n = int(sysd["d"]), sysd["A"].shape[1]
+
+        def view(off, dtype, count):
+            es = torch.tensor([], dtype=dtype).element_size()
+            return ws[off:off + count * es].view(dtype)
+
+        at64 = view(loc.at64, torch.float64, d * loc.ld64).view(d, loc.ld64)[:, :n]
+        at_lp = None
+        if loc.at_lp >= 0:
+            at_lp = view(loc.at_lp, lp_dtype, d * loc.ld_lp).view(d, loc.ld_lp)[:, :n]
+        out.append(SketchOut(at64, at_lp, view(loc.bt, torch.float64, d), view(loc.nu2, torch.float64, d), None,
+                             None))
+    return out
 
 
 def csk_solve_mrhs(At_lp: torch.Tensor, At64: torch.Tensor, Bt: torch.Tensor, nu2: torch.Tensor, *,

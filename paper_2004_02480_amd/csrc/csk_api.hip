@@ -216,7 +216,7 @@ const char* csk_status_string(csk_status s)
 
 const char* csk_last_error(void) { return g_err; }
 
-int32_t csk_version(void) { return 10000; }
+int32_t csk_version(void) { return 10100; }
 
 csk_status csk_hash(uint64_t seed, int64_t m, int64_t d, uint32_t* bucket, int8_t* sign, void* stream)
 {
@@ -764,6 +764,25 @@ csk_status csk_solve_batched_workspace_size(const csk_system_desc* sys, int32_t 
     c.take<int32_t>(nsys);
     c.take<char>(kBatchExchRecords * solve_exch_record_bytes());
     *bytes = c.bytes();
+    return CSK_OK;
+}
+
+csk_status csk_solve_batched_sketch_loc(const csk_system_desc* sys, int32_t nsys, csk_dtype a_dtype,
+                                        csk_dtype lp_dtype, int32_t s, csk_batched_sketch_loc* out)
+{
+    g_err[0] = 0;
+    if (!out) { set_error("out is NULL"); return CSK_ERR_INVALID_ARG; }
+    csk_status st = check_batch(sys, nsys, a_dtype, lp_dtype);
+    if (st != CSK_OK) return st;
+    if (s < 0 || s >= nsys) { set_error("system %d outside [0, %d)", s, nsys); return CSK_ERR_INVALID_ARG; }
+    // the per-system data block is the workspace's first piece (offset 0)
+    const BatchLayout L = batch_layout(sys, nsys, lp_dtype);
+    out->at64 = L.off_64[s];
+    out->at_lp = L.off_lp[s];
+    out->bt = L.off_bt[s];
+    out->nu2 = L.off_nu2[s];
+    out->ld64 = L.ld_64[s];
+    out->ld_lp = L.ld_lp[s];
     return CSK_OK;
 }
 

@@ -75,6 +75,7 @@ struct Ctl {
     int32_t rres;          // relaxed greedy randomized rule: LDS residuals per workgroup
     double theta;          // ... its relaxation parameter
     uint64_t sel_seed;     // ... and the seed of its selection stream
+    int64_t* trace;        // nullable: row projected at each iteration
 };
 
 // Element access.  A chunk slot holds one 16-byte vector per k (VW elements)
@@ -691,6 +692,7 @@ __device__ __forceinline__ void solve_loop(const SolveSys& S, const Ctl& C, XRec
         }
 
         // Projection onto row i_k, on this workgroup's copy of x.
+        if (C.trace && wg == 0 && tid == 0) C.trace[k] = pick;
         const double* __restrict__ arow = S.At64 + (int64_t)pick * S.ldat64;
         if (std::is_same<Tag, tag_f16>::value && refresh) {
             // ||alpha a|| = |r| / ||a|| = sqrt(score), identical in every workgroup
@@ -1024,6 +1026,7 @@ Ctl make_ctl(const csk_solve_opts* o)
     C.cancel = o->cancel;
     C.refresh_every = o->refresh_every > 0 ? o->refresh_every : 64;
     C.check_every = o->check_every > 0 ? o->check_every : 256;
+    C.trace = o->trace_idx;
     return C;
 }
 
@@ -1259,6 +1262,7 @@ csk_status solve_batched_run(const SolveSys* sys_dev, int32_t nsys, const Batche
                              const csk_solve_opts* o, hipStream_t st)
 {
     Ctl C = make_ctl(o);
+    C.trace = nullptr;  // one trace cannot describe many systems
     C.queue = bp.queue_dev;
     C.order = bp.order_dev;
     C.nsys = nsys;

@@ -47,6 +47,7 @@ struct CsrCtl {
     int32_t res_cap;       // stored entries kept in LDS per workgroup
     int32_t row_weight;    // split weight of a row, in stored entries
     int32_t pad_;
+    int64_t* trace;        // nullable: row projected at each iteration
 };
 
 // LDS carve: x, the slice of x_ref, resident values (16-byte aligned), row
@@ -302,6 +303,7 @@ __global__ __launch_bounds__(kNT) void k_solve_csr(CsrSolveSys S, CsrCtl C)
         // projection onto row i_k: its stored columns are distinct, so each
         // thread updates its own entries of x
         const double alpha = tot.r;
+        if (C.trace && wg == 0 && tid == 0) C.trace[k] = tot.idx;
         const int64_t a0 = S.rp[tot.idx], a1 = S.rp[tot.idx + 1];
         for (int64_t p = a0 + tid; p < a1; p += kNT) {
             const int c = S.col[p];
@@ -420,6 +422,7 @@ csk_status csr_solve_run(const CsrSolveSys& sys_in, const csk_solve_opts* o, voi
     C.maxit = o->maxit;
     C.cancel = o->cancel;
     C.check_every = o->check_every > 0 ? o->check_every : 256;
+    C.trace = o->trace_idx;
     C.exch = c.take<XRec>(2 * (size_t)grid);
     double* nu2_ws = c.take<double>(S.d);
     if (c.bytes() > ws_bytes) {

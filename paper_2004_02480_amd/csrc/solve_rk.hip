@@ -50,6 +50,7 @@ struct RkArgs {
     int64_t maxit;
     uint64_t seed;
     double tol2;
+    int64_t* trace;  // nullable: row projected at each iteration
     int32_t d, n;
     int32_t check_every;
 };
@@ -215,7 +216,8 @@ __global__ __launch_bounds__(NT) void k_solve_rk(RkArgs P)
     double xref2 = 0.0;
     for (int w = 0; w < NW; ++w) xref2 += red[1][w][0];
 
-    auto load_row = [&](int i, double (&v)[J], double& bi, double& ni) {
+    auto load_row = [&](int i, double (&v)[J], double& bi, double& ni, int& ii) {
+        ii = i;
         const double* __restrict__ row = P.At + (int64_t)i * P.ldat;
         for (int j = 0; j < J; ++j) {
             const int c = tid + j * NT;
@@ -227,12 +229,14 @@ __global__ __launch_bounds__(NT) void k_solve_rk(RkArgs P)
     // ring slot u holds the row of every iteration k with k % AH == u
     constexpr int AH = rk_ahead<J>();
     double ring[AH][J], rb[AH], rn[AH];
+    int ri[AH];  // the row index of each slot
 #pragma unroll
     for (int u = 0; u < AH; ++u) {
-        if (u <= P.maxit) load_row(pick[0][u], ring[u], rb[u], rn[u]);
+        if (u <= P.maxit) load_row(pick[0][u], ring[u], rb[u], rn[u], ri[u]);
         else {
             for (int j = 0; j < J; ++j) ring[u][j] = 0.0;
             rb[u] = rn[u] = 0.0;
+            ri[u] = 0;
         }
     }
 
@@ -249,9 +253,10 @@ __global__ __launch_bounds__(NT) void k_solve_rk(RkArgs P)
             double a[J];
             for (int j = 0; j < J; ++j) a[j] = ring[u][j];
             const double bi = rb[u], ni = rn[u];
+            const int row = ri[u];
             // the row of iteration k + AH into the freed slot
             const int64_t kn = k + AH;
-            if (kn <= P.maxit) load_row(pick[(kn / kRkBatch) & 1][kn % kRkBatch], ring[u], rb[u], rn[u]);
+            if (kn <= P.maxit) load_row(pick[(kn / kRkBatch) & 1][kn % kRkBatch], ring[u], rb[u], rn[u], ri[u]);
             double pd = 0.0, pe = 0.0;
             for (int j = 0; j < J; ++j) {
                 pd += a[j] * x[j];
@@ -281,6 +286,7 @@ __global__ __launch_bounds__(NT) void k_solve_rk(RkArgs P)
             const double r = bi - dot;
             if (!isfinite(r)) { status = CSK_ERR_NONFINITE; done = true; break; }
             const double alpha = r / ni;
+            if (P.trace && tid == 0) P.trace[k] = row;
             for (int j = 0; j < J; ++j) x[j] = x[j] + alpha * a[j];
             ++k;
         }
@@ -339,6 +345,7 @@ csk_status solve_rk_run(const double* At, int64_t ldat, int64_t d, int64_t n, co
     P.maxit = o->maxit;
     P.seed = sel_seed;
     P.tol2 = o->tol * o->tol;
+    P.trace = o->trace_idx;
     P.d = (int32_t)d;
     P.n = (int32_t)n;
     P.check_every = o->check_every > 0 ? o->check_every : 256;

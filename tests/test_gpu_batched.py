@@ -1,7 +1,9 @@
 """GPU parity of the batched form: many independent systems, each sketched
-with its own seed and solved by its own MWRK loop, in one pass.  Every
-system's sketch is bit-exact with the oracle's; every solution meets the
-tolerance against x* and agrees with the oracle's solution."""
+with its own seed and solved by its own MWRK loop, in one pass.  The
+sketches the batched call builds for its solves (read from its workspace)
+are bit-exact with the oracle's, zero padding included; every solution meets
+the tolerance against x* and lies within twice it of the oracle's FP64
+solution."""
 import math
 
 import numpy as np
@@ -39,6 +41,38 @@ def test_batched_small_matches_oracle(gpu, orc, a_dtype, lp):
                     maxit=400000)
         assert o.status == 0
         assert np.linalg.norm(xg - o.x) <= 2e-8 * np.linalg.norm(xr), k
+
+
+@pytest.mark.parametrize("a_dtype,lp", [(torch.float32, torch.bfloat16), (torch.float64, torch.float64),
+                                        (torch.float32, torch.float16), (torch.float32, torch.float32)])
+def test_batched_sketch_bitexact(gpu, orc, a_dtype, lp):
+    # uneven systems, some with d > m / 10 and odd n (ragged rows padded with
+    # zeros to the library's row length), sketched together in one pipeline:
+    # every system's At64, its low-precision copy and bt equal the oracle's
+    shapes, _ = W.batched_shapes(20, base_seed=300, sketch_base=400, m_range=(1000, 30000), n_range=(20, 300))
+    systems = make_batch(shapes, a_dtype)
+    xs, raw, ws = gpu.csk_solve_batched(systems, lp_dtype=lp, tol=1e-8, maxit=5, sync=False)
+    torch.cuda.synchronize()
+    views = gpu.csk_solve_batched_sketches(systems, ws, lp_dtype=lp)
+    for k, (sysd, v) in enumerate(zip(systems, views)):
+        At, bt = orc.sketch_dense(sysd["A"].cpu().numpy(), sysd["b"].cpu().numpy(), sysd["d"], sysd["seed"])
+        np.testing.assert_array_equal(v.At64.cpu().numpy(), At, err_msg=f"system {k}")
+        np.testing.assert_array_equal(v.bt.cpu().numpy(), bt, err_msg=f"system {k}")
+        np.testing.assert_allclose(v.nu2.cpu().numpy(), orc.row_norms2(At), rtol=1e-13, atol=0)
+        n = sysd["A"].shape[1]
+        full64 = v.At64.as_strided((v.At64.shape[0], v.At64.stride(0)), (v.At64.stride(0), 1))
+        assert torch.count_nonzero(full64[:, n:]).item() == 0, k
+        if v.At_lp is not None:
+            if lp == torch.float32:
+                np.testing.assert_array_equal(v.At_lp.cpu().numpy().view(np.uint32),
+                                              orc.round_f64_to_f32(At).view(np.uint32), err_msg=f"system {k}")
+            else:
+                bits = v.At_lp.contiguous().view(torch.int16).cpu().numpy().view(np.uint16)
+                want = orc.round_f64_to_bf16_bits(At) if lp == torch.bfloat16 else orc.round_f64_to_f16_bits(At)
+                np.testing.assert_array_equal(bits, want, err_msg=f"system {k}")
+            fl = v.At_lp.as_strided((v.At_lp.shape[0], v.At_lp.stride(0)), (v.At_lp.stride(0), 1))
+            assert torch.count_nonzero(fl[:, n:]).item() == 0, k
+    del ws
 
 
 def test_batched_single_system_equals_plain_path(gpu):

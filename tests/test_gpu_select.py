@@ -6,12 +6,15 @@ Both sides draw the same uniforms (the selection stream of the seed), so the
 rows drawn are the same as long as no draw sits within rounding of a
 boundary: the relaxed greedy rule's keys and working-set test read residuals
 summed in another order than the oracle's, and randomized Kaczmarz's
-cumulative norms start from squared norms summed in another order.  Iterates
-after K steps are compared to ~1e-12, converged solutions against x*."""
+cumulative norms start from squared norms summed in another order.  The rows
+drawn in iterations 0..K-1 are compared bit for bit with the oracle's, the
+iterate after K steps element by element to 1e-12 of its norm, converged
+solutions against x* and the oracle's."""
 import numpy as np
 import pytest
 import torch
 
+from _compare import assert_iterate_close, assert_trace_equal, new_trace
 from paper_2004_02480_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -36,11 +39,13 @@ def _setup(gpu, orc, m, n, d, seed, sketch_seed):
 def test_rgrk_iterates_match_oracle(gpu, orc, theta, path, K):
     s, sk, At, bt = _setup(gpu, orc, 20000, 150, 1900, 61, 62)
     kw = dict(single_wg=1) if path == "single" else dict(single_wg=0, grid=24)
+    tr = new_trace(K)
     r = gpu.csk_solve_rgrk(sk.At64, sk.bt, theta=theta, sel_seed=77, nu2=sk.nu2, x_ref=s.x_star, tol=0.0,
-                           maxit=K, **kw)
+                           maxit=K, trace_idx=tr, **kw)
     assert r.status == gpu.CSK_NOT_CONVERGED and r.iters == K
-    o = orc.rgrk(At, bt, theta=theta, sel_seed=77, xref=s.x_star.cpu().numpy(), tol=0.0, maxit=K)
-    assert np.linalg.norm(r.x.cpu().numpy() - o.x) <= 1e-12 * np.linalg.norm(o.x)
+    o = orc.rgrk(At, bt, theta=theta, sel_seed=77, xref=s.x_star.cpu().numpy(), tol=0.0, maxit=K, trace=True)
+    assert_trace_equal(tr, o.idx)
+    assert_iterate_close(r.x, o.x)
 
 
 @pytest.mark.parametrize("path", ["single", "grid"])
@@ -73,9 +78,13 @@ def test_rgrk_converges_and_matches_oracle(gpu, orc, theta):
 def test_rgrk_grid_shape_and_residual_mode(gpu, orc):
     s, sk, At, bt = _setup(gpu, orc, 30000, 200, 2500, 67, 68)
     xs = s.x_star.cpu().numpy()
-    xa = gpu.csk_solve_rgrk(sk.At64, sk.bt, sel_seed=3, nu2=sk.nu2, x_ref=s.x_star, tol=0.0, maxit=50, grid=8).x
-    xb = gpu.csk_solve_rgrk(sk.At64, sk.bt, sel_seed=3, nu2=sk.nu2, x_ref=s.x_star, tol=0.0, maxit=50, grid=40).x
-    assert np.linalg.norm((xa - xb).cpu().numpy()) <= 1e-12 * np.linalg.norm(xa.cpu().numpy())
+    ta, tb = new_trace(50), new_trace(50)
+    xa = gpu.csk_solve_rgrk(sk.At64, sk.bt, sel_seed=3, nu2=sk.nu2, x_ref=s.x_star, tol=0.0, maxit=50, grid=8,
+                            trace_idx=ta).x
+    xb = gpu.csk_solve_rgrk(sk.At64, sk.bt, sel_seed=3, nu2=sk.nu2, x_ref=s.x_star, tol=0.0, maxit=50, grid=40,
+                            trace_idx=tb).x
+    assert torch.equal(ta, tb)
+    assert_iterate_close(xa, xb)
     # residual stop, norms computed by the library
     r = gpu.csk_solve_rgrk(sk.At64, sk.bt, sel_seed=3, tol=1e-9, maxit=200000, stop_mode=gpu.CSK_STOP_REL_RESID,
                            single_wg=0)
@@ -97,9 +106,12 @@ def test_rgrk_full_size_first_steps_and_convergence(gpu, orc):
     sk = gpu.csk_sketch(s.A, s.b, c["d"], c["sketch_seed"])
     At, bt = orc.sketch_dense(s.A.cpu().numpy(), s.b.cpu().numpy(), c["d"], c["sketch_seed"])
     xs = s.x_star.cpu().numpy()
-    r = gpu.csk_solve_rgrk(sk.At64, sk.bt, theta=0.5, sel_seed=1, nu2=sk.nu2, x_ref=s.x_star, tol=0.0, maxit=4)
-    o = orc.rgrk(At, bt, theta=0.5, sel_seed=1, xref=xs, tol=0.0, maxit=4)
-    assert np.linalg.norm(r.x.cpu().numpy() - o.x) <= 1e-12 * np.linalg.norm(o.x)
+    tr = new_trace(4)
+    r = gpu.csk_solve_rgrk(sk.At64, sk.bt, theta=0.5, sel_seed=1, nu2=sk.nu2, x_ref=s.x_star, tol=0.0, maxit=4,
+                           trace_idx=tr)
+    o = orc.rgrk(At, bt, theta=0.5, sel_seed=1, xref=xs, tol=0.0, maxit=4, trace=True)
+    assert_trace_equal(tr, o.idx)
+    assert_iterate_close(r.x, o.x)
     r = gpu.csk_solve_rgrk(sk.At64, sk.bt, theta=0.5, sel_seed=1, nu2=sk.nu2, x_ref=s.x_star, tol=c["tol"],
                            maxit=10 * c["maxit"])
     assert r.status == gpu.CSK_OK, r.status_name
@@ -112,10 +124,12 @@ def test_rk_iterates_match_oracle(gpu, orc, n, K):
     # K crosses the 512-iteration draw batches; n = 1100 gives three columns
     # per thread with a ragged tail
     s, sk, At, bt = _setup(gpu, orc, 12 * n + 500, n, 6 * n + 50, 70 + n, 71)
-    r = gpu.csk_solve_rk(sk.At64, sk.bt, sel_seed=8, nu2=sk.nu2, x_ref=s.x_star, tol=0.0, maxit=K)
+    tr = new_trace(K)
+    r = gpu.csk_solve_rk(sk.At64, sk.bt, sel_seed=8, nu2=sk.nu2, x_ref=s.x_star, tol=0.0, maxit=K, trace_idx=tr)
     assert r.status == gpu.CSK_NOT_CONVERGED and r.iters == K
-    o = orc.rk(At, bt, sel_seed=8, xref=s.x_star.cpu().numpy(), tol=0.0, maxit=K)
-    assert np.linalg.norm(r.x.cpu().numpy() - o.x) <= 1e-12 * np.linalg.norm(o.x)
+    o = orc.rk(At, bt, sel_seed=8, xref=s.x_star.cpu().numpy(), tol=0.0, maxit=K, trace=True)
+    assert_trace_equal(tr, o.idx)
+    assert_iterate_close(r.x, o.x)
 
 
 @pytest.mark.parametrize("n", [900, 3000, 8192])
@@ -128,10 +142,12 @@ def test_rk_wide_rows_match_oracle(gpu, orc, n):
     xs = torch.randn(n, dtype=torch.float64, generator=g)
     b = A @ xs
     An, bn, xn = A.numpy(), b.numpy(), xs.numpy()
-    r = gpu.csk_solve_rk(A.to(DEV), b.to(DEV), sel_seed=12, x_ref=xs.to(DEV), tol=0.0, maxit=K)
+    tr = new_trace(K)
+    r = gpu.csk_solve_rk(A.to(DEV), b.to(DEV), sel_seed=12, x_ref=xs.to(DEV), tol=0.0, maxit=K, trace_idx=tr)
     assert r.status == gpu.CSK_NOT_CONVERGED and r.iters == K
-    o = orc.rk(An, bn, sel_seed=12, xref=xn, tol=0.0, maxit=K)
-    assert np.linalg.norm(r.x.cpu().numpy() - o.x) <= 1e-12 * np.linalg.norm(o.x)
+    o = orc.rk(An, bn, sel_seed=12, xref=xn, tol=0.0, maxit=K, trace=True)
+    assert_trace_equal(tr, o.idx)
+    assert_iterate_close(r.x, o.x)
 
 
 def test_rk_converges_with_library_norms_and_x0(gpu, orc):

@@ -26,6 +26,21 @@ def test_hash_bitexact(gpu, orc, m, d, seed):
     np.testing.assert_array_equal(sign.cpu().numpy(), os_)
 
 
+def test_hash_equals_published_splitmix64_outputs(gpu):
+    # the library's hash against the generator's published first outputs
+    # (tests/golden/splitmix64.json), independently of the oracle
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "splitmix64.json")) as f:
+        vecs = json.load(f)["vectors"]
+    for v in vecs:
+        words = [int(h, 16) for h in v["outputs_hex"]] if "outputs_hex" in v else [int(w) for w in v["outputs"]]
+        for d in (2, 20000, 2**31 - 1):
+            bucket, sign = gpu.csk_hash(int(v["seed"]), len(words), d, device=DEV)
+            assert [int(x) for x in bucket.cpu().numpy().view(np.uint32)] == [((w >> 32) * d) >> 32 for w in words]
+            assert [int(x) for x in sign.cpu().numpy()] == [-1 if (w & 1) else 1 for w in words]
+
+
 def _check_sketch(gpu, orc, A, b, d, seed, lp=None):
     out = gpu.csk_sketch(A, b, d, seed, lp_dtype=lp, want_perm=True)
     torch.cuda.synchronize()

@@ -1,17 +1,21 @@
 """GPU parity of the MWRK loop (Algorithm 1, loop; Section 3 stopping rule).
 
 Floating-point residuals are summed in a different order than the oracle's,
-so whole trajectories are compared through their results: the iterate after
-K steps agrees with the oracle's to ~1e-12 while no near-tie intervenes, and
-converged solutions agree with x* (and with the oracle's solution) to the
-requested tolerance.  Status paths, determinism and resume are checked
-directly."""
-import ctypes
+so trajectories are compared step by step while no near-tie intervenes: the
+rows selected in iterations 0..K-1 equal the oracle's bit for bit, and the
+iterate after K steps agrees with the oracle's element by element to 1e-12 of
+its norm.  Converged solutions agree with x* to the requested tolerance and
+with the oracle's converged solution to twice it.  The mixed-precision loop
+starts with an exact FP64 refresh, so its first step equals the oracle's
+FP64 step; its converged solution is held to the same bounds.  Status paths,
+determinism and resume are checked directly."""
+import os
 
 import numpy as np
 import pytest
 import torch
 
+from _compare import assert_iterate_close, assert_trace_equal, new_trace
 from paper_2004_02480_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -52,11 +56,13 @@ def test_iterates_match_oracle_step_by_step(gpu, orc, path, K):
     s = W.gaussian(12000, 90, seed=21, device=DEV)
     sk = sketched(gpu, s, 1100, 22)
     kw = dict(single_wg=1) if path == "single" else dict(single_wg=0, grid=16)
-    r = gpu.csk_solve(sk.At64, sk.bt, nu2=sk.nu2, x_ref=s.x_star, tol=0.0, maxit=K, **kw)
+    tr = new_trace(K)
+    r = gpu.csk_solve(sk.At64, sk.bt, nu2=sk.nu2, x_ref=s.x_star, tol=0.0, maxit=K, trace_idx=tr, **kw)
     assert r.status == gpu.CSK_NOT_CONVERGED and r.iters == K
     At, bt = orc.sketch_dense(s.A.cpu().numpy(), s.b.cpu().numpy(), 1100, 22)
-    o = orc.mwrk(At, bt, xref=s.x_star.cpu().numpy(), tol=0.0, maxit=K)
-    assert np.linalg.norm(r.x.cpu().numpy() - o.x) <= 1e-12 * np.linalg.norm(o.x)
+    o = orc.mwrk(At, bt, xref=s.x_star.cpu().numpy(), tol=0.0, maxit=K, trace=True)
+    assert_trace_equal(tr, o.idx)
+    assert_iterate_close(r.x, o.x)
 
 
 @pytest.mark.parametrize("path,m,n,d,grid", [("single", 8000, 60, 1500, 1), ("grid", 60000, 90, 9000, 8),
@@ -70,10 +76,12 @@ def test_alternating_walk_iterates_match_oracle(gpu, orc, path, m, n, d, grid):
     kw = dict(single_wg=1) if path == "single" else dict(single_wg=0, grid=grid)
     At, bt = orc.sketch_dense(s.A.cpu().numpy(), s.b.cpu().numpy(), d, 5)
     for K in (1, 2, 25):
-        r = gpu.csk_solve(sk.At64, sk.bt, nu2=sk.nu2, x_ref=s.x_star, tol=0.0, maxit=K, **kw)
+        tr = new_trace(K)
+        r = gpu.csk_solve(sk.At64, sk.bt, nu2=sk.nu2, x_ref=s.x_star, tol=0.0, maxit=K, trace_idx=tr, **kw)
         assert r.status == gpu.CSK_NOT_CONVERGED and r.iters == K
-        o = orc.mwrk(At, bt, xref=s.x_star.cpu().numpy(), tol=0.0, maxit=K)
-        assert np.linalg.norm(r.x.cpu().numpy() - o.x) <= 1e-12 * np.linalg.norm(o.x), (path, K)
+        o = orc.mwrk(At, bt, xref=s.x_star.cpu().numpy(), tol=0.0, maxit=K, trace=True)
+        assert_trace_equal(tr, o.idx, f"{path} K={K}")
+        assert_iterate_close(r.x, o.x, what=f"{path} K={K}")
 
 
 def test_full_size_dense_coherent(gpu, orc):
@@ -82,14 +90,50 @@ def test_full_size_dense_coherent(gpu, orc):
     c = W.config("dense_coherent")
     s = W.uniform01(c["m"], c["n"], c["seed"], device=DEV)
     sk = sketched(gpu, s, c["d"], c["sketch_seed"])
-    r3 = gpu.csk_solve(sk.At64, sk.bt, nu2=sk.nu2, x_ref=s.x_star, tol=0.0, maxit=3)
+    tr = new_trace(3)
+    r3 = gpu.csk_solve(sk.At64, sk.bt, nu2=sk.nu2, x_ref=s.x_star, tol=0.0, maxit=3, trace_idx=tr)
     At, bt = orc.sketch_dense(s.A.cpu().numpy(), s.b.cpu().numpy(), c["d"], c["sketch_seed"])
-    o3 = orc.mwrk(At, bt, xref=s.x_star.cpu().numpy(), tol=0.0, maxit=3)
-    assert np.linalg.norm(r3.x.cpu().numpy() - o3.x) <= 1e-12 * np.linalg.norm(o3.x)
+    o3 = orc.mwrk(At, bt, xref=s.x_star.cpu().numpy(), tol=0.0, maxit=3, trace=True)
+    assert_trace_equal(tr, o3.idx)
+    assert_iterate_close(r3.x, o3.x)
     r = gpu.csk_solve(sk.At64, sk.bt, nu2=sk.nu2, x_ref=s.x_star, tol=c["tol"], maxit=c["maxit"])
     assert r.status == gpu.CSK_OK, r.status_name
     assert relerr(r.x, s.x_star) <= 1e-10
     print(f"dense_coherent iterations {r.iters}")
+
+
+def oracle_threads():
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+@pytest.mark.parametrize("path", ["single", "grid"])
+@pytest.mark.parametrize("n", [200, 203])  # whole 16-byte vectors, and a masked tail
+@pytest.mark.parametrize("lp", [torch.bfloat16, torch.float16, torch.float32])
+def test_mixed_precision_matches_oracle(gpu, orc, lp, n, path):
+    # the mixed loop's iteration 0 is an exact FP64 refresh: the same row and
+    # the same step as the oracle's FP64 loop; the converged solution lies
+    # within twice the tolerance of the oracle's FP64 solution
+    s = W.row_scaled(60000, n, seed=31, device=DEV)
+    sk = sketched(gpu, s, 2000, 32, lp=lp)
+    kw = dict(single_wg=1) if path == "single" else dict(single_wg=0, grid=16)
+    At, bt = orc.sketch_dense(s.A.cpu().numpy(), s.b.cpu().numpy(), 2000, 32)
+    xs = s.x_star.cpu().numpy()
+    tr = new_trace(1)
+    r1 = gpu.csk_solve(sk.At_lp, sk.bt, At64=sk.At64, nu2=sk.nu2, x_ref=s.x_star, tol=0.0, maxit=1, trace_idx=tr,
+                       **kw)
+    o1 = orc.mwrk(At, bt, xref=xs, tol=0.0, maxit=1, trace=True)
+    assert r1.iters == 1 and r1.refreshes == 1
+    assert_trace_equal(tr, o1.idx)
+    assert_iterate_close(r1.x, o1.x)
+    tol = 1e-10
+    r = gpu.csk_solve(sk.At_lp, sk.bt, At64=sk.At64, nu2=sk.nu2, x_ref=s.x_star, tol=tol, maxit=200000, **kw)
+    o = orc.mwrk(At, bt, xref=xs, tol=tol, maxit=200000)
+    assert r.status == gpu.CSK_OK and o.status == orc.OK, (r.status_name, o.status)
+    assert relerr(r.x, xs) <= tol
+    assert np.linalg.norm(r.x.cpu().numpy() - o.x) <= 2 * tol * np.linalg.norm(xs)
+    assert r.iters <= 1.5 * o.iters + 64, (r.iters, o.iters)
+    print(f"mixed {lp} n={n} {path}: iterations {r.iters} (oracle FP64 {o.iters}), "
+          f"|x - x_oracle|/|x*| = {np.linalg.norm(r.x.cpu().numpy() - o.x) / np.linalg.norm(xs):.2e}")
 
 
 @pytest.mark.parametrize("n", [200, 203])  # whole 16-byte vectors, and a masked tail
@@ -177,17 +221,46 @@ def test_nu2_computed_when_absent(gpu):
     assert relerr(b.x, s.x_star) <= 1e-10
 
 
-@pytest.mark.parametrize("lp", [torch.bfloat16, torch.float16])
-def test_mixed_full_size_row_scaled(gpu, lp):
+_ROW_SCALED = {}
+
+
+def row_scaled_oracle(orc, s, c):
+    """The oracle's sketch, first step and converged FP64 solution of the
+    full row-scaled workload (computed once per session, on the host cores;
+    bitwise the single-thread oracle)."""
+    if not _ROW_SCALED:
+        xs = s.x_star.cpu().numpy()
+        with orc.threads(oracle_threads()):
+            At, bt = orc.sketch_dense(s.A.cpu().numpy(), s.b.cpu().numpy(), c["d"], c["sketch_seed"])
+            o1 = orc.mwrk(At, bt, xref=xs, tol=0.0, maxit=1, trace=True)
+            o = orc.mwrk(At, bt, xref=xs, tol=c["tol"], maxit=c["maxit"])
+        _ROW_SCALED.update(o1=o1, o=o)
+    return _ROW_SCALED["o1"], _ROW_SCALED["o"]
+
+
+@pytest.mark.parametrize("lp", [torch.bfloat16, torch.float16, torch.float32])
+def test_mixed_full_size_row_scaled(gpu, orc, lp):
     # rows scaled over four decades: the FP16 operand copy of x - x_ref is
-    # rescaled at every refresh; both 16-bit formats reach 1e-10 without the
-    # FP64 fallback, in about the FP64 loop's iteration count
+    # rescaled at every refresh; every low-precision format reaches 1e-10
+    # without the FP64 fallback, in about the FP64 loop's iteration count;
+    # the first step equals the oracle's and the solution lies within twice
+    # the tolerance of the oracle's FP64 solution
     c = W.config("row_scaled")
     s = W.row_scaled(c["m"], c["n"], c["seed"], device=DEV)
     sk = sketched(gpu, s, c["d"], c["sketch_seed"], lp=lp)
-    r = gpu.csk_solve(sk.At_lp, sk.bt, At64=sk.At64, nu2=sk.nu2, x_ref=s.x_star, tol=1e-10, maxit=c["maxit"])
+    o1, o = row_scaled_oracle(orc, s, c)
+    tr = new_trace(1)
+    r1 = gpu.csk_solve(sk.At_lp, sk.bt, At64=sk.At64, nu2=sk.nu2, x_ref=s.x_star, tol=0.0, maxit=1, trace_idx=tr)
+    assert_trace_equal(tr, o1.idx)
+    assert_iterate_close(r1.x, o1.x)
+    r = gpu.csk_solve(sk.At_lp, sk.bt, At64=sk.At64, nu2=sk.nu2, x_ref=s.x_star, tol=c["tol"], maxit=c["maxit"])
     assert r.status == gpu.CSK_OK, r.status_name
-    assert relerr(r.x, s.x_star) <= 1e-10
+    assert relerr(r.x, s.x_star) <= c["tol"]
     assert r.fp64_fallback == 0
     assert r.iters <= 6400, r.iters
-    print(f"row_scaled {lp} iterations {r.iters} refreshes {r.refreshes} fallback {r.fp64_fallback}")
+    xs = s.x_star.cpu().numpy()
+    assert o.status == orc.OK
+    dif = np.linalg.norm(r.x.cpu().numpy() - o.x) / np.linalg.norm(xs)
+    assert dif <= 2 * c["tol"]
+    print(f"row_scaled {lp} iterations {r.iters} (oracle FP64 {o.iters}) refreshes {r.refreshes} "
+          f"fallback {r.fp64_fallback} |x - x_oracle|/|x*| = {dif:.2e}")

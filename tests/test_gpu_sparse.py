@@ -4,12 +4,15 @@
 The sparse sketch must hold, bit for bit, the oracle's dense sketch (scattered
 into a dense array), with each row's pattern the union of the stored columns
 of its bucket's rows.  The loop's residuals are summed over the stored entries
-in another order than the oracle's dense sums, so iterates are compared after
-K steps to ~1e-12 and converged solutions against x* and the oracle."""
+in another order than the oracle's dense sums, so the rows selected in
+iterations 0..K-1 are compared bit for bit with the oracle's, the iterate
+after K steps element by element to 1e-12 of its norm, and converged
+solutions against x* and the oracle."""
 import numpy as np
 import pytest
 import torch
 
+from _compare import assert_iterate_close, assert_trace_equal, new_trace
 from paper_2004_02480_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -95,10 +98,13 @@ def test_sparse_iterates_match_oracle(gpu, orc, path, K):
     s, sk, At, bt = _system(orc, gpu, 30000, 400, 0.01, 3000, 41)
     xs = torch.from_numpy(s.x_star).to(DEV)
     kw = dict(single_wg=1) if path == "single" else dict(single_wg=0, grid=24)
-    r = gpu.csk_solve_csr(sk.row_ptr, sk.col, sk.val, s.n, sk.bt, nu2=sk.nu2, x_ref=xs, tol=0.0, maxit=K, **kw)
+    tr = new_trace(K)
+    r = gpu.csk_solve_csr(sk.row_ptr, sk.col, sk.val, s.n, sk.bt, nu2=sk.nu2, x_ref=xs, tol=0.0, maxit=K,
+                          trace_idx=tr, **kw)
     assert r.status == gpu.CSK_NOT_CONVERGED and r.iters == K
-    o = orc.mwrk(At, bt, xref=s.x_star, tol=0.0, maxit=K)
-    assert np.linalg.norm(r.x.cpu().numpy() - o.x) <= 1e-12 * np.linalg.norm(o.x)
+    o = orc.mwrk(At, bt, xref=s.x_star, tol=0.0, maxit=K, trace=True)
+    assert_trace_equal(tr, o.idx)
+    assert_iterate_close(r.x, o.x)
 
 
 @pytest.mark.parametrize("path", ["single", "grid"])
@@ -126,10 +132,12 @@ def test_sparse_residual_mode_norms_computed_and_x0(gpu, orc):
     x = r.x.cpu().numpy()
     assert np.linalg.norm(bt - At @ x) <= 1e-9 * np.linalg.norm(bt) * (1 + 1e-6)
     # first steps from x0, with the norms computed by the library, agree with the oracle's
+    tr = new_trace(5)
     r1 = gpu.csk_solve_csr(sk.row_ptr, sk.col, sk.val, s.n, sk.bt, x0=x0, tol=0.0, maxit=5,
-                           stop_mode=gpu.CSK_STOP_REL_RESID, single_wg=0)
-    o = orc.mwrk(At, bt, x0=x0.cpu().numpy(), tol=0.0, maxit=5, stop_mode=orc.STOP_REL_RESID)
-    assert np.linalg.norm(r1.x.cpu().numpy() - o.x) <= 1e-12 * np.linalg.norm(o.x)
+                           stop_mode=gpu.CSK_STOP_REL_RESID, single_wg=0, trace_idx=tr)
+    o = orc.mwrk(At, bt, x0=x0.cpu().numpy(), tol=0.0, maxit=5, stop_mode=orc.STOP_REL_RESID, trace=True)
+    assert_trace_equal(tr, o.idx)
+    assert_iterate_close(r1.x, o.x)
 
 
 def test_sparse_status_paths(gpu):
