@@ -235,6 +235,33 @@ csk_status csk_solve(const void* At, csk_dtype at_dtype, int64_t ldat,
                      const csk_solve_opts* opts /*host*/, csk_solve_result* res,
                      void* ws, size_t ws_bytes, void* stream);
 
+/* ---- csk_solve without a workspace: for callers that cannot allocate ---- *
+ * For code that must not call hipMalloc (work recorded under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * solve as csk_solve, same arguments and results, bitwise the same x and
+ * result for the same inputs and launch shape, but its workspace (exchange
+ * records, the FP64 refresh residual, norms computed when nu2 is NULL) comes
+ * from a static device array of CSK_NOALLOC_SCRATCH_BYTES inside the library.
+ * The library makes no allocation of any kind on this path.
+ * Limit: the workspace csk_solve would need, 16 bytes per row plus 128 bytes
+ * per workgroup of the launch, must fit the scratch (d up to about 520000
+ * rows); a larger solve returns CSK_ERR_WORKSPACE before anything is
+ * enqueued (csk_last_error names the sizes).
+ * Each device holds its own copy of the array from the library's load until
+ * the process ends; every call on a device shares that copy, and each call
+ * clears what it needs cleared, so calls in sequence (on one stream, or
+ * ordered by events) are independent.  Calls that may overlap on one device
+ * (two streams, or two threads, without ordering) race on the scratch and
+ * give undefined results: order them, or use csk_solve with separate
+ * workspaces.                                                                */
+#define CSK_NOALLOC_SCRATCH_BYTES (8u << 20)
+csk_status csk_solve_noalloc(const void* At, csk_dtype at_dtype, int64_t ldat,
+                             const double* At64, int64_t ldat64,
+                             int64_t d, int64_t n, const double* bt, const double* nu2,
+                             const double* x0, double* x,
+                             const csk_solve_opts* opts /*host*/, csk_solve_result* res,
+                             void* stream);
+
 /* ---- Randomized selection rules on the FP64 sketch --------------------- *
  * The introduction places Algorithm 1's loop in a family of row-selection
  * rules and Section 3 compares it with two of them; these calls run the loop

@@ -35,7 +35,7 @@ EXPORTED = [
     "csk_sketch_workspace_size", "csk_sketch",
     "csk_sketch_csr_workspace_size", "csk_sketch_csr",
     "csk_sketch_csr_sparse_workspace_size", "csk_sketch_csr_sparse",
-    "csk_solve_workspace_size", "csk_solve",
+    "csk_solve_workspace_size", "csk_solve", "csk_solve_noalloc",
     "csk_solve_csr_workspace_size", "csk_solve_csr",
     "csk_solve_rgrk_workspace_size", "csk_solve_rgrk",
     "csk_solve_rk_workspace_size", "csk_solve_rk",
@@ -94,6 +94,9 @@ class TuneEntry(ctypes.Structure):
         ("us_per_iter", ctypes.c_double),
     ]
 
+
+# the static scratch of csk_solve_noalloc (CSK_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 8 << 20
 
 # csk_solve_result: int64 iters; int32 status; int32 fp64_fallback;
 # double final_measure; int64 refreshes  -> 32 bytes
@@ -164,6 +167,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.csk_solve.restype = I32
     lib.csk_solve.argtypes = [P, I32, I64, P, I64, I64, I64, P, P, P, P,
                               ctypes.POINTER(SolveOpts), P, P, SZ, P]
+    lib.csk_solve_noalloc.restype = I32
+    lib.csk_solve_noalloc.argtypes = [P, I32, I64, P, I64, I64, I64, P, P, P, P,
+                                      ctypes.POINTER(SolveOpts), P, P]
     lib.csk_solve_batched_workspace_size.restype = I32
     lib.csk_solve_batched_workspace_size.argtypes = [ctypes.POINTER(SystemDesc), I32, I32, I32, PSZ]
     lib.csk_solve_batched_sketch_loc.restype = I32

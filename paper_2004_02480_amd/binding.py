@@ -25,7 +25,7 @@ from ._abi import (CSK_BF16, CSK_CANCELLED, CSK_ERR_DEGENERATE, CSK_ERR_DEVICE, 
 _lib = _abi.load()
 
 __all__ = ["CskError", "SketchOut", "SolveResult", "csk_hash", "csk_sketch", "csk_sketch_csr",
-           "csk_solve", "csk_solve_batched", "csk_solve_batched_sketches", "csk_solve_mrhs", "csk_tune_solve",
+           "csk_solve", "csk_solve_noalloc", "csk_solve_batched", "csk_solve_batched_sketches", "csk_solve_mrhs", "csk_tune_solve",
            "csk_tune_lookup", "csk_tune_clear", "csk_status_string", "lib"]
 
 lib = _lib
@@ -370,6 +370,31 @@ def csk_solve(At: torch.Tensor, bt: torch.Tensor, *, At64: Optional[torch.Tensor
     (stream or torch.cuda.current_stream()).synchronize()
     it, st, fb, meas, nref = parse_results(res)[0]
     return SolveResult(x, it, st, fb, meas, nref)
+
+
+def csk_solve_noalloc(At: torch.Tensor, bt: torch.Tensor, *, At64: Optional[torch.Tensor] = None,
+                      nu2: Optional[torch.Tensor] = None, x0: Optional[torch.Tensor] = None,
+                      x_ref: Optional[torch.Tensor] = None, tol: float = 1e-10, maxit: int = 100000,
+                      stop_mode: Optional[int] = None, refresh_every: int = 64, cancel: Optional[int] = None,
+                      check_every: int = 256, grid: int = 0, single_wg: int = -1,
+                      out: torch.Tensor, result: torch.Tensor, trace_idx: Optional[torch.Tensor] = None,
+                      stream=None):
+    """csk_solve with its workspace taken from the library's static scratch:
+    the caller passes the output x and the raw result buffer, and nothing is
+    allocated (no workspace argument).  Returns (x, raw_result_tensor)
+    without synchronizing."""
+    _need_cuda(At, "At")
+    ldat = _rowmajor(At, "At")
+    d, n = At.shape
+    at_code = _TORCH_TO_CSK[At.dtype]
+    ldat64 = _rowmajor(At64, "At64") if At64 is not None else ldat
+    if stop_mode is None:
+        stop_mode = CSK_STOP_REL_ERR if x_ref is not None else CSK_STOP_REL_RESID
+    o = _opts(tol, maxit, stop_mode, refresh_every, x_ref, cancel, check_every, grid, single_wg, trace_idx)
+    _check(_lib.csk_solve_noalloc(_ptr(At), at_code, ldat, _ptr(At64), ldat64, d, n, _ptr(bt), _ptr(nu2),
+                                  _ptr(x0), _ptr(out), ctypes.byref(o), _ptr(result), _stream(stream)),
+           "csk_solve_noalloc")
+    return out, result
 
 
 def _solve_fp64_select(name, At, bt, extra, nu2, x0, x_ref, tol, maxit, stop_mode, cancel, check_every, grid,

@@ -405,9 +405,15 @@ csk_status csk_solve_workspace_size(int64_t d, int64_t n, csk_dtype at_dtype, si
     return CSK_OK;
 }
 
-csk_status csk_solve(const void* At, csk_dtype at_dtype, int64_t ldat, const double* At64, int64_t ldat64,
-                     int64_t d, int64_t n, const double* bt, const double* nu2, const double* x0, double* x,
-                     const csk_solve_opts* opts, csk_solve_result* res, void* ws, size_t ws_bytes, void* stream)
+namespace {
+
+// Argument checks and launch of csk_solve and csk_solve_noalloc.  `ws` is
+// the caller's workspace, or with from_scratch the library's static one
+// (then ws_bytes is its size and a shortfall reports the scratch limit).
+csk_status solve_entry(const void* At, csk_dtype at_dtype, int64_t ldat, const double* At64, int64_t ldat64,
+                       int64_t d, int64_t n, const double* bt, const double* nu2, const double* x0, double* x,
+                       const csk_solve_opts* opts, csk_solve_result* res, void* ws, size_t ws_bytes, void* stream,
+                       bool from_scratch)
 {
     g_err[0] = 0;
     csk_status st = check_opts(opts);
@@ -431,10 +437,17 @@ csk_status csk_solve(const void* At, csk_dtype at_dtype, int64_t ldat, const dou
         set_error("CSK_STOP_REL_ERR needs opts->x_ref");
         return CSK_ERR_INVALID_ARG;
     }
-    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u)) { set_error("workspace NULL or unaligned"); return CSK_ERR_INVALID_ARG; }
     const SolvePlan plan = solve_plan(d, n, at_dtype, ldat, At, opts);
-    if (ws_bytes < solve_ws_bytes(d, n, plan.grid)) {
-        set_error("workspace: need %zu bytes, got %zu", solve_ws_bytes(d, n, plan.grid), ws_bytes);
+    const size_t need = solve_ws_bytes(d, n, plan.grid);
+    if (from_scratch && need > ws_bytes) {
+        set_error("csk_solve_noalloc: this solve needs %zu bytes of scratch, the library's static scratch holds %zu "
+                  "(d = %lld too large; use csk_solve with a workspace)",
+                  need, ws_bytes, (long long)d);
+        return CSK_ERR_WORKSPACE;
+    }
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u)) { set_error("workspace NULL or unaligned"); return CSK_ERR_INVALID_ARG; }
+    if (ws_bytes < need) {
+        set_error("workspace: need %zu bytes, got %zu", need, ws_bytes);
         return CSK_ERR_WORKSPACE;
     }
     SolveSys S{};
@@ -443,7 +456,7 @@ csk_status csk_solve(const void* At, csk_dtype at_dtype, int64_t ldat, const dou
     S.bt = bt;
     S.nu2 = nu2;
     S.x0 = x0;
-    S.xref = opts->stop_mode == CSK_STOP_REL_ERR ? opts->x_ref : opts->x_ref;
+    S.xref = opts->x_ref;
     S.x = x;
     S.res = res;
     S.ldat = ldat;
@@ -452,6 +465,66 @@ csk_status csk_solve(const void* At, csk_dtype at_dtype, int64_t ldat, const dou
     S.n = (int32_t)n;
     S.stop_mode = opts->stop_mode;
     return solve_run(S, at_dtype, opts, ws, ws_bytes, as_stream(stream));
+}
+
+}  // namespace
+
+csk_status csk_solve(const void* At, csk_dtype at_dtype, int64_t ldat, const double* At64, int64_t ldat64,
+                     int64_t d, int64_t n, const double* bt, const double* nu2, const double* x0, double* x,
+                     const csk_solve_opts* opts, csk_solve_result* res, void* ws, size_t ws_bytes, void* stream)
+{
+    return solve_entry(At, at_dtype, ldat, At64, ldat64, d, n, bt, nu2, x0, x, opts, res, ws, ws_bytes, stream,
+                       false);
+}
+
+// ---- csk_solve without a workspace argument ---------------------------------
+// The solve's workspace (exchange records, r_ref, computed norms) comes from
+// one static device array.  In host code `scratch` names a host-side stand-in,
+// not device memory: only the address hipGetSymbolAddress returns for the
+// current device is ever passed to a kernel.  Each device holds its own copy
+// of the array until the process ends; calls on one device share it.
+
+static __device__ __align__(256) unsigned char scratch[CSK_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// The current device's copy of `scratch`, looked up once per device.
+csk_status scratch_of_current_device(void** out)
+{
+    int dev = 0;
+    const hipError_t ge = hipGetDevice(&dev);
+    if (ge != hipSuccess) return hip_fail(ge, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxScratchDevices) {
+        set_error("csk_solve_noalloc: device %d beyond the %d the library tracks", dev, kMaxScratchDevices);
+        return CSK_ERR_UNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return CSK_OK;
+}
+
+}  // namespace
+
+csk_status csk_solve_noalloc(const void* At, csk_dtype at_dtype, int64_t ldat, const double* At64, int64_t ldat64,
+                             int64_t d, int64_t n, const double* bt, const double* nu2, const double* x0, double* x,
+                             const csk_solve_opts* opts, csk_solve_result* res, void* stream)
+{
+    g_err[0] = 0;
+    void* ws = nullptr;
+    const csk_status e = scratch_of_current_device(&ws);
+    if (e != CSK_OK) return e;
+    return solve_entry(At, at_dtype, ldat, At64, ldat64, d, n, bt, nu2, x0, x, opts, res, ws,
+                       (size_t)CSK_NOALLOC_SCRATCH_BYTES, stream, true);
 }
 
 // ---- Algorithm 1 as one HIP graph -------------------------------------------
