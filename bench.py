@@ -10,6 +10,13 @@ kernel (the solve), the sketch bandwidth, the mixed-precision, batched and
 sparse-input measurements, and the CPU oracle timed on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
+
+The CPU-baseline leg (skipped with --no-cpu-baseline or --quick) times the
+oracle on the host: a single-thread bounded sample of the headline workload
+(extrapolated), the full headline run on all of the process's cores (the
+reported cpu_baseline), and the oracle's solution of every other workload
+(full runs, or the first 200 iterations where a full run would take
+minutes), against which each GPU result's error is reported.
 """
 import argparse
 import json
@@ -158,31 +165,182 @@ def main_workload(args, P, W, torch):
                sketch_gbs=sketch_bytes / sketch_s / 1e9, iter_bytes=iter_bytes,
                solve_gbs=it * iter_bytes / solve_s / 1e9, us_per_iter=solve_s / max(it, 1) * 1e6,
                sketch_bytes=sketch_bytes, m=m, n=n, d=d)
+    out["x"] = x.cpu().numpy()
     del sk
     return out, s, c
 
 
-def cpu_baseline(s, c, iters_gpu, budget_iters=2000):
-    """The oracle as it stands (single thread) on the same workload: the full
-    sketch, then `budget_iters` MWRK iterations, extrapolated to the GPU's
-    iteration count."""
+def oracle_small_workload(P, W, torch, reps=20):
+    """The oracle-size system (A 2000 x 50 N(0,1), d = 500, tol 1e-10): sketch
+    and single-workgroup solve, microseconds per iteration (latency-bound:
+    everything sits in one CU's LDS)."""
+    c = W.config("oracle_small")
+    dev = "cuda:0"
+    s = W.gaussian(c["m"], c["n"], c["seed"], device=dev)
+    sk = P.csk_sketch(s.A, s.b, c["d"], c["sketch_seed"])
+    solve = lambda: P.csk_solve(sk.At64, sk.bt, nu2=sk.nu2, x_ref=s.x_star, tol=c["tol"], maxit=c["maxit"],
+                                sync=False)
+    solve()
+    t_sv, (x, raw) = timed(solve, reps)
+    t_sk, _ = timed(lambda: P.csk_sketch(s.A, s.b, c["d"], c["sketch_seed"]), reps)
+    it, st = P.parse_results(raw)[0][:2]
+    rel = ((x - s.x_star).norm() / s.x_star.norm()).item()
+    log(f"[bench] oracle_small: sketch {t_sk * 1e6:.1f} us, solve {t_sv * 1e6:.1f} us, {it} iterations "
+        f"({t_sv / max(it, 1) * 1e6:.2f} us each), rel {rel:.2e} {P.csk_status_string(st)}")
+    return dict(sketch_s=t_sk, solve_s=t_sv, iters=it, us_per_iter=t_sv / max(it, 1) * 1e6, relerr=rel,
+                status=P.csk_status_string(st), x=x.cpu().numpy())
+
+
+def host_cpu():
+    """(CPU model, logical CPUs of the machine, CPUs this process may use)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return model, os.cpu_count() or 1, usable
+
+
+def cpu_baseline_leg(main_res, s_main, c_main, extra, W, torch, budget_iters=2000, max_threads=16):
+    """The CPU oracle on the host (test infrastructure, timed as it stands).
+
+    * single thread: the headline workload's full sketch plus `budget_iters`
+      MWRK iterations, extrapolated to the GPU's iteration count;
+    * all usable cores (at most `max_threads`): the headline workload run in
+      full (the reported value), and its first `budget_iters` iterations
+      checked bitwise against the single-thread run (the threaded loops keep
+      every sum's order);
+    * the oracle's solution of every other workload measured here, against
+      which the GPU result's relative difference ||x_gpu - x_oracle|| /
+      ||x*|| is reported: full runs for the oracle-size, headline and
+      row-scaled (FP64 oracle vs every stored precision) workloads, the first
+      32 of the 512 batched systems and the first 8 of the 256 right-hand
+      sides; for the 1e6 x 5000 CSR workload the full sketch and the first
+      200 iterations (vs the GPU's iterate after 200), its full time
+      extrapolated and labelled so."""
     import numpy as np
     import oracle
-    A = s.A.cpu().numpy()
-    b = s.b.cpu().numpy()
-    xs = s.x_star.cpu().numpy()
+    model, ncpu, usable = host_cpu()
+    T = max(1, min(usable, max_threads))
+    parity = {}
+    rel = lambda x, xo, xs: float(np.linalg.norm(x - xo) / np.linalg.norm(xs))
+
+    # headline: single-thread sample, then the full run on T threads
+    A = s_main.A.cpu().numpy()
+    b = s_main.b.cpu().numpy()
+    xs = s_main.x_star.cpu().numpy()
+    d, tol, maxit = c_main["d"], c_main["tol"], c_main["maxit"]
+    oracle.set_threads(1)
     t0 = time.perf_counter()
-    At, bt = oracle.sketch_dense(A, b, c["d"], c["sketch_seed"])
+    At, bt = oracle.sketch_dense(A, b, d, c_main["sketch_seed"])
     t1 = time.perf_counter()
-    oracle.mwrk(At, bt, xref=xs, tol=0.0, maxit=budget_iters)
+    o1 = oracle.mwrk(At, bt, xref=xs, tol=0.0, maxit=budget_iters)
     t2 = time.perf_counter()
-    per_iter = (t2 - t1) / budget_iters
-    est = (t1 - t0) + per_iter * iters_gpu
+    per_iter1 = (t2 - t1) / budget_iters
+    single = dict(value=(t1 - t0) + per_iter1 * main_res["iters"], unit="s", cores=1, extrapolated=True,
+                  sample=f"full sketch ({t1 - t0:.2f} s) + {budget_iters} of {main_res['iters']} MWRK iterations "
+                         f"({per_iter1 * 1e3:.2f} ms each), extrapolated to the GPU's iteration count")
+    log(f"[bench] oracle 1 thread: {single['sample']} -> {single['value']:.1f} s")
+    with oracle.threads(T):
+        t3 = time.perf_counter()
+        At, bt = oracle.sketch_dense(A, b, d, c_main["sketch_seed"])
+        t4 = time.perf_counter()
+        of = oracle.mwrk(At, bt, xref=xs, tol=tol, maxit=maxit)
+        t5 = time.perf_counter()
+        oT = oracle.mwrk(At, bt, xref=xs, tol=0.0, maxit=budget_iters)
+    same = bool(np.array_equal(o1.x.view(np.uint64), oT.x.view(np.uint64)))
+    parity["dense_coherent"] = dict(rel_diff=rel(main_res["x"], of.x, xs), oracle_iters=of.iters,
+                                    gpu_iters=main_res["iters"], oracle_status=of.status)
+    log(f"[bench] oracle {T} threads: full dense_coherent {t5 - t3:.2f} s (sketch {t4 - t3:.2f} s, "
+        f"{of.iters} iterations), first {budget_iters} iterations bitwise equal to 1 thread: {same}; "
+        f"GPU vs oracle {parity['dense_coherent']['rel_diff']:.2e}")
+    mA, nA = A.shape
     del A, At
-    np.asarray(0)
-    return dict(value=est, unit="s", cores=1, kind="oracle",
-                sample=f"full sketch ({t1 - t0:.2f} s) + {budget_iters} of {iters_gpu} MWRK iterations "
-                       f"({per_iter * 1e3:.1f} ms each), extrapolated to the GPU's iteration count")
+    cpu = dict(value=t5 - t3, unit="s", cores=T, kind="oracle",
+               sample=f"the full dense_coherent run (A {mA}x{nA}, sketch {t4 - t3:.2f} s + {of.iters} MWRK "
+                      f"iterations) on {T} threads",
+               cpu_model=model, nproc=ncpu, usable_cpus=usable, single_thread=single,
+               threads_bitwise_identical=same)
+
+    with oracle.threads(T):
+        if "oracle_small" in extra:
+            c = W.config("oracle_small")
+            s = W.gaussian(c["m"], c["n"], c["seed"], device="cuda:0")
+            t0 = time.perf_counter()
+            o = oracle.csk(s.A.cpu().numpy(), s.b.cpu().numpy(), c["d"], c["sketch_seed"],
+                           xref=s.x_star.cpu().numpy(), tol=c["tol"], maxit=c["maxit"])
+            parity["oracle_small"] = dict(rel_diff=rel(extra["oracle_small"]["x"], o.x, s.x_star.cpu().numpy()),
+                                          oracle_iters=o.iters, gpu_iters=extra["oracle_small"]["iters"],
+                                          oracle_s=time.perf_counter() - t0)
+        if "row_scaled_mixed" in extra:
+            c = W.config("row_scaled")
+            s = W.row_scaled(c["m"], c["n"], c["seed"], device="cuda:0")
+            xs = s.x_star.cpu().numpy()
+            t0 = time.perf_counter()
+            o = oracle.csk(s.A.cpu().numpy(), s.b.cpu().numpy(), c["d"], c["sketch_seed"], xref=xs, tol=c["tol"],
+                           maxit=c["maxit"])
+            t1 = time.perf_counter()
+            del s
+            mx = extra["row_scaled_mixed"]
+            parity["row_scaled"] = dict(oracle_iters=o.iters, oracle_s=t1 - t0, **{
+                f"{k}_rel_diff": rel(mx[k]["x"], o.x, xs) for k in ("f64", "bf16", "f16", "f32") if k in mx})
+        if "sparse_csr" in extra and "x_iter200" in extra["sparse_csr"]:
+            c = W.config("sparse_csr")
+            sp = W.sparse_csr(c["m"], c["n"], c["density"], c["seed"])
+            t0 = time.perf_counter()
+            At, bt = oracle.sketch_csr(sp.row_ptr, sp.col, sp.val, c["m"], c["n"], sp.b, c["d"], c["sketch_seed"])
+            t1 = time.perf_counter()
+            o = oracle.mwrk(At, bt, xref=sp.x_star, tol=0.0, maxit=CSR_ORACLE_ITERS)
+            t2 = time.perf_counter()
+            del At
+            its = extra["sparse_csr"].get("sparse_iters", CSR_ORACLE_ITERS)
+            parity["sparse_csr"] = dict(
+                iters_compared=CSR_ORACLE_ITERS,
+                rel_diff_after_200=rel(extra["sparse_csr"]["x_iter200"], o.x, sp.x_star),
+                oracle_s_extrapolated=(t1 - t0) + (t2 - t1) / CSR_ORACLE_ITERS * its,
+                oracle_sample=f"full sketch ({t1 - t0:.2f} s) + {CSR_ORACLE_ITERS} iterations on the dense FP64 "
+                              f"sketch ({(t2 - t1) / CSR_ORACLE_ITERS * 1e3:.1f} ms each) on {T} threads, "
+                              f"extrapolated to {its} iterations")
+        if "batched_512" in extra:
+            c = W.config("batched")
+            shapes, _ = W.batched_shapes(c["nsys"], c["seed"], c["sketch_seed"])
+            worst = {}
+            t0 = time.perf_counter()
+            for j, sh in enumerate(shapes[:BATCH_ORACLE_SYSTEMS]):
+                s = W.gaussian(sh.m, sh.n, sh.seed, dtype=torch.float32, device="cuda:0")
+                xs = s.x_star.cpu().numpy()
+                o = oracle.csk(s.A.cpu().numpy(), s.b.cpu().numpy(), sh.d, sh.sketch_seed, xref=xs, tol=c["tol"],
+                               maxit=c["maxit"])
+                for k in ("f64", "f32", "bf16"):
+                    if k in extra["batched_512"]:
+                        worst[k] = max(worst.get(k, 0.0), rel(extra["batched_512"][k]["x_first"][j], o.x, xs))
+            parity["batched_512"] = dict(systems_compared=BATCH_ORACLE_SYSTEMS, oracle_s=time.perf_counter() - t0,
+                                         **{f"{k}_worst_rel_diff": v for k, v in worst.items()})
+        if "multi_rhs_256" in extra:
+            c = W.config("multi_rhs")
+            s = W.multi_rhs(c["m"], c["n"], c["nrhs"], c["seed"], device="cuda:0")
+            Bk = s.B[:, :MRHS_ORACLE_COLUMNS].cpu().numpy()
+            Xs = s.X_star[:, :MRHS_ORACLE_COLUMNS].cpu().numpy()
+            t0 = time.perf_counter()
+            At, Bt = oracle.sketch_dense(s.A.cpu().numpy(), Bk, c["d"], c["sketch_seed"])
+            del s
+            w = 0.0
+            for j in range(MRHS_ORACLE_COLUMNS):
+                o = oracle.mwrk(At, Bt[:, j], xref=Xs[:, j], tol=c["tol"], maxit=c["maxit"])
+                w = max(w, rel(extra["multi_rhs_256"]["X_first"][:, j], o.x, Xs[:, j]))
+            parity["multi_rhs_256"] = dict(columns_compared=MRHS_ORACLE_COLUMNS, worst_rel_diff=w,
+                                           oracle_s=time.perf_counter() - t0)
+    torch.cuda.empty_cache()
+    log(f"[bench] GPU vs oracle: {json.dumps(parity)}")
+    return cpu, parity
 
 
 def mixed_workload(P, W, torch, reps=2):
@@ -207,13 +365,17 @@ def mixed_workload(P, W, torch, reps=2):
         it, st, fb, meas, nref = P.parse_results(raw)[0]
         rel = ((x - s.x_star).norm() / s.x_star.norm()).item()
         out[name] = dict(time_s=t, iters=it, status=P.csk_status_string(st), relerr=rel, refreshes=nref,
-                         fp64_fallback=fb)
+                         fp64_fallback=fb, x=x.cpu().numpy())
         log(f"[bench] row_scaled {name}: {t * 1e3:.2f} ms iters={it} rel={rel:.2e} {P.csk_status_string(st)}")
     for name in ("bf16", "f16", "f32"):
         out[name]["speedup_vs_f64"] = out["f64"]["time_s"] / out[name]["time_s"]
     del s
     torch.cuda.empty_cache()
     return out
+
+
+BATCH_ORACLE_SYSTEMS = 32  # systems whose solution the oracle leg recomputes
+MRHS_ORACLE_COLUMNS = 8    # right-hand sides whose solution the oracle leg recomputes
 
 
 def batched_workload(P, W, torch):
@@ -229,9 +391,9 @@ def batched_workload(P, W, torch):
     torch.cuda.synchronize()
     a_bytes = sum(sh.m * sh.n * 4 for sh in shapes)
     out = dict(systems=len(shapes), a_bytes=a_bytes, redraws=redraws)
-    # the sketch is stored in FP32 and, separately, in BF16 (half the bytes
-    # per inner iteration); both refresh in FP64
-    for name, lp in (("f32", torch.float32), ("bf16", torch.bfloat16)):
+    # the sketch is stored in FP64 (the plain path: FP64 rows in every
+    # iteration), in FP32 and in BF16 (the latter two with an FP64 refresh)
+    for name, lp in (("f64", torch.float64), ("f32", torch.float32), ("bf16", torch.bfloat16)):
         P.csk_solve_batched(systems[:4], lp_dtype=lp, tol=c["tol"], maxit=c["maxit"])
         t, (xs, raw, ws) = timed(lambda: P.csk_solve_batched(systems, lp_dtype=lp, tol=c["tol"],
                                                               maxit=c["maxit"], sync=False))
@@ -241,10 +403,13 @@ def batched_workload(P, W, torch):
         log(f"[bench] batched {name}: {t * 1e3:.1f} ms for {len(shapes)} systems, {ok} converged, "
             f"worst rel {worst:.2e}")
         out[name] = dict(time_s=t, converged=ok, systems_per_s=len(shapes) / t, worst_relerr=worst,
-                         total_iters=int(sum(r[0] for r in res)))
+                         total_iters=int(sum(r[0] for r in res)),
+                         x_first=[x.cpu().numpy() for x in xs[:BATCH_ORACLE_SYSTEMS]])
         del xs, raw, ws
     out["time_s"] = out["f32"]["time_s"]
     out["systems_per_s"] = out["f32"]["systems_per_s"]
+    out["f32_speedup_vs_f64"] = out["f64"]["time_s"] / out["f32"]["time_s"]
+    out["bf16_speedup_vs_f64"] = out["f64"]["time_s"] / out["bf16"]["time_s"]
     out["bf16_speedup_vs_f32"] = out["f32"]["time_s"] / out["bf16"]["time_s"]
     del systems
     torch.cuda.empty_cache()
@@ -274,11 +439,13 @@ def mrhs_workload(P, W, torch):
     flops = 2.0 * c["d"] * c["n"] * c["nrhs"] * its
     log(f"[bench] multi_rhs: sketch {t_sk * 1e3:.2f} ms, solve {t_sv * 1e3:.1f} ms, {its} iterations, "
         f"{ok}/{c['nrhs']} converged, worst rel {err:.2e}, {flops / t_sv / 1e12:.1f} TFLOP/s (BF16 MFMA)")
+    Xk = X[:, :MRHS_ORACLE_COLUMNS].cpu().numpy()
     del s, sk
     torch.cuda.empty_cache()
     return dict(sketch_s=t_sk, solve_s=t_sv, time_s=t_sk + t_sv, iters=its, converged=ok, worst_relerr=err,
                 rhs_per_s=c["nrhs"] / (t_sk + t_sv), mfma_tflops=flops / t_sv / 1e12,
-                mfma_frac_bf16_peak=flops / t_sv / 2.5e15)
+                mfma_frac_bf16_peak=flops / t_sv / 2.5e15, us_per_iter=t_sv / max(its, 1) * 1e6,
+                X_first=Xk)
 
 
 # Section 3, Table 1: the paper's means over 50 trials (MATLAB, unstated
@@ -304,13 +471,13 @@ def graph_of(fn, torch):
     return g, out
 
 
-def table1_workload(P, W, torch, trials=5):
+def table1_workload(P, W, torch, trials=50, graph_trials=5):
     """Section 3's experiment on this GPU: CSK (sketch with d = n^2, then
     MWRK on the sketch) against MWRK on the full (A, b), mean iterations
-    and times over `trials` seeded draws per shape.  Each method is timed
-    twice: as eager library calls, and as one replay of a HIP graph holding
-    the same calls (no launch gaps between the sketch's kernels and the
-    solve)."""
+    and times over `trials` seeded draws per shape (the paper's 50).  Each
+    method is timed as eager library calls, and on the first `graph_trials`
+    draws also as one replay of a HIP graph holding the same calls (no launch
+    gaps between the sketch's kernels and the solve)."""
     c = W.config("table1")
     dev = "cuda:0"
     paper = table1_paper()
@@ -345,6 +512,9 @@ def table1_workload(P, W, torch, trials=5):
                 it_m.append(im)
                 t_c.append(tc)
                 t_m.append(tm)
+                if t >= graph_trials:
+                    del s
+                    continue
                 gc, (_, rgc) = graph_of(csk, torch)
                 gm, (_, rgm) = graph_of(mwrk, torch)
                 gc.replay()
@@ -358,7 +528,9 @@ def table1_workload(P, W, torch, trials=5):
                 del gc, gm, s
             mean = lambda v: sum(v) / len(v)
             pc, pm, pct, pmt = paper[(m, n)]
+            sd = lambda v: (sum((u - mean(v)) ** 2 for u in v) / max(len(v) - 1, 1)) ** 0.5
             row = dict(m=m, n=n, d=d, csk_it=mean(it_c), mwrk_it=mean(it_m), csk_s=mean(t_c), mwrk_s=mean(t_m),
+                       csk_it_sd=sd(it_c), mwrk_it_sd=sd(it_m), csk_it_min=min(it_c), csk_it_max=max(it_c),
                        it_speedup=mean(it_m) / mean(it_c), time_speedup=mean(t_m) / mean(t_c),
                        csk_graph_s=mean(g_c), mwrk_graph_s=mean(g_m), time_speedup_graph=mean(g_m) / mean(g_c),
                        paper_csk_it=pc, paper_mwrk_it=pm, paper_time_speedup=pmt / pct)
@@ -369,7 +541,7 @@ def table1_workload(P, W, torch, trials=5):
                 f"{row['mwrk_graph_s'] * 1e3:.2f} ms, speedup {row['time_speedup_graph']:.1f} "
                 f"(paper: CSK {pc} it, MWRK {pm} it, speedup {pmt / pct:.1f})")
     torch.cuda.empty_cache()
-    return dict(trials=trials, rows=rows)
+    return dict(trials=trials, graph_trials=graph_trials, rows=rows)
 
 
 def figure_workload(P, W, torch, trials=3):
@@ -415,6 +587,9 @@ def figure_workload(P, W, torch, trials=3):
     return out
 
 
+CSR_ORACLE_ITERS = 200  # the oracle leg runs this many iterations of the 1e6 x 5000 CSR workload
+
+
 def csr_workload(P, W, torch, solve=True):
     """CSR A 1e6 x 5000 at 0.1%, d = 50000: the sketch kept sparse and the FP64
     loop on it, beside the dense sketch and its mixed FP32 solve, to 1e-8."""
@@ -445,6 +620,10 @@ def csr_workload(P, W, torch, solve=True):
         out.update(sparse_solve_s=t2, sparse_iters=r.iters, sparse_status=P.csk_status_string(r.status),
                    sparse_relerr=rel, sparse_us_per_iter=us,
                    sparse_entry_gbs=sk.nnz * 12 / (us * 1e-6) / 1e9)
+        # the iterate after the first CSR_ORACLE_ITERS projections, for the oracle leg
+        r200 = P.csk_solve_csr(sk.row_ptr, sk.col, sk.val, c["n"], sk.bt, nu2=sk.nu2, x_ref=xs, tol=0.0,
+                               maxit=CSR_ORACLE_ITERS)
+        out["x_iter200"] = r200.x.cpu().numpy()
         log(f"[bench] sparse_csr sparse solve {t2:.3f} s iters={r.iters} ({us:.2f} us/iter) rel={rel:.2e} "
             f"{P.csk_status_string(r.status)}")
     del sk
@@ -473,18 +652,41 @@ def csr_workload(P, W, torch, solve=True):
 
 
 def memory_rates(torch):
-    """Measured read rates of this GPU's memory system (context for the
-    roofline): a 160 MB buffer read repeatedly (it fits the 256 MB Infinity
-    Cache) and a 2 GB buffer (it does not)."""
-    out = {}
-    for name, nbytes in (("read_160MB", 160 << 20), ("read_2GB", 2 << 30)):
-        t = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda:0").fill_(1.0)
-        t.sum()
-        sec, _ = timed(lambda: t.sum(), 20)
-        out[name + "_gbs"] = nbytes / sec / 1e9
-        del t
+    """Read rates of this GPU's memory system, the ceilings the solve and the
+    sketch are compared against, from the streaming-read kernel of
+    libcsk_membw.so (each workgroup reads its own contiguous block in
+    16-byte vectors, eight loads in flight per lane, as the solve does):
+    a 4 GiB buffer read once per launch (HBM: far beyond the 256 MB Infinity
+    Cache) and a 160 MB buffer (the headline sketch's size, which the
+    Infinity Cache holds) read 20 times per launch, each with one workgroup
+    of 512 threads per CU and with four."""
+    import ctypes
+    from paper_2004_02480_amd import build as B
+    lib = ctypes.CDLL(B.MEMBW_LIB)
+    lib.membw_read.restype = ctypes.c_int
+    lib.membw_read.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                               ctypes.c_void_p]
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    sink = torch.zeros(4 * cus, dtype=torch.int32, device="cuda:0")
+    stream = torch.cuda.current_stream().cuda_stream
+    out = {"cus": cus}
+    for name, nbytes, reps, launches in (("hbm_4GiB", 4 << 30, 1, 10), ("mall_160MB", 160 * 10**6, 20, 5)):
+        buf = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda:0").fill_(1.0)
+        for wpc in (1, 4):
+            grid = wpc * cus
+
+            def run():
+                e = lib.membw_read(buf.data_ptr(), nbytes, reps, grid, sink.data_ptr(), stream)
+                if e != 0:
+                    raise SystemExit(f"membw_read failed: HIP error {e}")
+            run()
+            sec, _ = timed(run, launches)
+            out[f"{name}_{wpc}wg_per_cu_gbs"] = nbytes * reps / sec / 1e9
+        del buf
+    out["hbm_read_peak_gbs"] = max(v for k, v in out.items() if k.startswith("hbm_"))
+    out["mall_read_peak_gbs"] = max(v for k, v in out.items() if k.startswith("mall_"))
     torch.cuda.empty_cache()
-    log(f"[bench] memory read rates: {out}")
+    log(f"[bench] memory read rates (GB/s): {out}")
     return out
 
 
@@ -527,14 +729,14 @@ def main():
     main_res, s, c = main_workload(args, P, W, torch)
     extra = {}
     cpu = None
+    parity = None
     if not args.quick:
-        if not args.no_cpu_baseline:
-            log("[bench] CPU oracle baseline (bounded sample)")
-            cpu = cpu_baseline(s, c, main_res["iters"])
-            log(f"[bench] cpu_baseline ~{cpu['value']:.1f} s ({cpu['sample']})")
+        # the headline inputs stay on the host for the oracle leg
+        s_host = W.DenseSystem(s.A.cpu(), s.x_star.cpu(), s.b.cpu())
         del s
         torch.cuda.empty_cache()
         extras = {
+            "oracle_small": lambda: oracle_small_workload(P, W, torch),
             "row_scaled_mixed": lambda: mixed_workload(P, W, torch),
             "sparse_csr": lambda: csr_workload(P, W, torch),
             "batched_512": lambda: batched_workload(P, W, torch),
@@ -548,9 +750,55 @@ def main():
             if name not in extras:
                 raise SystemExit(f"unknown extra workload {name!r}; choose from {', '.join(extras)}")
             extra[name] = extras[name]()
+        if not args.no_cpu_baseline:
+            log("[bench] CPU oracle leg")
+            cpu, parity = cpu_baseline_leg(main_res, s_host, c, extra, W, torch)
+            log(f"[bench] cpu_baseline {cpu['value']:.2f} s on {cpu['cores']} threads ({cpu['cpu_model']}, "
+                f"nproc {cpu['nproc']}); single thread ~{cpu['single_thread']['value']:.1f} s")
+        del s_host
 
     traffic, note = measured_traffic()
     log(f"[bench] k_solve_grid measured traffic per launch: {traffic} ({note})")
+    solve_s = main_res["solve_s"]
+    roof = {
+        "bound": "hbm",
+        "kernel": "k_solve_grid",
+        "achieved": main_res["solve_gbs"],
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": main_res["solve_gbs"] / HBM_PEAK_GBS,
+        "traffic": traffic,
+        "algorithmic_bytes_per_launch": main_res["iters"] * main_res["iter_bytes"],
+        # where the bytes come from: At (160 MB) fits the 256 MB Infinity
+        # Cache and about a fifth of it stays in LDS for the whole solve
+        "resident": "At 160 MB in the Infinity Cache (MALL), ~20% of it held in LDS",
+    }
+    if traffic is not None:
+        roof["traffic_gbs"] = traffic / solve_s / 1e9
+        roof["traffic_frac"] = roof["traffic_gbs"] / HBM_PEAK_GBS
+    mr = extra.get("memory_rates")
+    if mr:
+        roof["measured_hbm_read_peak_gbs"] = mr["hbm_read_peak_gbs"]
+        roof["measured_mall_read_peak_gbs"] = mr["mall_read_peak_gbs"]
+        roof["frac_of_measured_mall_read"] = main_res["solve_gbs"] / mr["mall_read_peak_gbs"]
+        if traffic is not None:
+            roof["traffic_frac_of_measured_mall_read"] = roof["traffic_gbs"] / mr["mall_read_peak_gbs"]
+    sketch = {"kernel_chain": "k_hash_hist..k_segsum", "time_s": main_res["sketch_s"],
+              "gbs": main_res["sketch_gbs"], "frac": main_res["sketch_gbs"] / HBM_PEAK_GBS,
+              "bytes": main_res["sketch_bytes"]}
+    if mr:
+        sketch["frac_of_measured_hbm_read"] = main_res["sketch_gbs"] / mr["hbm_read_peak_gbs"]
+    if parity is not None:
+        parity["dense_coherent"]["gpu_relerr_vs_x_star"] = main_res["relerr"]
+
+    def strip(o):
+        """Drop the solution vectors kept for the oracle leg from the record."""
+        if isinstance(o, dict):
+            return {k: strip(v) for k, v in o.items() if not hasattr(v, "dtype") and k != "x_first"}
+        if isinstance(o, list):
+            return [strip(v) for v in o]
+        return o
+
     line = {
         "metric": METRIC,
         "value": main_res["total_s"],
@@ -566,23 +814,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": "dense_coherent", "m": main_res["m"], "n": main_res["n"], "d": main_res["d"],
                    "dist": "U[0,1)", "tol": c["tol"], "parallelism": "single-gpu"},
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "k_solve_grid",
-            "achieved": main_res["solve_gbs"],
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": main_res["solve_gbs"] / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "algorithmic_bytes_per_launch": main_res["iters"] * main_res["iter_bytes"],
-        },
-        "sketch": {"kernel_chain": "k_hash_hist..k_segsum", "time_s": main_res["sketch_s"],
-                   "gbs": main_res["sketch_gbs"], "frac": main_res["sketch_gbs"] / HBM_PEAK_GBS,
-                   "bytes": main_res["sketch_bytes"]},
+        "roofline": roof,
+        "sketch": sketch,
         "solve": {"time_s": main_res["solve_s"], "iters": main_res["iters"], "us_per_iter": main_res["us_per_iter"],
                   "bytes_per_iter": main_res["iter_bytes"], "relerr": main_res["relerr"]},
         "cpu_baseline": cpu,
-        "extra": extra,
+        "oracle_parity": parity,
+        "extra": strip(extra),
     }
     print(json.dumps(line), flush=True)
 

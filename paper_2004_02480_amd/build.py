@@ -1,7 +1,9 @@
 """Build libcsk.so (HIP, gfx950) in-tree with hipcc.
 
-Every .hip translation unit under csrc/ is compiled to an object and linked
-into paper_2004_02480_amd/libcsk.so, which the ctypes binding loads.
+The solve path's .hip translation units under csrc/ are compiled to objects
+and linked into paper_2004_02480_amd/libcsk.so, which the ctypes binding
+loads.  csrc/membw.hip (read-bandwidth reference kernels the benchmark
+compares against) is linked on its own into libcsk_membw.so.
 """
 import os
 import subprocess
@@ -14,9 +16,11 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libcsk.so")
+MEMBW_LIB = os.path.join(HERE, "libcsk_membw.so")
 ARCH = os.environ.get("CSK_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["csk_api.hip", "sketch.hip", "solve.hip", "solve_csr.hip", "solve_rk.hip", "mrhs.hip"]
+MEMBW_SOURCES = ["membw.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -44,15 +48,21 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(OBJDIR, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
-    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", LIB + ".tmp", *objs]
+def _link(objs, lib: str, verbose: bool) -> None:
+    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", lib + ".tmp", *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
+    os.replace(lib + ".tmp", lib)
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(OBJDIR, exist_ok=True)
+    srcs = SOURCES + MEMBW_SOURCES
+    with ThreadPoolExecutor(max_workers=min(4, len(srcs))) as ex:
+        objs = dict(zip(srcs, ex.map(lambda s: _compile(s, verbose), srcs)))
+    _link([objs[s] for s in SOURCES], LIB, verbose)
+    _link([objs[s] for s in MEMBW_SOURCES], MEMBW_LIB, verbose)
     return LIB
 
 

@@ -170,9 +170,17 @@ template <class T> __device__ __forceinline__ T coh_load(const T* p)
 // a release/acquire pair would write them back and invalidate them.  Flags
 // start at zero and epochs count up from 1; the spin is bounded (false:
 // timed out).
+// Ordering: the data stores before the barrier are device-coherent relaxed
+// stores, and the flag store is issued only after s_waitcnt 0 has seen each
+// of them acknowledged by the coherent level.  The wait builtin alone is not
+// a compiler barrier, so signal fences on both sides keep the compiler from
+// moving any memory access across it; the workgroup barrier then orders the
+// other waves' acknowledged stores before thread 0's flag store.
 __device__ __forceinline__ bool grid_barrier_flags(uint32_t* flags, int wg, int G, uint32_t epoch, uint32_t* s_ok)
 {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
     __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
     if (threadIdx.x == 0) *s_ok = 1u;
     __syncthreads();
     if (threadIdx.x == 0) coh_store(&flags[wg], epoch);
