@@ -399,7 +399,11 @@ csk_status csk_solve_batched_sketch_loc(const csk_system_desc* sys /*host*/, int
  * solves At X[:, j] = Bt[:, j].  The residuals of all columns are formed
  * together as R = R_ref - At_lp (X - X_ref) with At_lp in BF16 or F16 on the
  * matrix cores (FP32 accumulation) and an exact FP64 refresh
- * R_ref = Bt - At64 X_ref every refresh_every iterations.  Xref (n x nrhs,
+ * R_ref = Bt - At64 X_ref every refresh_every iterations.  For n <= 512,
+ * X - X_ref enters the products as the sum of the projected rows of At_lp
+ * (each step's sum formed in FP32 and rounded to lp_dtype); beyond that, as
+ * X - X_ref rounded to lp_dtype.  Selection, projections and X use the FP64
+ * rows in both cases.  Xref (n x nrhs,
  * leading dimension ldxref) is the reference for CSK_STOP_REL_ERR (per
  * column).  res: nrhs results (device).  Requires n <= 1024.                */
 csk_status csk_solve_mrhs_workspace_size(int64_t d, int64_t n, int64_t nrhs, size_t* bytes /*host*/);

@@ -78,3 +78,21 @@ def test_mrhs_full_size(gpu):
     assert all(r[1] == gpu.CSK_OK for r in res)
     assert err <= 1e-8
     print(f"multi_rhs max iterations {max(r[0] for r in res)}")
+
+
+@pytest.mark.parametrize("lp", [torch.bfloat16, torch.float16])
+def test_mrhs_wide_rows_two_barrier_form(gpu, orc, lp):
+    """Rows longer than 512 columns take the two-barrier form (Delta shared
+    through device memory); same bounds as the register-Delta form."""
+    m, n, nrhs, d = 30000, 700, 9, 3000
+    s, sk = setup(m, n, nrhs, d, seed=17, sketch_seed=18, lp=lp)
+    X, res = gpu.csk_solve_mrhs(sk.At_lp, sk.At64, sk.bt, sk.nu2, Xref=s.X_star, tol=1e-8, maxit=200000)
+    Xs = s.X_star.cpu().numpy()
+    Xg = X.cpu().numpy()
+    At, Bt = orc.sketch_dense(s.A.cpu().numpy(), s.B.cpu().numpy(), d, 18)
+    for j in (0, nrhs - 1):
+        assert res[j][1] == gpu.CSK_OK, (j, res[j])
+        assert np.linalg.norm(Xg[:, j] - Xs[:, j]) <= 1e-8 * np.linalg.norm(Xs[:, j])
+        with orc.threads(8):
+            o = orc.mwrk(At, Bt[:, j], xref=Xs[:, j], tol=1e-8, maxit=200000)
+        assert np.linalg.norm(Xg[:, j] - o.x) <= 2e-8 * np.linalg.norm(Xs[:, j])
