@@ -393,6 +393,56 @@ typedef struct csk_batched_sketch_loc {
 csk_status csk_solve_batched_sketch_loc(const csk_system_desc* sys /*host*/, int32_t nsys, csk_dtype a_dtype,
                                         csk_dtype lp_dtype, int32_t s, csk_batched_sketch_loc* out /*host*/);
 
+/* ---- Tuning of the multi-RHS and batched launches; the tune cache on disk *
+ * csk_tune_report: what a tuner measured.  `choice` is the fastest
+ * candidate and `default_choice` the library's untuned one, in the kernel
+ * family's terms (multi-RHS: 16-row tiles per workgroup; batched: the plan
+ * variant, see csk_tune_batched); `us` and `default_us` their measured times
+ * (multi-RHS: microseconds per iteration; batched: microseconds per call).
+ *
+ * csk_tune_mrhs times trial_iters iterations (no convergence test) of
+ * csk_solve_mrhs on the given system for every row-tile count from the
+ * default (the fewest that keep one workgroup per CU) up to 8, and records
+ * the fastest for (architecture, d, n, nrhs, lp_dtype); later csk_solve_mrhs
+ * calls of that key use it.  Arguments as csk_solve_mrhs; the workspace
+ * (csk_tune_mrhs_workspace_size) holds the trial runs' solutions and
+ * results.  The timing synchronizes the stream.
+ *
+ * csk_tune_batched runs csk_solve_batched on the given systems once per
+ * plan variant -- 0: the default (the split plan of the modelled iteration
+ * counts, longest estimated system first), 1: no system split, 2: splits
+ * priced at half the modelled exchange cost (more splitting), 3: at twice
+ * it (less), 4: the default split with the systems in the given order --
+ * and records the fastest for (architecture, the systems' shapes, a_dtype,
+ * lp_dtype); later csk_solve_batched calls of that key use it.  Each run is
+ * a full solve (the systems' x and res hold the last one's result);
+ * arguments and workspace as csk_solve_batched.
+ *
+ * The cache of all tuners is process-wide.  csk_tune_save writes it to a
+ * text file (architecture-keyed entries, stamped with csk_version());
+ * csk_tune_load merges a file's entries (a file of another library version
+ * is ignored; *entries, nullable, receives the count read, -1 for none).
+ * When the environment variable CSK_TUNE_CACHE names a file, the cache is
+ * read from it on first use and written back after every tuning call.      */
+typedef struct csk_tune_report {
+    int32_t choice, default_choice;
+    double us, default_us;
+    int32_t candidates;
+} csk_tune_report;
+csk_status csk_tune_mrhs_workspace_size(int64_t d, int64_t n, int64_t nrhs, size_t* bytes /*host*/);
+csk_status csk_tune_mrhs(const void* At_lp, csk_dtype lp_dtype, int64_t ldat_lp,
+                         const double* At64, int64_t ldat64, int64_t d, int64_t n,
+                         const double* Bt, int64_t nrhs, int64_t ldbt, const double* nu2,
+                         int32_t trial_iters, csk_tune_report* report /*host, nullable*/,
+                         void* ws, size_t ws_bytes, void* stream);
+csk_status csk_tune_batched(const csk_system_desc* sys /*host*/, int32_t nsys,
+                            csk_dtype a_dtype, csk_dtype lp_dtype,
+                            const csk_solve_opts* opts /*host*/, csk_solve_result* res,
+                            csk_tune_report* report /*host, nullable*/,
+                            void* ws, size_t ws_bytes, void* stream);
+csk_status csk_tune_save(const char* path /*host*/);
+csk_status csk_tune_load(const char* path /*host*/, int32_t* entries /*host, nullable*/);
+
 /* ---- A9: one sketch, many right-hand sides ----------------------------- *
  * Runs the loop of Algorithm 1 independently for each column j of Bt (d x
  * nrhs FP64) on the shared At: X[:, j] (n x nrhs, leading dimension ldx)

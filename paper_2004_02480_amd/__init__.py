@@ -13,6 +13,7 @@ _BINDING_NAMES = {
     "csk_sketch_csr_sparse", "csk_solve", "csk_solve_noalloc", "csk_solve_csr", "csk_solve_rgrk", "csk_solve_rk",
     "csk_pipeline_capture", "Pipeline",
     "csk_solve_batched", "csk_solve_batched_sketches", "csk_solve_mrhs", "csk_tune_solve", "csk_tune_lookup", "csk_tune_clear",
+    "csk_tune_mrhs", "csk_tune_batched", "csk_tune_save", "csk_tune_load",
     "csk_status_string", "parse_results", "lib",
     "CSK_OK", "CSK_NOT_CONVERGED", "CSK_ERR_INVALID_ARG", "CSK_ERR_UNSUPPORTED", "CSK_ERR_DEVICE",
     "CSK_ERR_WORKSPACE", "CSK_ERR_NONFINITE", "CSK_ERR_DEGENERATE", "CSK_CANCELLED",

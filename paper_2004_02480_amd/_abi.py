@@ -43,6 +43,7 @@ EXPORTED = [
     "csk_solve_batched_workspace_size", "csk_solve_batched", "csk_solve_batched_sketch_loc",
     "csk_solve_mrhs_workspace_size", "csk_solve_mrhs",
     "csk_tune_solve_workspace_size", "csk_tune_solve", "csk_tune_lookup", "csk_tune_clear",
+    "csk_tune_mrhs_workspace_size", "csk_tune_mrhs", "csk_tune_batched", "csk_tune_save", "csk_tune_load",
 ]
 
 
@@ -92,6 +93,16 @@ class TuneEntry(ctypes.Structure):
         ("grid", ctypes.c_int32),
         ("lanes_per_row", ctypes.c_int32),
         ("us_per_iter", ctypes.c_double),
+    ]
+
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [
+        ("choice", ctypes.c_int32),
+        ("default_choice", ctypes.c_int32),
+        ("us", ctypes.c_double),
+        ("default_us", ctypes.c_double),
+        ("candidates", ctypes.c_int32),
     ]
 
 
@@ -191,4 +202,16 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.csk_tune_lookup.argtypes = [I64, I64, I32, I32, ctypes.POINTER(TuneEntry)]
     lib.csk_tune_clear.restype = None
     lib.csk_tune_clear.argtypes = []
+    lib.csk_tune_mrhs_workspace_size.restype = I32
+    lib.csk_tune_mrhs_workspace_size.argtypes = [I64, I64, I64, PSZ]
+    lib.csk_tune_mrhs.restype = I32
+    lib.csk_tune_mrhs.argtypes = [P, I32, I64, P, I64, I64, I64, P, I64, I64, P, I32, ctypes.POINTER(TuneReport),
+                                  P, SZ, P]
+    lib.csk_tune_batched.restype = I32
+    lib.csk_tune_batched.argtypes = [ctypes.POINTER(SystemDesc), I32, I32, I32, ctypes.POINTER(SolveOpts), P,
+                                     ctypes.POINTER(TuneReport), P, SZ, P]
+    lib.csk_tune_save.restype = I32
+    lib.csk_tune_save.argtypes = [ctypes.c_char_p]
+    lib.csk_tune_load.restype = I32
+    lib.csk_tune_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(I32)]
     return lib

@@ -11,6 +11,7 @@ Method (Zhang & Li, arXiv 2004.02480, Algorithm 1): sketch ``At = S A``,
 weighted residual Kaczmarz loop on ``(At, bt)``.
 """
 import ctypes
+import os
 from dataclasses import dataclass
 from typing import List, Optional, Sequence
 
@@ -26,6 +27,7 @@ _lib = _abi.load()
 
 __all__ = ["CskError", "SketchOut", "SolveResult", "csk_hash", "csk_sketch", "csk_sketch_csr",
            "csk_solve", "csk_solve_noalloc", "csk_solve_batched", "csk_solve_batched_sketches", "csk_solve_mrhs", "csk_tune_solve",
+           "csk_tune_mrhs", "csk_tune_batched", "csk_tune_save", "csk_tune_load",
            "csk_tune_lookup", "csk_tune_clear", "csk_status_string", "lib"]
 
 lib = _lib
@@ -530,12 +532,8 @@ def csk_pipeline_capture(A: torch.Tensor, b: torch.Tensor, d: int, seed: int, *,
     return Pipeline(h, keep, x, res, SketchOut(At64, At_lp, bt, nu2, None, None))
 
 
-def csk_solve_batched(systems: Sequence[dict], *, lp_dtype: torch.dtype = torch.float32, tol: float = 1e-8,
-                      maxit: int = 200000, refresh_every: int = 64, sync: bool = True, stream=None):
-    """Sketch and solve many independent systems in one pass.
-
-    Each system is a dict with A (m x n, float32 or float64), b (m float64),
-    d, seed and optional x_ref (n float64).  Returns (xs, results)."""
+def _batched_descs(systems: Sequence[dict]):
+    """(descriptor array, outputs x, tensors to keep alive, A's dtype code)."""
     nsys = len(systems)
     a_dtype = systems[0]["A"].dtype
     descs = (_abi.SystemDesc * nsys)()
@@ -560,8 +558,18 @@ def csk_solve_batched(systems: Sequence[dict], *, lp_dtype: torch.dtype = torch.
         dsc.x = x.data_ptr()
         dsc.m, dsc.n, dsc.lda, dsc.d = m, n, lda, int(sysd["d"])
         dsc.seed = int(sysd["seed"]) & (2**64 - 1)
+    return descs, xs, keep, _TORCH_TO_CSK[a_dtype]
+
+
+def csk_solve_batched(systems: Sequence[dict], *, lp_dtype: torch.dtype = torch.float32, tol: float = 1e-8,
+                      maxit: int = 200000, refresh_every: int = 64, sync: bool = True, stream=None):
+    """Sketch and solve many independent systems in one pass.
+
+    Each system is a dict with A (m x n, float32 or float64), b (m float64),
+    d, seed and optional x_ref (n float64).  Returns (xs, results)."""
+    nsys = len(systems)
+    descs, xs, keep, a_code = _batched_descs(systems)
     dev = systems[0]["A"].device
-    a_code = _TORCH_TO_CSK[a_dtype]
     lp_code = _TORCH_TO_CSK[lp_dtype]
     nbytes = ctypes.c_size_t(0)
     _check(_lib.csk_solve_batched_workspace_size(descs, nsys, a_code, lp_code, ctypes.byref(nbytes)),
@@ -575,6 +583,32 @@ def csk_solve_batched(systems: Sequence[dict], *, lp_dtype: torch.dtype = torch.
         return xs, res, ws
     (stream or torch.cuda.current_stream()).synchronize()
     return xs, parse_results(res)
+
+
+def _report(r) -> dict:
+    return dict(choice=r.choice, default_choice=r.default_choice, us=r.us, default_us=r.default_us,
+                candidates=r.candidates)
+
+
+def csk_tune_batched(systems: Sequence[dict], *, lp_dtype: torch.dtype = torch.float32, tol: float = 1e-8,
+                     maxit: int = 200000, refresh_every: int = 64, stream=None) -> dict:
+    """Runs the batched solve once per plan variant, caches the fastest for
+    these shapes and returns the report (choice, default_choice, us,
+    default_us in microseconds per call, candidates)."""
+    nsys = len(systems)
+    descs, xs, keep, a_code = _batched_descs(systems)
+    dev = systems[0]["A"].device
+    lp_code = _TORCH_TO_CSK[lp_dtype]
+    nbytes = ctypes.c_size_t(0)
+    _check(_lib.csk_solve_batched_workspace_size(descs, nsys, a_code, lp_code, ctypes.byref(nbytes)),
+           "csk_solve_batched_workspace_size")
+    ws = _workspace(nbytes.value, dev)
+    res = torch.zeros(_abi.RESULT_BYTES * nsys, dtype=torch.uint8, device=dev)
+    o = _opts(tol, maxit, CSK_STOP_REL_ERR, refresh_every, None, None, 256, 0, -1)
+    rep = _abi.TuneReport()
+    _check(_lib.csk_tune_batched(descs, nsys, a_code, lp_code, ctypes.byref(o), _ptr(res), ctypes.byref(rep),
+                                 _ptr(ws), ws.numel(), _stream(stream)), "csk_tune_batched")
+    return _report(rep)
 
 
 def csk_solve_batched_sketches(systems: Sequence[dict], ws: torch.Tensor, *,
@@ -657,6 +691,39 @@ def csk_tune_solve(At: torch.Tensor, bt: torch.Tensor, *, At64: Optional[torch.T
                                int(trial_iters), ctypes.byref(best), _ptr(ws), ws.numel(), _stream(stream)),
            "csk_tune_solve")
     return dict(grid=best.grid, lanes_per_row=best.lanes_per_row, us_per_iter=best.us_per_iter)
+
+
+def csk_tune_mrhs(At_lp: torch.Tensor, At64: torch.Tensor, Bt: torch.Tensor, nu2: torch.Tensor, *,
+                  trial_iters: int = 200, stream=None) -> dict:
+    """Times the multi-RHS solve's row-tile counts on this system, caches
+    the fastest for its shape and returns the report (choice and
+    default_choice in 16-row tiles per workgroup, us and default_us per
+    iteration, candidates)."""
+    _need_cuda(At_lp, "At_lp")
+    d, n = At_lp.shape
+    nrhs = Bt.shape[1]
+    nbytes = ctypes.c_size_t(0)
+    _check(_lib.csk_tune_mrhs_workspace_size(d, n, nrhs, ctypes.byref(nbytes)), "csk_tune_mrhs_workspace_size")
+    ws = _workspace(nbytes.value, At_lp.device)
+    rep = _abi.TuneReport()
+    _check(_lib.csk_tune_mrhs(_ptr(At_lp), _TORCH_TO_CSK[At_lp.dtype], _rowmajor(At_lp, "At_lp"), _ptr(At64),
+                              _rowmajor(At64, "At64"), d, n, _ptr(Bt), nrhs, _rowmajor(Bt, "Bt"), _ptr(nu2),
+                              int(trial_iters), ctypes.byref(rep), _ptr(ws), ws.numel(), _stream(stream)),
+           "csk_tune_mrhs")
+    return _report(rep)
+
+
+def csk_tune_save(path: str) -> None:
+    """Writes every tuned choice of this process to `path`."""
+    _check(_lib.csk_tune_save(os.fsencode(path)), "csk_tune_save")
+
+
+def csk_tune_load(path: str) -> int:
+    """Merges the tuned choices in `path` (a file written by csk_tune_save
+    with this library version); returns the count read, -1 for none."""
+    k = ctypes.c_int32(0)
+    _check(_lib.csk_tune_load(os.fsencode(path), ctypes.byref(k)), "csk_tune_load")
+    return int(k.value)
 
 
 def csk_tune_lookup(d: int, n: int, dtype: torch.dtype, vector_rows: bool = True) -> dict:

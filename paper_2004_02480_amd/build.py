@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libcsk.so")
 MEMBW_LIB = os.path.join(HERE, "libcsk_membw.so")
 ARCH = os.environ.get("CSK_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["csk_api.hip", "sketch.hip", "solve.hip", "solve_csr.hip", "solve_rk.hip", "mrhs.hip"]
+SOURCES = ["csk_api.hip", "sketch.hip", "solve.hip", "solve_csr.hip", "solve_rk.hip", "mrhs.hip", "tune.hip"]
 MEMBW_SOURCES = ["membw.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

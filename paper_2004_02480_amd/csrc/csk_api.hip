@@ -15,6 +15,7 @@
 #include "csk_solve.h"
 #include "csk_solve_csr.h"
 #include "csk_mrhs.h"
+#include "csk_tune.h"
 
 namespace csk {
 
@@ -859,9 +860,43 @@ csk_status csk_solve_batched_sketch_loc(const csk_system_desc* sys, int32_t nsys
     return CSK_OK;
 }
 
+namespace {
+
+// The systems' shapes as a tune key: count and an FNV-1a hash of every (m, n, d).
+std::string batched_tune_key(const csk_system_desc* sys, int32_t nsys, csk_dtype a_dtype, csk_dtype lp_dtype)
+{
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](int64_t v) {
+        for (int b = 0; b < 8; ++b) {
+            h ^= static_cast<uint64_t>(v >> (8 * b)) & 0xFFu;
+            h *= 1099511628211ull;
+        }
+    };
+    for (int s = 0; s < nsys; ++s) {
+        mix(sys[s].m);
+        mix(sys[s].n);
+        mix(sys[s].d);
+    }
+    return tune_key("batched|nsys=%d|shapes=%016llx|a=%d|lp=%d", nsys, (unsigned long long)h, (int)a_dtype, (int)lp_dtype);
+}
+
+csk_status batched_entry(const csk_system_desc* sys, int32_t nsys, csk_dtype a_dtype, csk_dtype lp_dtype,
+                         const csk_solve_opts* opts, csk_solve_result* res, void* ws, size_t ws_bytes, void* stream,
+                         int variant);
+
+}  // namespace
+
 csk_status csk_solve_batched(const csk_system_desc* sys, int32_t nsys, csk_dtype a_dtype, csk_dtype lp_dtype,
                              const csk_solve_opts* opts, csk_solve_result* res, void* ws, size_t ws_bytes,
                              void* stream)
+{
+    return batched_entry(sys, nsys, a_dtype, lp_dtype, opts, res, ws, ws_bytes, stream, -1);
+}
+
+namespace {
+csk_status batched_entry(const csk_system_desc* sys, int32_t nsys, csk_dtype a_dtype, csk_dtype lp_dtype,
+                         const csk_solve_opts* opts, csk_solve_result* res, void* ws, size_t ws_bytes, void* stream,
+                         int variant)
 {
     g_err[0] = 0;
     csk_status st = check_opts(opts);
@@ -961,8 +996,13 @@ csk_status csk_solve_batched(const csk_system_desc* sys, int32_t nsys, csk_dtype
         const double q = std::min(0.9, (double)sys[i].n / (double)sys[i].d);
         return (double)sys[i].d * (double)sys[i].n * (double)sys[i].n / ((1.0 - std::sqrt(q)) * (1.0 - std::sqrt(q)));
     };
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return est(a) > est(b); });
+    if (variant < 0) {
+        TuneRec tr{};
+        variant = (tune_get(batched_tune_key(sys, nsys, a_dtype, lp_dtype), &tr) && tr.a >= 0 && tr.a <= 4) ? tr.a : 0;
+    }
+    if (variant != 4) std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return est(a) > est(b); });
     BatchedPlan bp;
+    bp.variant = variant;
     bp.order = order.data();
     bp.sys = hs.data();
     bp.npad_max = npad_max;
@@ -975,6 +1015,86 @@ csk_status csk_solve_batched(const csk_system_desc* sys, int32_t nsys, csk_dtype
     bp.exch_records = kBatchExchRecords;
     bp.queue_dev = d_queue;
     return solve_batched_run(d_sys, nsys, bp, lp_dtype, opts, stm);
+}
+}  // namespace
+
+csk_status csk_tune_batched(const csk_system_desc* sys, int32_t nsys, csk_dtype a_dtype, csk_dtype lp_dtype,
+                            const csk_solve_opts* opts, csk_solve_result* res, csk_tune_report* report, void* ws,
+                            size_t ws_bytes, void* stream)
+{
+    g_err[0] = 0;
+    hipStream_t stm = as_stream(stream);
+    hipEvent_t e0, e1;
+    CSK_HIP(hipEventCreate(&e0));
+    CSK_HIP(hipEventCreate(&e1));
+    csk_tune_report R{-1, 0, 0.0, 0.0, 0};
+    csk_status r = CSK_OK;
+    for (int v = 0; v <= 4 && r == CSK_OK; ++v) {
+        if (v == 0) {  // one untimed run first (the batch's first launch)
+            r = batched_entry(sys, nsys, a_dtype, lp_dtype, opts, res, ws, ws_bytes, stream, 0);
+            if (r != CSK_OK) break;
+        }
+        if (hipEventRecord(e0, stm) != hipSuccess) { set_error("hipEventRecord failed"); r = CSK_ERR_DEVICE; break; }
+        r = batched_entry(sys, nsys, a_dtype, lp_dtype, opts, res, ws, ws_bytes, stream, v);
+        if (r != CSK_OK) break;
+        if (hipEventRecord(e1, stm) != hipSuccess) { set_error("hipEventRecord failed"); r = CSK_ERR_DEVICE; break; }
+        if (hipEventSynchronize(e1) != hipSuccess) { set_error("tuning run failed"); r = CSK_ERR_DEVICE; break; }
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { set_error("hipEventElapsedTime failed"); r = CSK_ERR_DEVICE; break; }
+        const double us = ms * 1e3;
+        ++R.candidates;
+        if (v == 0) R.default_us = us;
+        if (R.choice < 0 || us < R.us) {
+            R.choice = v;
+            R.us = us;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (r != CSK_OK) return r;
+    tune_put(batched_tune_key(sys, nsys, a_dtype, lp_dtype), TuneRec{R.choice, 0, R.us});
+    if (report) *report = R;
+    return CSK_OK;
+}
+
+csk_status csk_tune_mrhs_workspace_size(int64_t d, int64_t n, int64_t nrhs, size_t* bytes)
+{
+    g_err[0] = 0;
+    if (!bytes || d < 1 || n < 1 || nrhs < 1) { set_error("bad sizes"); return CSK_ERR_INVALID_ARG; }
+    *bytes = mrhs_tune_ws_bytes(d, n, nrhs);
+    return CSK_OK;
+}
+
+csk_status csk_tune_mrhs(const void* At_lp, csk_dtype lp_dtype, int64_t ldat_lp, const double* At64, int64_t ldat64,
+                         int64_t d, int64_t n, const double* Bt, int64_t nrhs, int64_t ldbt, const double* nu2,
+                         int32_t trial_iters, csk_tune_report* report, void* ws, size_t ws_bytes, void* stream)
+{
+    g_err[0] = 0;
+    if (d < 1 || n < 1 || nrhs < 1 || d > INT32_MAX || n > 1024) { set_error("need 1 <= d < 2^31, 1 <= n <= 1024, nrhs >= 1"); return CSK_ERR_INVALID_ARG; }
+    if (!At_lp || !At64 || !Bt || !nu2) { set_error("At_lp, At64, Bt and nu2 are required"); return CSK_ERR_INVALID_ARG; }
+    if (lp_dtype != CSK_BF16 && lp_dtype != CSK_F16) { set_error("lp_dtype must be BF16 or F16"); return CSK_ERR_UNSUPPORTED; }
+    if (ldat_lp < n || ldat64 < n || ldbt < nrhs) { set_error("leading dimension too small"); return CSK_ERR_INVALID_ARG; }
+    if (trial_iters < 1 || trial_iters > 1000000) { set_error("trial_iters out of range"); return CSK_ERR_INVALID_ARG; }
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u)) { set_error("workspace NULL or unaligned"); return CSK_ERR_INVALID_ARG; }
+    return mrhs_tune(At_lp, lp_dtype, ldat_lp, At64, ldat64, d, n, Bt, nrhs, ldbt, nu2, trial_iters, report, ws,
+                     ws_bytes, as_stream(stream));
+}
+
+csk_status csk_tune_save(const char* path)
+{
+    g_err[0] = 0;
+    if (!path || !*path) { set_error("path is NULL or empty"); return CSK_ERR_INVALID_ARG; }
+    if (!tune_save_file(path)) { set_error("cannot write the tune cache to %s", path); return CSK_ERR_INVALID_ARG; }
+    return CSK_OK;
+}
+
+csk_status csk_tune_load(const char* path, int32_t* entries)
+{
+    g_err[0] = 0;
+    if (!path || !*path) { set_error("path is NULL or empty"); return CSK_ERR_INVALID_ARG; }
+    const int k = tune_load_file(path);
+    if (entries) *entries = k;
+    return CSK_OK;
 }
 
 csk_status csk_solve_mrhs_workspace_size(int64_t d, int64_t n, int64_t nrhs, size_t* bytes)

@@ -82,6 +82,7 @@ struct BatchedPlan {
     void* exch_dev;            // exch_records records
     size_t exch_records;
     uint32_t* queue_dev;
+    int32_t variant;           // plan variant (0 default; see csk_tune_batched)
 };
 
 // `sys_dev` is the device array of nsys descriptors (rows 16-byte aligned,

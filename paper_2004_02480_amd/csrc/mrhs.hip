@@ -20,6 +20,7 @@
 // Scores and projections use the FP64 rows, as in the single-system solver.
 #include "csk_grid.h"
 #include "csk_mrhs.h"
+#include "csk_tune.h"
 
 #include <algorithm>
 
@@ -997,14 +998,16 @@ struct Geom {
     int CB, RB, RT, rows_pad, npad, Rpad;
 };
 
-Geom geom(int64_t d, int64_t n, int64_t R)
+// Geometry of a multi-RHS launch: 128 columns per workgroup and RT 16-row
+// tiles (rt = 0: the fewest that keep one workgroup per CU, the default).
+Geom geom(int64_t d, int64_t n, int64_t R, int rt = 0)
 {
     Geom g;
     const int cus = std::max(1, device_cu_count());
     g.CB = (int)((R + kCols - 1) / kCols);
     const int rb_max = std::max(1, cus / g.CB);
     const int64_t rows_per = (d + rb_max - 1) / rb_max;
-    g.RT = (int)((rows_per + 15) / 16);
+    g.RT = rt > 0 ? rt : (int)((rows_per + 15) / 16);
     g.RB = (int)((d + 16 * g.RT - 1) / (16 * g.RT));
     g.rows_pad = g.RB * 16 * g.RT;
     // rows up to 512 columns are padded to 32 * KS, KS in {2, 4, 8, 16} (the
@@ -1139,9 +1142,9 @@ csk_status dispatch_rd(const RdCtl& C, int RT, int G, hipStream_t st, size_t shm
 
 }  // namespace
 
-size_t mrhs_ws_bytes(int64_t d, int64_t n, int64_t nrhs)
+namespace {
+size_t ws_bytes_of(const Geom& g)
 {
-    const Geom g = geom(d, n, nrhs);
     Carve c(nullptr);
     c.take<uint16_t>((size_t)g.rows_pad * g.npad);
     c.take<double>((size_t)g.Rpad * g.npad);
@@ -1160,12 +1163,37 @@ size_t mrhs_ws_bytes(int64_t d, int64_t n, int64_t nrhs)
     return c.bytes();
 }
 
+std::string mrhs_tune_key(int64_t d, int64_t n, int64_t nrhs, csk_dtype lp)
+{
+    return tune_key("mrhs|d=%lld|n=%lld|nrhs=%lld|dtype=%d", (long long)d, (long long)n, (long long)nrhs, (int)lp);
+}
+}  // namespace
+
+// The row-tile counts a launch may use: from the default (fewest) up to
+// kMaxRT.  The workspace covers all of them (more row tiles can pad more rows).
+int mrhs_rt_min(int64_t d, int64_t n, int64_t nrhs) { return geom(d, n, nrhs).RT; }
+
+size_t mrhs_ws_bytes(int64_t d, int64_t n, int64_t nrhs)
+{
+    size_t b = 0;
+    for (int rt = std::max(1, mrhs_rt_min(d, n, nrhs)); rt <= kMaxRT; ++rt) b = std::max(b, ws_bytes_of(geom(d, n, nrhs, rt)));
+    return std::max(b, ws_bytes_of(geom(d, n, nrhs)));
+}
+
 csk_status mrhs_run(const void* At_lp, csk_dtype lp_dtype, int64_t ldat_lp, const double* At64, int64_t ldat64,
                     int64_t d, int64_t n, const double* Bt, int64_t nrhs, int64_t ldbt, const double* nu2,
                     const double* X0, double* X, int64_t ldx, const double* Xref, int64_t ldxref,
-                    const csk_solve_opts* o, csk_solve_result* res, void* ws, size_t ws_bytes, hipStream_t st)
+                    const csk_solve_opts* o, csk_solve_result* res, void* ws, size_t ws_bytes, hipStream_t st,
+                    int rt_force)
 {
-    const Geom g = geom(d, n, nrhs);
+    // row tiles: forced (tuning), else tuned for this shape, else the default
+    int rt = rt_force;
+    if (rt <= 0) {
+        TuneRec tr{};
+        if (tune_get(mrhs_tune_key(d, n, nrhs, lp_dtype), &tr) && tr.a >= mrhs_rt_min(d, n, nrhs) && tr.a <= kMaxRT)
+            rt = tr.a;
+    }
+    const Geom g = geom(d, n, nrhs, rt);
     if ((nrhs + (int64_t)g.RB * g.CB - 1) / ((int64_t)g.RB * g.CB) > kMaxOwned) {
         set_error("multi-RHS: %lld right-hand sides on %d workgroups exceed %d per workgroup", (long long)nrhs,
                   g.RB * g.CB, kMaxOwned);
@@ -1284,6 +1312,72 @@ csk_status mrhs_run(const void* At_lp, csk_dtype lp_dtype, int64_t ldat_lp, cons
     k_store_x<<<grid_for(n * nrhs, 8192), 256, 0, st>>>(C.XT, g.npad, (int)n, (int)nrhs, X, ldx);
     CSK_LAUNCH_CHECK("k_store_x");
     return CSK_OK;
+}
+
+// Times `trial_iters` iterations (no convergence: tol 0, residual mode) of
+// every row-tile count from the default up to kMaxRT, and stores the fastest.
+csk_status mrhs_tune(const void* At_lp, csk_dtype lp_dtype, int64_t ldat_lp, const double* At64, int64_t ldat64,
+                     int64_t d, int64_t n, const double* Bt, int64_t nrhs, int64_t ldbt, const double* nu2,
+                     int32_t trial_iters, csk_tune_report* rep, void* ws, size_t ws_bytes, hipStream_t st)
+{
+    Carve c(ws);
+    void* sws = c.take<char>(mrhs_ws_bytes(d, n, nrhs));
+    double* X = c.take<double>((size_t)n * nrhs);
+    csk_solve_result* res = c.take<csk_solve_result>(nrhs);
+    if (c.bytes() > ws_bytes) {
+        set_error("tuning workspace: need %zu bytes, got %zu", c.bytes(), ws_bytes);
+        return CSK_ERR_WORKSPACE;
+    }
+    csk_solve_opts o{};
+    o.tol = 0.0;
+    o.maxit = trial_iters;
+    o.stop_mode = CSK_STOP_REL_RESID;
+    o.refresh_every = 64;
+    o.check_every = 256;
+    hipEvent_t e0, e1;
+    CSK_HIP(hipEventCreate(&e0));
+    CSK_HIP(hipEventCreate(&e1));
+    const int rt0 = mrhs_rt_min(d, n, nrhs);
+    csk_tune_report R{0, rt0, 0.0, 0.0, 0};
+    csk_status r = CSK_OK;
+    for (int rt = rt0; rt <= kMaxRT && r == CSK_OK; ++rt) {
+        if (rt > rt0 && geom(d, n, nrhs, rt).RB == geom(d, n, nrhs, rt - 1).RB) continue;  // same launch
+        r = mrhs_run(At_lp, lp_dtype, ldat_lp, At64, ldat64, d, n, Bt, nrhs, ldbt, nu2, nullptr, X, n, nullptr, 0,
+                     &o, res, sws, mrhs_ws_bytes(d, n, nrhs), st, rt);
+        if (r == CSK_ERR_UNSUPPORTED) { r = CSK_OK; continue; }  // this shape does not launch here
+        if (r != CSK_OK) break;
+        if (hipEventRecord(e0, st) != hipSuccess) { set_error("hipEventRecord failed"); r = CSK_ERR_DEVICE; break; }
+        r = mrhs_run(At_lp, lp_dtype, ldat_lp, At64, ldat64, d, n, Bt, nrhs, ldbt, nu2, nullptr, X, n, nullptr, 0,
+                     &o, res, sws, mrhs_ws_bytes(d, n, nrhs), st, rt);
+        if (r != CSK_OK) break;
+        if (hipEventRecord(e1, st) != hipSuccess) { set_error("hipEventRecord failed"); r = CSK_ERR_DEVICE; break; }
+        if (hipEventSynchronize(e1) != hipSuccess) { set_error("tuning run failed"); r = CSK_ERR_DEVICE; break; }
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { set_error("hipEventElapsedTime failed"); r = CSK_ERR_DEVICE; break; }
+        const double us = ms * 1e3 / trial_iters;
+        ++R.candidates;
+        if (rt == rt0) R.default_us = us;
+        if (R.choice == 0 || us < R.us) {
+            R.choice = rt;
+            R.us = us;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (r != CSK_OK) return r;
+    if (R.choice == 0) { set_error("no multi-RHS launch shape fits this system"); return CSK_ERR_UNSUPPORTED; }
+    tune_put(mrhs_tune_key(d, n, nrhs, lp_dtype), TuneRec{R.choice, 0, R.us});
+    if (rep) *rep = R;
+    return CSK_OK;
+}
+
+size_t mrhs_tune_ws_bytes(int64_t d, int64_t n, int64_t nrhs)
+{
+    Carve c(nullptr);
+    c.take<char>(mrhs_ws_bytes(d, n, nrhs));
+    c.take<double>((size_t)n * nrhs);
+    c.take<csk_solve_result>(nrhs);
+    return c.bytes();
 }
 
 }  // namespace csk

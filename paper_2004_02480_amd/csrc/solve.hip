@@ -31,6 +31,7 @@
 // batched kernel hands whole systems to workgroups from an atomic queue.
 #include "csk_grid.h"
 #include "csk_solve.h"
+#include "csk_tune.h"
 
 #include <algorithm>
 #include <cmath>
@@ -950,10 +951,13 @@ csk_status launch_batched(const SolveSys* sys_dev, int32_t nsys, const BatchedPl
     // workgroup.
     const double esz = (double)sizeof(typename Elem<Tag>::S);
     const double ce = 0.18e-3 * (esz == 2.0 ? 1.5 : esz == 8.0 ? 1.4 : 1.0);
+    // plan variants (tuning): 1 never splits, 2 and 3 price the exchange of
+    // a split system at half and twice the modelled cost
+    const double split_cost = bp.variant == 2 ? 3.0 : bp.variant == 3 ? 12.0 : 6.0;
     auto model = [&](const SolveSys& S, int parts) {
         const double q = std::min(0.9, (double)S.n / (double)std::max(S.d, 1));
         const double iters = (double)S.n / ((1.0 - std::sqrt(q)) * (1.0 - std::sqrt(q)));
-        return iters * ((parts > 1 ? 6.0 : 2.0) + ce * (double)S.d * (double)S.n / parts);
+        return iters * ((parts > 1 ? split_cost : 2.0) + ce * (double)S.d * (double)S.n / parts);
     };
     std::vector<int> nparts(nsys, 1);
     std::vector<double> tsys(nsys);
@@ -971,7 +975,7 @@ csk_status launch_batched(const SolveSys* sys_dev, int32_t nsys, const BatchedPl
         const SolveSys& S = bp.sys[bp.order[p]];
         const int cur = nparts[p];
         const int next = cur + 1;
-        const int maxp = std::max(1, std::min(cap / 2, S.d / 32));
+        const int maxp = bp.variant == 1 ? 1 : std::max(1, std::min(cap / 2, S.d / 32));
         const size_t rec_next = rec - (cur > 1 ? 2 * (size_t)cur : 0) + 2 * (size_t)next;
         if (next > maxp || rec_next > bp.exch_records) break;
         const double t_next = model(S, next);
@@ -1064,54 +1068,32 @@ int pick_lpr(int64_t n, int64_t per_lane)
     return best;
 }
 
-// Tuned launch shapes, keyed by (device, d, n, working dtype, vector path):
-// written by csk_tune_solve, read by every default-shaped solve.
+// Tuned launch shapes of the persistent solve, keyed by (architecture, d, n,
+// working dtype, vector path) in the shared tune store: written by
+// csk_tune_solve, read by every default-shaped solve.
 namespace {
-struct TuneKey {
-    int dev;
-    int64_t d, n;
-    int dtype, vw;
-    bool operator<(const TuneKey& o) const
-    {
-        return std::tie(dev, d, n, dtype, vw) < std::tie(o.dev, o.d, o.n, o.dtype, o.vw);
-    }
-};
-struct TuneVal {
-    int grid, lpr;
-    double us;
-};
-std::mutex g_tune_mu;
-std::map<TuneKey, TuneVal> g_tune;
-
-int current_device()
+std::string solve_tune_key(int64_t d, int64_t n, csk_dtype at_dtype, int vw)
 {
-    int dev = 0;
-    return hipGetDevice(&dev) == hipSuccess ? dev : -1;
+    return tune_key("solve|d=%lld|n=%lld|dtype=%d|vw=%d", (long long)d, (long long)n, (int)at_dtype, vw);
 }
 }  // namespace
 
 void tune_store(int64_t d, int64_t n, csk_dtype at_dtype, int vw, int grid, int lpr, double us)
 {
-    std::lock_guard<std::mutex> lock(g_tune_mu);
-    g_tune[TuneKey{current_device(), d, n, (int)at_dtype, vw}] = TuneVal{grid, lpr, us};
+    tune_put(solve_tune_key(d, n, at_dtype, vw), TuneRec{grid, lpr, us});
 }
 
 bool tune_lookup(int64_t d, int64_t n, csk_dtype at_dtype, int vw, int* grid, int* lpr, double* us)
 {
-    std::lock_guard<std::mutex> lock(g_tune_mu);
-    const auto it = g_tune.find(TuneKey{current_device(), d, n, (int)at_dtype, vw});
-    if (it == g_tune.end()) return false;
-    *grid = it->second.grid;
-    *lpr = it->second.lpr;
-    if (us) *us = it->second.us;
+    TuneRec r{};
+    if (!tune_get(solve_tune_key(d, n, at_dtype, vw), &r)) return false;
+    *grid = r.a;
+    *lpr = r.b;
+    if (us) *us = r.us;
     return true;
 }
 
-void tune_clear()
-{
-    std::lock_guard<std::mutex> lock(g_tune_mu);
-    g_tune.clear();
-}
+void tune_clear() { tune_reset(); }
 
 int solve_vw(csk_dtype at_dtype, int64_t ldat, const void* At)
 {
