@@ -133,9 +133,23 @@ def main_workload(args, P, W, torch):
         return sk
 
     log(f"[bench] warmup {args.warmup} step(s)")
+    sk = None
     for _ in range(args.warmup):
-        step(False)
+        sk = step(False)
     torch.cuda.synchronize()
+    # the library's default launch shape, then the tuner's (the timed steps
+    # use the tuned shape: default-shaped solves read the tune cache)
+    tuning = {}
+    if not args.no_tune:
+        if sk is None:
+            sk = step(False)
+        t_def, _ = timed(lambda: P.csk_solve(sk.At64, sk.bt, nu2=sk.nu2, x_ref=s.x_star, tol=c["tol"],
+                                             maxit=c["maxit"], out=x, result=res, workspace=ws, sync=False))
+        it_def = P.parse_results(res)[0][0]
+        best = P.csk_tune_solve(sk.At64, sk.bt, nu2=sk.nu2, trial_iters=200)
+        tuning = dict(default_solve_s=t_def, default_us_per_iter=t_def / max(it_def, 1) * 1e6, tuned_shape=best)
+        log(f"[bench] tuned launch shape {best} (default shape: {tuning['default_us_per_iter']:.2f} us/iter)")
+    del sk
     log(f"[bench] timing {args.steps} step(s)")
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
@@ -166,6 +180,7 @@ def main_workload(args, P, W, torch):
                solve_gbs=it * iter_bytes / solve_s / 1e9, us_per_iter=solve_s / max(it, 1) * 1e6,
                sketch_bytes=sketch_bytes, m=m, n=n, d=d)
     out["x"] = x.cpu().numpy()
+    out["tuning"] = tuning
     del sk
     return out, s, c
 
@@ -343,7 +358,7 @@ def cpu_baseline_leg(main_res, s_main, c_main, extra, W, torch, budget_iters=200
     return cpu, parity
 
 
-def mixed_workload(P, W, torch, reps=2):
+def mixed_workload(P, W, torch, reps=2, tune=True):
     """Row-scaled FP32 A 500000 x 1000, d = 10000: FP64 path vs BF16 / FP16
     storage with FP64 refresh, time to 1e-10 (sketch + solve)."""
     c = W.config("row_scaled")
@@ -361,6 +376,13 @@ def mixed_workload(P, W, torch, reps=2):
             return P.csk_solve(sk.At_lp, sk.bt, At64=sk.At64, nu2=sk.nu2, x_ref=s.x_star, tol=c["tol"],
                                maxit=c["maxit"], sync=False)
         run()
+        if tune:
+            sk = P.csk_sketch(s.A, s.b, c["d"], c["sketch_seed"], lp_dtype=lp)
+            if lp is None:
+                P.csk_tune_solve(sk.At64, sk.bt, nu2=sk.nu2, trial_iters=200)
+            else:
+                P.csk_tune_solve(sk.At_lp, sk.bt, At64=sk.At64, nu2=sk.nu2, trial_iters=200)
+            del sk
         t, (x, raw) = timed(run, reps)
         it, st, fb, meas, nref = P.parse_results(raw)[0]
         rel = ((x - s.x_star).norm() / s.x_star.norm()).item()
@@ -378,7 +400,7 @@ BATCH_ORACLE_SYSTEMS = 32  # systems whose solution the oracle leg recomputes
 MRHS_ORACLE_COLUMNS = 8    # right-hand sides whose solution the oracle leg recomputes
 
 
-def batched_workload(P, W, torch):
+def batched_workload(P, W, torch, tune=True):
     """512 uneven Gaussian FP32 systems, sketch + solve to 1e-8 in one pass."""
     c = W.config("batched")
     dev = "cuda:0"
@@ -395,6 +417,11 @@ def batched_workload(P, W, torch):
     # iteration), in FP32 and in BF16 (the latter two with an FP64 refresh)
     for name, lp in (("f64", torch.float64), ("f32", torch.float32), ("bf16", torch.bfloat16)):
         P.csk_solve_batched(systems[:4], lp_dtype=lp, tol=c["tol"], maxit=c["maxit"])
+        tuned = None
+        if tune:
+            tuned = P.csk_tune_batched(systems, lp_dtype=lp, tol=c["tol"], maxit=c["maxit"])
+            log(f"[bench] batched {name} plan: variant {tuned['choice']} {tuned['us'] / 1e3:.1f} ms "
+                f"(default {tuned['default_us'] / 1e3:.1f} ms)")
         t, (xs, raw, ws) = timed(lambda: P.csk_solve_batched(systems, lp_dtype=lp, tol=c["tol"],
                                                               maxit=c["maxit"], sync=False))
         res = P.parse_results(raw)
@@ -403,7 +430,7 @@ def batched_workload(P, W, torch):
         log(f"[bench] batched {name}: {t * 1e3:.1f} ms for {len(shapes)} systems, {ok} converged, "
             f"worst rel {worst:.2e}")
         out[name] = dict(time_s=t, converged=ok, systems_per_s=len(shapes) / t, worst_relerr=worst,
-                         total_iters=int(sum(r[0] for r in res)),
+                         total_iters=int(sum(r[0] for r in res)), tuned_plan=tuned,
                          x_first=[x.cpu().numpy() for x in xs[:BATCH_ORACLE_SYSTEMS]])
         del xs, raw, ws
     out["time_s"] = out["f32"]["time_s"]
@@ -416,7 +443,7 @@ def batched_workload(P, W, torch):
     return out
 
 
-def mrhs_workload(P, W, torch):
+def mrhs_workload(P, W, torch, tune=True):
     """A 200000 x 500 FP32 Gaussian, 256 right-hand sides, d = 10000: sketch of
     A and B together, then all columns solved to 1e-8 with BF16 matrix-core
     residual products and FP64 refresh."""
@@ -431,6 +458,14 @@ def mrhs_workload(P, W, torch):
     solve = lambda: P.csk_solve_mrhs(sk.At_lp, sk.At64, sk.bt, sk.nu2, Xref=s.X_star, tol=c["tol"],
                                      maxit=c["maxit"], sync=False)
     solve()
+    tuned = None
+    t_default = None
+    if tune:
+        t_default, _ = timed(solve)
+        tuned = P.csk_tune_mrhs(sk.At_lp, sk.At64, sk.bt, sk.nu2, trial_iters=200)
+        log(f"[bench] multi_rhs row tiles: {tuned['choice']} ({tuned['us']:.2f} us/iter; default "
+            f"{tuned['default_choice']}: {tuned['default_us']:.2f} us/iter)")
+        solve()
     t_sv, (X, raw) = timed(solve)
     res = P.parse_results(raw)
     ok = sum(1 for r in res if r[1] == P.CSK_OK)
@@ -445,6 +480,7 @@ def mrhs_workload(P, W, torch):
     return dict(sketch_s=t_sk, solve_s=t_sv, time_s=t_sk + t_sv, iters=its, converged=ok, worst_relerr=err,
                 rhs_per_s=c["nrhs"] / (t_sk + t_sv), mfma_tflops=flops / t_sv / 1e12,
                 mfma_frac_bf16_peak=flops / t_sv / 2.5e15, us_per_iter=t_sv / max(its, 1) * 1e6,
+                tuned_row_tiles=tuned, default_solve_s=t_default,
                 X_first=Xk)
 
 
@@ -709,6 +745,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--quick", action="store_true", help="main workload only (for profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="time the library's default launch shapes only")
     ap.add_argument("--extra", default="all",
                     help="comma-separated extra workloads after the main one (default all; see EXTRAS)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -737,10 +774,10 @@ def main():
         torch.cuda.empty_cache()
         extras = {
             "oracle_small": lambda: oracle_small_workload(P, W, torch),
-            "row_scaled_mixed": lambda: mixed_workload(P, W, torch),
+            "row_scaled_mixed": lambda: mixed_workload(P, W, torch, tune=not args.no_tune),
             "sparse_csr": lambda: csr_workload(P, W, torch),
-            "batched_512": lambda: batched_workload(P, W, torch),
-            "multi_rhs_256": lambda: mrhs_workload(P, W, torch),
+            "batched_512": lambda: batched_workload(P, W, torch, tune=not args.no_tune),
+            "multi_rhs_256": lambda: mrhs_workload(P, W, torch, tune=not args.no_tune),
             "table1": lambda: table1_workload(P, W, torch),
             "figure_selection_rules": lambda: figure_workload(P, W, torch),
             "memory_rates": lambda: memory_rates(torch),
@@ -817,7 +854,8 @@ def main():
         "roofline": roof,
         "sketch": sketch,
         "solve": {"time_s": main_res["solve_s"], "iters": main_res["iters"], "us_per_iter": main_res["us_per_iter"],
-                  "bytes_per_iter": main_res["iter_bytes"], "relerr": main_res["relerr"]},
+                  "bytes_per_iter": main_res["iter_bytes"], "relerr": main_res["relerr"],
+                  "tuning": main_res["tuning"]},
         "cpu_baseline": cpu,
         "oracle_parity": parity,
         "extra": strip(extra),

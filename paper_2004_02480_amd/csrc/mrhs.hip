@@ -1088,7 +1088,8 @@ int rd_nown(const Geom& g, int64_t nrhs)
 bool rd_fits(const Geom& g, int64_t nrhs)
 {
     const int nown = rd_nown(g, nrhs);
-    constexpr size_t kStatic = 8 * 16 * 8 + 8 * 8 + 8 * 4 + 256;  // s_nu2 (RT <= 8), s_e2, s_odone, slack
+    // static LDS of k_mrhs_rd: s_nu2 and s_inu2 (RT <= kMaxRT), s_e2, s_odone, and slack
+    constexpr size_t kStatic = 2 * kMaxRT * 16 * 8 + (kNT / kWave) * (8 + 4) + 256;
     return g.npad <= kRdMaxNpad && nown <= kNT / kWave && nown * g.RB <= kNT &&
            rd_lds_bytes(g, nown) + kStatic <= (size_t)device_max_lds();
 }
