@@ -172,12 +172,27 @@ __global__ __launch_bounds__(1024) void k_scan_single(const uint32_t* __restrict
     __shared__ uint32_t wtot[16];
     const int lane = threadIdx.x & (kWave - 1);
     const int w = threadIdx.x / kWave;
-    for (int64_t j = threadIdx.x; j < D; j += 1024) sc[j] = cnt[j];
+    {
+        // all of a thread's loads are issued before the first is waited for
+        uint32_t v[kScanRegs];
+#pragma unroll
+        for (int k = 0; k < kScanRegs; ++k) {
+            const int64_t j = threadIdx.x + (int64_t)k * 1024;
+            v[k] = j < D ? cnt[j] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < kScanRegs; ++k) {
+            const int64_t j = threadIdx.x + (int64_t)k * 1024;
+            if (j < D) sc[j] = v[k];
+        }
+    }
     __syncthreads();
     const int64_t per = (D + 1023) / 1024;
     const int64_t lo = min<int64_t>(D, threadIdx.x * per), hi = min<int64_t>(D, lo + per);
     uint32_t sum = 0;
-    for (int64_t j = lo; j < hi; ++j) sum += sc[j];
+#pragma unroll
+    for (int k = 0; k < kScanRegs; ++k)
+        if (lo + k < hi) sum += sc[lo + k];
     uint32_t x = sum;
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) {
@@ -194,11 +209,13 @@ __global__ __launch_bounds__(1024) void k_scan_single(const uint32_t* __restrict
         total += t;
     }
     uint32_t run = carry + x - sum;
-    for (int64_t j = lo; j < hi; ++j) {
-        const uint32_t v = sc[j];
-        sc[j] = run;
-        run += v;
-    }
+#pragma unroll
+    for (int k = 0; k < kScanRegs; ++k)
+        if (lo + k < hi) {
+            const uint32_t v = sc[lo + k];
+            sc[lo + k] = run;
+            run += v;
+        }
     __syncthreads();
     for (int64_t j = threadIdx.x; j < D; j += 1024) ptr[j] = sc[j];
     if (threadIdx.x == 0) ptr[D] = total;
@@ -257,14 +274,33 @@ __global__ __launch_bounds__(kHistNT) void k_scatter_lds(Batch b, int64_t rows_p
     const int64_t r0 = min(b.M, blockIdx.x * rows_per_block), r1 = min(b.M, r0 + rows_per_block);
     block_hist(S, r0, r1, h);
     // counting down through cnt (it ends at zero): this block's slots of
-    // bucket j are [old - h[j], old)
-    for (uint32_t j = threadIdx.x; j < d; j += kHistNT)
-        if (h[j]) h[j] = atomicSub(&b.cnt[j], h[j]) - h[j];
+    // bucket j are ptr[j] + [old - h[j], old).  A thread's counter updates
+    // and ptr loads are all issued before the first is waited for (d is at
+    // most kHistCap, so a thread holds at most kPer buckets).
+    constexpr int kPer = kHistCap / kHistNT;
+    {
+        uint32_t hv[kPer], old[kPer], base[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const uint32_t j = threadIdx.x + k * kHistNT;
+            hv[k] = j < d ? h[j] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const uint32_t j = threadIdx.x + k * kHistNT;
+            old[k] = hv[k] ? atomicSub(&b.cnt[j], hv[k]) : 0u;
+            base[k] = hv[k] ? b.ptr[j] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const uint32_t j = threadIdx.x + k * kHistNT;
+            if (hv[k]) h[j] = base[k] + old[k] - hv[k];
+        }
+    }
     __syncthreads();
     for (int64_t i = r0 + threadIdx.x; i < r1; i += kHistNT) {
         const uint32_t j = draw_bucket(draw_word(S.seed, static_cast<uint64_t>(i)), d);
-        const uint32_t pos = atomicAdd(&h[j], 1u);
-        b.perm[b.ptr[j] + pos] = static_cast<uint32_t>(i);
+        b.perm[atomicAdd(&h[j], 1u)] = static_cast<uint32_t>(i);
     }
 }
 
