@@ -695,7 +695,9 @@ def memory_rates(torch):
     a 4 GiB buffer read once per launch (HBM: far beyond the 256 MB Infinity
     Cache) and a 160 MB buffer (the headline sketch's size, which the
     Infinity Cache holds) read 20 times per launch, each with one workgroup
-    of 512 threads per CU and with four."""
+    of 512 threads per CU and with four; and a streaming mix that reads ten
+    bytes per byte it writes (the headline sketch's mix, 1.76 GB per
+    launch)."""
     import ctypes
     from paper_2004_02480_amd import build as B
     lib = ctypes.CDLL(B.MEMBW_LIB)
@@ -721,6 +723,23 @@ def memory_rates(torch):
         del buf
     out["hbm_read_peak_gbs"] = max(v for k, v in out.items() if k.startswith("hbm_"))
     out["mall_read_peak_gbs"] = max(v for k, v in out.items() if k.startswith("mall_"))
+    # the headline sketch's byte mix: ten bytes read per byte written (A
+    # 1.6 GB in, At 160 MB out), as coalesced streams, one vector per thread
+    lib.membw_mix.restype = ctypes.c_int
+    lib.membw_mix.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                              ctypes.c_void_p]
+    P, nvec = 10, 10**7
+    src = torch.empty(P * nvec * 2, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    dst = torch.empty(nvec * 2, dtype=torch.float64, device="cuda:0")
+
+    def run_mix():
+        e = lib.membw_mix(src.data_ptr(), nvec, P, dst.data_ptr(), (nvec + 255) // 256, stream)
+        if e != 0:
+            raise SystemExit(f"membw_mix failed: HIP error {e}")
+    run_mix()
+    sec, _ = timed(run_mix, 5)
+    out["hbm_read10_write1_gbs"] = (P + 1) * nvec * 16 / sec / 1e9
+    del src, dst
     torch.cuda.empty_cache()
     log(f"[bench] memory read rates (GB/s): {out}")
     return out
@@ -825,6 +844,10 @@ def main():
               "bytes": main_res["sketch_bytes"]}
     if mr:
         sketch["frac_of_measured_hbm_read"] = main_res["sketch_gbs"] / mr["hbm_read_peak_gbs"]
+        if "hbm_read10_write1_gbs" in mr:
+            # the chain moves ten bytes in per byte out; a plain stream with
+            # that mix is its ceiling
+            sketch["frac_of_measured_read10_write1"] = main_res["sketch_gbs"] / mr["hbm_read10_write1_gbs"]
     if parity is not None:
         parity["dense_coherent"]["gpu_relerr_vs_x_star"] = main_res["relerr"]
 
