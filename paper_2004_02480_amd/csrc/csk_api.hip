@@ -289,7 +289,7 @@ csk_status csk_sketch_csr_workspace_size(int64_t m, int64_t n, int64_t d, size_t
 {
     g_err[0] = 0;
     if (!bytes || m < 1 || n < 1 || d < 1) { set_error("bad sizes"); return CSK_ERR_INVALID_ARG; }
-    *bytes = sketch_ws_bytes(m, d, d, 1);
+    *bytes = sketch_csr_ws_bytes(m, d, false);
     return CSK_OK;
 }
 

@@ -559,7 +559,8 @@ struct CsrOut {
 template <int LP, bool SP>
 __global__ __launch_bounds__(kCsrNT) void k_segsum_csr(Batch b, const int64_t* __restrict__ row_ptr,
                                                        const int32_t* __restrict__ colidx,
-                                                       const float* __restrict__ val, int chunk, CsrOut so)
+                                                       const float* __restrict__ val, int chunk, CsrOut so,
+                                                       const uint32_t* __restrict__ queue)
 {
     extern __shared__ __align__(16) char smem[];
     double* acc = reinterpret_cast<double*>(smem);              // chunk columns
@@ -575,7 +576,10 @@ __global__ __launch_bounds__(kCsrNT) void k_segsum_csr(Batch b, const int64_t* _
     const int wid = tid / kWave;
     const SketchSys S = sys_at(b, 0);
     const int n = S.n;
-    for (int64_t j = blockIdx.x; j < S.d; j += gridDim.x) {
+    // queue: null (every bucket), or a count followed by the buckets to do
+    const int64_t count = queue ? (int64_t)queue[0] : (int64_t)S.d;
+    for (int64_t q = blockIdx.x; q < count; q += gridDim.x) {
+        const int64_t j = queue ? (int64_t)queue[1 + q] : q;
         const uint32_t beg = b.ptr[j], end = b.ptr[j + 1];
         const uint32_t len = end - beg;
         // stage: thread t takes row beg+t (first kCsrRows rows)
@@ -701,6 +705,186 @@ __global__ __launch_bounds__(kCsrNT) void k_segsum_csr(Batch b, const int64_t* _
                         bacc = bacc + draw_sign(draw_word(S.seed, row)) * S.B[row];
                     }
                 }
+                S.Bt[j] = bacc;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// The same sums for the common bucket, without an accumulator row: its
+// stored entries (at most kCsrSortCap, from at most kCsrRows rows, with
+// n <= kCsrRunsMaxN) are staged in LDS in row order and ranked by
+// (column, position), so each column's entries form one run in ascending
+// row order; every run is summed sequentially from +0.0 by one thread, all
+// runs at once.  A bitmap of the touched columns with per-word prefix counts
+// gives any column's run in O(1): the dense output and the squared norm walk
+// each thread's columns (c = t, t + 256, ...: the operand order of
+// k_segsum_csr, so the bits are the same), and the sparse output is the
+// runs themselves.  The LDS loops issue their reads ahead (unrolled, 16-byte
+// reads in the ranking), since a serial loop would wait out the LDS latency
+// once per step.  About 23 KB of LDS per workgroup, so six workgroups share a
+// CU.  A bucket that does not fit is appended to `queue` (count, then bucket
+// indices) for k_segsum_csr.
+constexpr int kCsrSortCap = 512;
+constexpr int kCsrRunsMaxN = 16384;  // columns: bitmap of 512 words
+
+template <int LP, bool SP>
+__global__ __launch_bounds__(kCsrNT) void k_segsum_csr_runs(Batch b, const int64_t* __restrict__ row_ptr,
+                                                            const int32_t* __restrict__ colidx,
+                                                            const float* __restrict__ val, CsrOut so,
+                                                            uint32_t* __restrict__ queue)
+{
+    // staged entries in row order; after the ranking, the runs (column, sum)
+    __shared__ __align__(16) int32_t s_col[kCsrSortCap];
+    __shared__ double s_val[kCsrSortCap];
+    __shared__ int32_t s_sc[kCsrSortCap];   // entries sorted by (column, position)
+    __shared__ double s_sv[kCsrSortCap];
+    __shared__ double s_b[kCsrRows];
+    __shared__ int64_t s_rs[kCsrRows];      // staged row: first stored entry in the CSR arrays
+    __shared__ uint32_t s_st[kCsrRows];     // staged row: first staging slot
+    __shared__ double s_sg[kCsrRows];       // staged row: sign
+    __shared__ uint32_t s_bm[kCsrRunsMaxN / 32];    // touched columns
+    __shared__ uint32_t s_wpre[kCsrRunsMaxN / 32];  // runs before each bitmap word
+    __shared__ double s_red[kCsrNT / kWave];
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wid = tid / kWave;
+    const SketchSys S = sys_at(b, 0);
+    const int n = S.n;
+    const int nwords = (n + 31) >> 5;
+    for (int64_t j = blockIdx.x; j < S.d; j += gridDim.x) {
+        const uint32_t beg = b.ptr[j], end = b.ptr[j + 1];
+        const uint32_t len = end - beg;
+        const bool rows_fit = len <= (uint32_t)kCsrRows && n <= kCsrRunsMaxN;
+        uint32_t mycnt = 0;
+        int64_t rs = 0;
+        double sg = 0.0;
+        if (rows_fit && (uint32_t)tid < len) {
+            const uint32_t myrow = b.perm[beg + tid];
+            sg = draw_sign(draw_word(S.seed, myrow));
+            rs = row_ptr[myrow];
+            mycnt = (uint32_t)(row_ptr[myrow + 1] - rs);
+            s_b[tid] = S.B ? sg * S.B[myrow] : 0.0;
+        }
+        uint32_t T;
+        const uint32_t start = block_incl_scan<kCsrNT>(mycnt, &T) - mycnt;
+        if (!rows_fit || T > (uint32_t)kCsrSortCap) {
+            if (tid == 0) queue[1 + atomicAdd(&queue[0], 1u)] = static_cast<uint32_t>(j);
+            continue;  // uniform: every thread saw the same len and T
+        }
+        if ((uint32_t)tid < len) {
+            s_rs[tid] = rs;
+            s_st[tid] = start;
+            s_sg[tid] = sg;
+        }
+        for (int w = tid; w < nwords; w += kCsrNT) s_bm[w] = 0u;
+        const uint32_t T4 = (T + 3u) & ~3u;
+        if ((uint32_t)tid < T4 - T) s_col[T + tid] = INT32_MAX;  // padding: above every column
+        __syncthreads();
+        // stage slot p from the row holding it (the last row whose first
+        // slot is at most p: rows without entries share their successor's
+        // first slot), all of a thread's loads at once
+        for (uint32_t p = tid; p < T; p += kCsrNT) {
+            uint32_t lo = 0, hi = len - 1;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi + 1) >> 1;
+                if (s_st[mid] <= p) lo = mid;
+                else hi = mid - 1;
+            }
+            const int64_t e = s_rs[lo] + (p - s_st[lo]);
+            s_col[p] = colidx[e];
+            s_val[p] = s_sg[lo] * static_cast<double>(val[e]);
+        }
+        __syncthreads();
+        // rank by (column, position): distinct keys, a permutation of [0, T)
+        for (uint32_t e = tid; e < T; e += kCsrNT) {
+            const int32_t ce = s_col[e];
+            uint32_t rank = 0;
+            const int4* c4 = reinterpret_cast<const int4*>(s_col);
+#pragma unroll 4
+            for (uint32_t f = 0; f < T4; f += 4) {
+                const int4 v = c4[f >> 2];
+                rank += (v.x < ce || (v.x == ce && f < e)) ? 1u : 0u;
+                rank += (v.y < ce || (v.y == ce && f + 1 < e)) ? 1u : 0u;
+                rank += (v.z < ce || (v.z == ce && f + 2 < e)) ? 1u : 0u;
+                rank += (v.w < ce || (v.w == ce && f + 3 < e)) ? 1u : 0u;
+            }
+            s_sc[rank] = ce;
+            s_sv[rank] = s_val[e];
+        }
+        __syncthreads();
+        // runs: thread t looks at sorted positions 2t and 2t + 1 (T <= 512);
+        // a run's column and sum go to s_col / s_val at its index
+        const uint32_t p0 = 2u * tid, p1 = p0 + 1u;
+        const int32_t c0 = p0 < T ? s_sc[p0] : 0;
+        const int32_t c1 = p1 < T ? s_sc[p1] : 0;
+        const uint32_t f0 = (p0 < T && (p0 == 0 || s_sc[p0 - 1] != c0)) ? 1u : 0u;
+        const uint32_t f1 = (p1 < T && c1 != c0) ? 1u : 0u;
+        uint32_t nruns;
+        const uint32_t r0 = block_incl_scan<kCsrNT>(f0 + f1, &nruns) - (f0 + f1);
+        auto run_sum = [&](uint32_t p, int32_t c, uint32_t r) {
+            double acc = 0.0;
+            for (uint32_t q = p; q < T && s_sc[q] == c; ++q) acc = acc + s_sv[q];
+            s_col[r] = c;
+            s_val[r] = acc;
+            atomicOr(&s_bm[c >> 5], 1u << (c & 31));
+        };
+        if (f0) run_sum(p0, c0, r0);
+        if (f1) run_sum(p1, c1, r0 + f0);
+        __syncthreads();
+        // runs before each bitmap word (thread t: words 2t and 2t + 1)
+        {
+            const int w0 = 2 * tid, w1 = w0 + 1;
+            const uint32_t n0 = w0 < nwords ? __popc(s_bm[w0]) : 0u;
+            const uint32_t n1 = w1 < nwords ? __popc(s_bm[w1]) : 0u;
+            uint32_t all;
+            const uint32_t before = block_incl_scan<kCsrNT>(n0 + n1, &all) - (n0 + n1);
+            if (w0 < nwords) s_wpre[w0] = before;
+            if (w1 < nwords) s_wpre[w1] = before + n0;
+        }
+        __syncthreads();
+        double nrm = 0.0;
+        double* const At64 = S.At64 ? S.At64 + j * S.ldat64 : nullptr;
+        void* const Atlp = LP != 0 ? static_cast<void*>(static_cast<char*>(S.Atlp) + j * S.ldatlp * (LP == CSK_F32 ? 4 : 2)) : nullptr;
+        auto column = [&](int c) {
+            const uint32_t word = s_bm[c >> 5];
+            const uint32_t below = word & ((1u << (c & 31)) - 1u);
+            const bool hit = (word >> (c & 31)) & 1u;
+            const double a = hit ? s_val[s_wpre[c >> 5] + __popc(below)] : 0.0;
+            nrm += a * a;
+            if constexpr (!SP) {
+                if (At64) At64[c] = a;
+                if constexpr (LP != 0) store_lp<LP>(Atlp, c, a);
+            }
+        };
+        // whole rounds of 256 columns without a bound check, then the tail
+        const int full = n / kCsrNT;
+#pragma unroll 4
+        for (int k = 0; k < full; ++k) column(k * kCsrNT + tid);
+        if (full * kCsrNT + tid < n) column(full * kCsrNT + tid);
+        if constexpr (SP) {
+            const uint32_t o = so.ofs[j];
+            for (uint32_t r = tid; r < nruns; r += kCsrNT) {
+                so.col[o + r] = s_col[r];
+                so.val[o + r] = s_val[r];
+            }
+            if (tid == 0) {
+                so.rp[j] = so.ofs[j];
+                if (j == S.d - 1) so.rp[S.d] = so.ofs[S.d];
+            }
+        }
+        nrm = wave_sum(nrm);
+        if (lane == 0) s_red[wid] = nrm;
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+            for (int w = 0; w < kCsrNT / kWave; ++w) t += s_red[w];
+            if (S.nu2) S.nu2[j] = t;
+            if (S.Bt) {
+                double bacc = 0.0;
+#pragma unroll 8
+                for (uint32_t p = 0; p < len; ++p) bacc = bacc + s_b[p];
                 S.Bt[j] = bacc;
             }
         }
@@ -1106,7 +1290,7 @@ namespace {
 // sketch_csr_ws_bytes sizes).  ofs (d + 1) only for the sparse output.
 csk_status csr_setup(const double* b, double* bt, double* nu2, int64_t m, int64_t n, int64_t d, uint64_t seed,
                      double* At64, int64_t ldat64, void* At_lp, int64_t ldat_lp, void* ws, size_t ws_bytes,
-                     bool sparse, Batch& bt_, uint32_t** ofs, hipStream_t st)
+                     bool sparse, Batch& bt_, uint32_t** queue, uint32_t** ofs, hipStream_t st)
 {
     std::vector<SketchSys> hs(1);
     SketchSys& S = hs[0];
@@ -1137,6 +1321,7 @@ csk_status csr_setup(const double* b, double* bt, double* nu2, int64_t m, int64_
     bt_.perm = c.take<uint32_t>(m);
     bt_.nu2part = c.take<double>(d);
     bt_.scan_part = c.take<uint32_t>(d / kScanTile + 2);
+    *queue = c.take<uint32_t>(d + 1);
     if (sparse) *ofs = c.take<uint32_t>(d + 1);
     if (c.bytes() > ws_bytes) {
         set_error("sketch workspace too small: need %zu bytes, got %zu", c.bytes(), ws_bytes);
@@ -1151,17 +1336,24 @@ csk_status csr_setup(const double* b, double* bt, double* nu2, int64_t m, int64_
     return group_rows(bt_, st);
 }
 
+// Every bucket goes to k_segsum_csr_runs; the few that do not fit its
+// staging (queue: count, then bucket indices; d + 1 words) follow through
+// k_segsum_csr, whose grid loops over the queue's count.
 template <int LP, bool SP>
 csk_status launch_segsum_csr(const Batch& b, const int64_t* row_ptr, const int32_t* col, const float* val, int64_t n,
-                             int64_t d, const CsrOut& so, hipStream_t st)
+                             int64_t d, const CsrOut& so, uint32_t* queue, hipStream_t st)
 {
+    k_fill_u32<<<1, 64, 0, st>>>(queue, 1, 0u);
+    CSK_LAUNCH_CHECK("k_fill_u32");
+    k_segsum_csr_runs<LP, SP><<<grid_for(d, 1, 1 << 20), kCsrNT, 0, st>>>(b, row_ptr, col, val, so, queue);
+    CSK_LAUNCH_CHECK("k_segsum_csr_runs");
     // accumulator chunk: up to 8192 columns (64 KB of LDS), plus its bitmap
     const int chunk = static_cast<int>(std::min<int64_t>(n, kCsrChunk));
     const size_t shm = (size_t)chunk * 8 + (SP ? kCsrNT * 4 : 0);
-    const int grid = grid_for(d, 1, 1 << 20);
+    const int grid = grid_for(d, 1, 1024);
     CSK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_segsum_csr<LP, SP>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-    k_segsum_csr<LP, SP><<<grid, kCsrNT, shm, st>>>(b, row_ptr, col, val, chunk, so);
+    k_segsum_csr<LP, SP><<<grid, kCsrNT, shm, st>>>(b, row_ptr, col, val, chunk, so, queue);
     CSK_LAUNCH_CHECK("k_segsum_csr");
     return CSK_OK;
 }
@@ -1170,7 +1362,7 @@ csk_status launch_segsum_csr(const Batch& b, const int64_t* row_ptr, const int32
 
 size_t sketch_csr_ws_bytes(int64_t m, int64_t d, bool sparse)
 {
-    return sketch_ws_bytes(m, d, d, 1) + (sparse ? (size_t)(d + 1) * 4 + 256 : 0);
+    return sketch_ws_bytes(m, d, d, 1) + (size_t)(d + 1) * 4 + 256 + (sparse ? (size_t)(d + 1) * 4 + 256 : 0);
 }
 
 csk_status sketch_csr_run(const int64_t* row_ptr, const int32_t* col, const float* val, int64_t m, int64_t n,
@@ -1180,15 +1372,16 @@ csk_status sketch_csr_run(const int64_t* row_ptr, const int32_t* col, const floa
 {
     (void)nnz;
     Batch bt_;
+    uint32_t* queue = nullptr;
     csk_status r = csr_setup(b, bt, nu2, m, n, d, seed, At64, ldat64, At_lp, ldat_lp, ws, ws_bytes, false, bt_,
-                             nullptr, st);
+                             &queue, nullptr, st);
     if (r != CSK_OK) return r;
     const CsrOut none{};
     switch (lp_dtype) {
-    case CSK_F32: return launch_segsum_csr<CSK_F32, false>(bt_, row_ptr, col, val, n, d, none, st);
-    case CSK_F16: return launch_segsum_csr<CSK_F16, false>(bt_, row_ptr, col, val, n, d, none, st);
-    case CSK_BF16: return launch_segsum_csr<CSK_BF16, false>(bt_, row_ptr, col, val, n, d, none, st);
-    default: return launch_segsum_csr<0, false>(bt_, row_ptr, col, val, n, d, none, st);
+    case CSK_F32: return launch_segsum_csr<CSK_F32, false>(bt_, row_ptr, col, val, n, d, none, queue, st);
+    case CSK_F16: return launch_segsum_csr<CSK_F16, false>(bt_, row_ptr, col, val, n, d, none, queue, st);
+    case CSK_BF16: return launch_segsum_csr<CSK_BF16, false>(bt_, row_ptr, col, val, n, d, none, queue, st);
+    default: return launch_segsum_csr<0, false>(bt_, row_ptr, col, val, n, d, none, queue, st);
     }
 }
 
@@ -1199,7 +1392,9 @@ csk_status sketch_csr_sparse_run(const int64_t* row_ptr, const int32_t* col, con
 {
     Batch bt_;
     uint32_t* ofs = nullptr;
-    csk_status r = csr_setup(b, bt, nu2, m, n, d, seed, nullptr, 0, nullptr, 0, ws, ws_bytes, true, bt_, &ofs, st);
+    uint32_t* queue = nullptr;
+    csk_status r = csr_setup(b, bt, nu2, m, n, d, seed, nullptr, 0, nullptr, 0, ws, ws_bytes, true, bt_, &queue, &ofs,
+                             st);
     if (r != CSK_OK) return r;
     // distinct columns per bucket (into cnt, which the grouping left zero),
     // then their exclusive scan: each bucket's offset in the result
@@ -1212,7 +1407,7 @@ csk_status sketch_csr_sparse_run(const int64_t* row_ptr, const int32_t* col, con
     CSK_LAUNCH_CHECK("k_csr_distinct");
     if ((r = exclusive_scan(bt_.cnt, d, bt_.scan_part, ofs, st)) != CSK_OK) return r;
     const CsrOut so{ofs, at_rp, at_col, at_val};
-    return launch_segsum_csr<0, true>(bt_, row_ptr, col, val, n, d, so, st);
+    return launch_segsum_csr<0, true>(bt_, row_ptr, col, val, n, d, so, queue, st);
 }
 
 }  // namespace csk

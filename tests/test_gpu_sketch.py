@@ -127,7 +127,12 @@ def test_sketch_row_scaled_full_size_bitexact(gpu, orc):
     np.testing.assert_array_equal(_bits16(out.At_lp), orc.round_f64_to_bf16_bits(At))
 
 
-@pytest.mark.parametrize("m,n,dens,d", [(3000, 400, 0.01, 150), (20000, 3000, 0.002, 700), (50, 9000, 0.01, 10)])
+# (6000, 3000, 0.02, 600): about 600 stored entries per bucket, so some
+# buckets fit the ranked-run kernel's 512-entry staging and the rest go
+# through the queue to the accumulator-row kernel; (20000, 2000, 0.01, 40):
+# 500 rows per bucket, every bucket queued
+@pytest.mark.parametrize("m,n,dens,d", [(3000, 400, 0.01, 150), (20000, 3000, 0.002, 700), (50, 9000, 0.01, 10),
+                                        (6000, 3000, 0.02, 600), (20000, 2000, 0.01, 40)])
 def test_sketch_csr_bitexact(gpu, orc, m, n, dens, d):
     s = W.sparse_csr(m, n, dens, seed=m)
     rp = torch.from_numpy(s.row_ptr).to(DEV)

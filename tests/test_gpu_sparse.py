@@ -42,7 +42,7 @@ def _union_pattern(orc, s, d, seed):
 
 
 @pytest.mark.parametrize("m,n,dens,d", [(3000, 400, 0.01, 150), (20000, 3000, 0.002, 700), (50, 9000, 0.01, 10),
-                                        (40000, 2000, 0.003, 4000)])
+                                        (40000, 2000, 0.003, 4000), (6000, 3000, 0.02, 600)])
 def test_sparse_sketch_bitexact(gpu, orc, m, n, dens, d):
     s = W.sparse_csr(m, n, dens, seed=m + 1)
     rp, col, val, b = _upload(s)
