@@ -48,6 +48,7 @@ namespace {
 constexpr int kNT = 512;        // threads per workgroup
 constexpr int kNW = kNT / kWave;
 constexpr int kK = 8;           // 16-byte vectors per lane per chunk (FP64, FP32)
+constexpr int kRegChunks = 2;   // register-resident chunks per lane group (FP64 greedy loop)
 constexpr int kK16 = 4;         // ... for the 16-bit types (8 elements per vector)
 
 using Red = GridRed;            // Red.r carries the step length alpha
@@ -260,8 +261,43 @@ template <class Tag, int kD> struct Ring {
     int lim[kD];
 };
 
+// Register-resident chunks: the RG chunks that follow the LDS-resident ones
+// in each lane group's walk, loaded once before the loop and kept in spare
+// registers for the whole solve (with their right-hand sides, norms and
+// element limits), so the ring streams RG fewer chunks per iteration.
+template <class Tag, int RG> struct RegRes {
+    uint4 buf[RG > 0 ? RG : 1][chunk_k<Tag>()];
+    double pr[RG > 0 ? RG : 1], pn[RG > 0 ? RG : 1];
+    int lim[RG > 0 ? RG : 1];
+};
+
+// Loads the register chunks: chunks L, L+1, ..., L+RG-1 of each group's walk
+// over rows [r0, r1) (those past the group's last chunk are off).
+template <class Tag, bool VEC, int LPR, int RG>
+__device__ __forceinline__ void fill_regres(RegRes<Tag, RG>& G, const typename Elem<Tag>::S* __restrict__ A,
+                                            int64_t lda, int n, int nseg, int r0, int r1,
+                                            const double* __restrict__ rhs, const double* __restrict__ nu2, int L)
+{
+    using E = Elem<Tag>;
+    constexpr int VW = VEC ? E::kVec : 1;
+    constexpr int NG = kNT / LPR;
+    constexpr int KK = chunk_k<Tag>();
+    const int q = threadIdx.x % LPR;
+    const int g = threadIdx.x / LPR;
+    const int span = r1 - r0;
+    const int nrows = span > g ? (span - g + NG - 1) / NG : 0;
+    const int nchunk = nrows * nseg;
+#pragma unroll
+    for (int u = 0; u < RG; ++u) {
+        const int c = L + u;
+        const int row = c / nseg, seg = c - (c / nseg) * nseg;
+        G.lim[u] = load_chunk<Tag, VW, LPR, KK>(G.buf[u], G.pr[u], G.pn[u], A, lda, n, r0 + g + NG * row, r0, seg, q,
+                                                c < nchunk, rhs, nu2);
+    }
+}
+
 // Issues the ring's first kD loads: chunks L, L+1, ... of each lane group's
-// walk over rows [r0, r1) (the first L are LDS-resident).
+// walk over rows [r0, r1) (the first L are LDS- or register-resident).
 template <class Tag, bool VEC, int LPR, int kD>
 __device__ __forceinline__ void ring_prime(Ring<Tag, kD>& R, const typename Elem<Tag>::S* __restrict__ A,
                                            int64_t lda, int n, int nseg, int r0, int r1,
@@ -306,12 +342,13 @@ __device__ __forceinline__ void ring_prime(Ring<Tag, kD>& R, const typename Elem
 // rows the previous one read last, some of which are still in L2.  The FP64
 // loop alternates (1.3% faster at A 200000 x 1000, d = 20000); the
 // low-precision inner product does not (FP32 measured 2.7% slower).
-template <class Tag, bool VEC, int LPR, int kD, bool ROUT, bool M>
+template <class Tag, bool VEC, int LPR, int kD, bool ROUT, bool M, int RG = 0>
 __device__ __forceinline__ void stream_rows(const typename Elem<Tag>::S* __restrict__ A, int64_t lda, int n,
                                             int nseg, int r0, int r1, const typename Elem<Tag>::Op* __restrict__ xs,
                                             const double* __restrict__ rhs, double* __restrict__ rout,
                                             const double* __restrict__ nu2, Red& loc, const ResLds& res,
-                                            double* lrout, int nrow_out, double dscale = 1.0, bool rev = false)
+                                            double* lrout, int nrow_out, double dscale = 1.0, bool rev = false,
+                                            const RegRes<Tag, RG>* reg = nullptr)
 {
     Ring<Tag, kD> R;
     using E = Elem<Tag>;
@@ -327,17 +364,19 @@ __device__ __forceinline__ void stream_rows(const typename Elem<Tag>::S* __restr
     const int nchunk = nrows * nseg;
     const int nchunk_max = (span > 0 ? (span + NG - 1) / NG : 0) * nseg;  // group 0 has the most
     const int Lg = min(res.L, nchunk_max);
+    const int Lr = RG > 0 ? min(RG, nchunk_max - Lg) : 0;  // register chunks in use
+    const int Ls = Lg + Lr;                   // first streamed chunk
     // The streamed part is padded to whole rounds of the ring so that every
     // slot is consumed and refilled unconditionally (the extra chunks are
     // off: one shared cache line, masked); the compiler then tracks the
     // in-order load counter exactly and waits only for the slot in use.
-    const int nstream = nchunk_max - Lg;
+    const int nstream = nchunk_max - Ls;
     const int nround = (nstream + kD - 1) / kD;
     // reversed walk: streamed group row irow (R0 <= irow < Rtot) reads
     // physical row R0 + Rtot - 1 - irow; only when the resident part ends on
     // a row (padding chunks past Rtot stay off)
-    const bool rv = rev && (Lg % nseg) == 0;
-    const int R0 = Lg / nseg, Rtot = nchunk_max / nseg;
+    const bool rv = rev && (Ls % nseg) == 0;
+    const int R0 = Ls / nseg, Rtot = nchunk_max / nseg;
 
     auto finish = [&](int crow, Acc s, double pr, double nn) {
         const int row = r0 + g + NG * crow;
@@ -367,8 +406,8 @@ __device__ __forceinline__ void stream_rows(const typename Elem<Tag>::S* __restr
     auto& pr = R.pr;  // right-hand side and squared norm of the slot's row
     auto& pn = R.pn;
     auto& lim = R.lim;  // valid elements of the slot from this lane's first column
-    ring_prime<Tag, VEC, LPR, kD>(R, A, lda, n, nseg, r0, r1, rhs, nu2, res.L, rv);
-    int iload = Lg + kD;  // next chunk to load
+    ring_prime<Tag, VEC, LPR, kD>(R, A, lda, n, nseg, r0, r1, rhs, nu2, Ls, rv);
+    int iload = Ls + kD;  // next chunk to load
     int irow = iload / nseg, iseg = iload - (iload / nseg) * nseg;
     int crow = 0, cseg = 0;  // next chunk to consume
     Acc acc = Acc(0);
@@ -385,6 +424,25 @@ __device__ __forceinline__ void stream_rows(const typename Elem<Tag>::S* __restr
             if (c < nchunk) finish(crow, s, res.rhs[crow * NG + g], res.nn[crow * NG + g]);
         }
         if (++cseg == nseg) { cseg = 0; ++crow; }
+    }
+    // the register chunks (chunks Lg .. Ls - 1 of the walk, in order)
+    if constexpr (RG > 0) {
+#pragma unroll
+        for (int u = 0; u < RG; ++u) {
+            if (u < Lr) {
+                const int c = Lg + u;
+                const int cbase = cseg * SW + q * VW;
+#pragma unroll
+                for (int kk = 0; kk < KK; ++kk)
+                    acc += E::template dot<VW, M>(reg->buf[u][kk], xs + cbase + kk * LPR * VW, reg->lim[u] - kk * LPR * VW);
+                if (cseg == nseg - 1) {
+                    const Acc s = group_sum_t<Acc, LPR>(acc);
+                    acc = Acc(0);
+                    if (c < nchunk) finish(crow, s, reg->pr[u], reg->pn[u]);
+                }
+                if (++cseg == nseg) { cseg = 0; ++crow; }
+            }
+        }
     }
     // consume the next chunk of the ring (group row crow, segment cseg)
     auto consume = [&](const uint4 (&v)[KK], int lm, double p, double nn) {
@@ -569,6 +627,10 @@ __device__ __forceinline__ void solve_loop(const SolveSys& S, const Ctl& C, XRec
     else
         fill_resident<tag_f64, VEC, LPR>(S.At64, S.ldat64, n, nseg64, r0, r1, S.bt, S.nu2, lchunks, lrhs, lnn, L);
     const int nrow_res = L / nseg_res;  // group rows whose last segment is resident
+    // the FP64 greedy loop keeps the chunks after the LDS ones in registers
+    constexpr int RG = (!MIXED && SEL == 0) ? kRegChunks : 0;
+    RegRes<tag_f64, RG> regres;
+    if constexpr (RG > 0) fill_regres<tag_f64, VEC, LPR, RG>(regres, S.At64, S.ldat64, n, nseg64, r0, r1, S.bt, S.nu2, L);
     // ||x_ref||^2 and ||bt||^2, reduced identically by every workgroup.
     Red q = red_identity();
     if (S.xref)
@@ -617,9 +679,10 @@ __device__ __forceinline__ void solve_loop(const SolveSys& S, const Ctl& C, XRec
                                                                         S.bt, nullptr, S.nu2, loc, res, sres,
                                                                         gmax_rows, 1.0, (k & 1) != 0);
         } else if constexpr (!MIXED) {
-            stream_rows<tag_f64, VEC, LPR, ring_depth<tag_f64>(), false, M>(S.At64, S.ldat64, n, nseg64, r0, r1, sx,
-                                                                         S.bt, nullptr, S.nu2, loc, res, nullptr, 0,
-                                                                         1.0, (k & 1) != 0);
+            // two register chunks take the registers of the ring's third slot
+            constexpr int kDg = RG >= 2 ? 2 : ring_depth<tag_f64>();
+            stream_rows<tag_f64, VEC, LPR, kDg, false, M, RG>(S.At64, S.ldat64, n, nseg64, r0, r1, sx, S.bt, nullptr,
+                                                           S.nu2, loc, res, nullptr, 0, 1.0, (k & 1) != 0, &regres);
         } else {
             stream_rows<Tag, VEC, LPR, ring_depth<Tag>(), false, M>(static_cast<const LPS*>(S.At), S.ldat, n, nseglp,
                                                                  r0, r1, op_lp, S.rref, nullptr, S.nu2, loc, res,
