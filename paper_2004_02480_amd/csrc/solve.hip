@@ -48,7 +48,7 @@ namespace {
 constexpr int kNT = 512;        // threads per workgroup
 constexpr int kNW = kNT / kWave;
 constexpr int kK = 8;           // 16-byte vectors per lane per chunk (FP64, FP32)
-constexpr int kRegChunks = 2;   // register-resident chunks per lane group (FP64 greedy loop)
+constexpr int kRegChunks = 4;   // register-resident chunks per lane group (FP64 greedy loop)
 constexpr int kK16 = 4;         // ... for the 16-bit types (8 elements per vector)
 
 using Red = GridRed;            // Red.r carries the step length alpha
@@ -627,8 +627,9 @@ __device__ __forceinline__ void solve_loop(const SolveSys& S, const Ctl& C, XRec
     else
         fill_resident<tag_f64, VEC, LPR>(S.At64, S.ldat64, n, nseg64, r0, r1, S.bt, S.nu2, lchunks, lrhs, lnn, L);
     const int nrow_res = L / nseg_res;  // group rows whose last segment is resident
-    // the FP64 greedy loop keeps the chunks after the LDS ones in registers
-    constexpr int RG = (!MIXED && SEL == 0) ? kRegChunks : 0;
+    // the FP64 greedy loop over 16-byte rows keeps the chunks after the LDS
+    // ones in registers
+    constexpr int RG = (!MIXED && SEL == 0 && VEC) ? kRegChunks : 0;
     RegRes<tag_f64, RG> regres;
     if constexpr (RG > 0) fill_regres<tag_f64, VEC, LPR, RG>(regres, S.At64, S.ldat64, n, nseg64, r0, r1, S.bt, S.nu2, L);
     // ||x_ref||^2 and ||bt||^2, reduced identically by every workgroup.
@@ -679,8 +680,11 @@ __device__ __forceinline__ void solve_loop(const SolveSys& S, const Ctl& C, XRec
                                                                         S.bt, nullptr, S.nu2, loc, res, sres,
                                                                         gmax_rows, 1.0, (k & 1) != 0);
         } else if constexpr (!MIXED) {
-            // two register chunks take the registers of the ring's third slot
-            constexpr int kDg = RG >= 2 ? 2 : ring_depth<tag_f64>();
+            // the register chunks take the registers of all ring slots but
+            // one: eight waves per CU with one 8 KB chunk in flight each
+            // still cover the Infinity Cache's latency, and every chunk held
+            // in registers is one the ring no longer streams
+            constexpr int kDg = RG > 0 ? 1 : ring_depth<tag_f64>();
             stream_rows<tag_f64, VEC, LPR, kDg, false, M, RG>(S.At64, S.ldat64, n, nseg64, r0, r1, sx, S.bt, nullptr,
                                                            S.nu2, loc, res, nullptr, 0, 1.0, (k & 1) != 0, &regres);
         } else {
