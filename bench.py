@@ -682,6 +682,17 @@ def csr_workload(P, W, torch, solve=True):
         log(f"[bench] sparse_csr dense mixed solve {t2:.3f} s iters={it} rel={rel:.2e} {P.csk_status_string(st)}")
         if "sparse_solve_s" in out:
             out["sparse_speedup_vs_dense"] = t2 / out["sparse_solve_s"]
+        # the same mixed solve with each FP64 refresh residual formed as
+        # S (b - A x) from the CSR A instead of bt - At64 x
+        t3, (x3, raw3) = timed(lambda: P.csk_solve_csr_refresh(sk.At_lp, sk.bt, rp, col, val, b, c["sketch_seed"],
+                                                               At64=sk.At64, nu2=sk.nu2, x_ref=xs, tol=c["tol"],
+                                                               maxit=c["maxit"], sync=False))
+        it3, st3, fb3, meas3, nref3 = P.parse_results(raw3)[0]
+        rel3 = ((x3 - xs).norm() / xs.norm()).item()
+        out.update(csr_refresh_solve_s=t3, csr_refresh_iters=it3, csr_refresh_status=P.csk_status_string(st3),
+                   csr_refresh_relerr=rel3, csr_refresh_refreshes=nref3)
+        log(f"[bench] sparse_csr dense mixed solve, refresh from the CSR A: {t3:.3f} s iters={it3} "
+            f"refreshes={nref3} rel={rel3:.2e} {P.csk_status_string(st3)}")
     del sk
     torch.cuda.empty_cache()
     return out

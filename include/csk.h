@@ -235,6 +235,30 @@ csk_status csk_solve(const void* At, csk_dtype at_dtype, int64_t ldat,
                      const csk_solve_opts* opts /*host*/, csk_solve_result* res,
                      void* ws, size_t ws_bytes, void* stream);
 
+/* ---- A7 for a sparse A: the refresh residual from the CSR A itself ---- *
+ * The mixed-precision solve of csk_solve (at_dtype F32, F16 or BF16, At64
+ * required for the projections and the FP64 fallback) on the sketch of a
+ * CSR matrix, with each refresh residual taken as r_ref = S (b - A x) from
+ * the CSR A (row_ptr m + 1 int64, col int32, val FP32, b m FP64, all
+ * device; S the count sketch of seed, as csk_sketch_csr used) instead of
+ * bt - At64 x: equal in exact arithmetic, it reads about 12 bytes per
+ * stored entry of A per refresh where bt - At64 x reads the d x n FP64
+ * sketch.  y_i = b_i - sum_e val_e x_col(e) (row i's entries in order,
+ * summed from zero in FP64), then r_ref_j = sum over rows i of bucket j in
+ * ascending order of D_ii y_i.  The call groups the rows by bucket itself
+ * (inside ws).  Other arguments, results and errors as csk_solve;
+ * additionally CSK_ERR_INVALID_ARG for an FP64 At, missing CSR arrays or b,
+ * or m or d outside [1, 2^31).  ws: csk_solve_csr_refresh_workspace_size
+ * bytes, 256-byte aligned.                                                  */
+csk_status csk_solve_csr_refresh_workspace_size(int64_t m, int64_t d, int64_t n, size_t* bytes /*host*/);
+csk_status csk_solve_csr_refresh(const void* At, csk_dtype at_dtype, int64_t ldat,
+                                 const double* At64, int64_t ldat64, int64_t d, int64_t n,
+                                 const int64_t* row_ptr, const int32_t* col, const float* val,
+                                 int64_t m, const double* b, uint64_t seed,
+                                 const double* bt, const double* nu2, const double* x0, double* x,
+                                 const csk_solve_opts* opts /*host*/, csk_solve_result* res,
+                                 void* ws, size_t ws_bytes, void* stream);
+
 /* ---- csk_solve without a workspace: for callers that cannot allocate ---- *
  * For code that must not call hipMalloc (work recorded under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation): the same

@@ -44,6 +44,7 @@ def _load():
     lib.orc_sketch_dense_f64.argtypes = [_p, _i64, _i64, _i64, _p, _i64, _i64, _i64, _u64, _p, _i64, _p, _i64]
     lib.orc_sketch_dense_f32.argtypes = lib.orc_sketch_dense_f64.argtypes
     lib.orc_sketch_csr_f32.argtypes = [_p, _p, _p, _i64, _i64, _p, _i64, _u64, _p, _i64, _p]
+    lib.orc_sketch_residual_csr.argtypes = [_p, _p, _p, _i64, _p, _p, _i64, _u64, _p]
     for name in ("orc_round_f64_to_f32", "orc_round_f64_to_bf16", "orc_round_f64_to_f16",
                  "orc_round_f32_to_bf16", "orc_round_f32_to_f16"):
         getattr(lib, name).argtypes = [_p, _p, _i64]
@@ -163,6 +164,18 @@ def sketch_csr(row_ptr, col, val, m: int, n: int, b, d: int, seed: int):
     _load().orc_sketch_csr_f32(_ptr(row_ptr), _ptr(col), _ptr(val), m, n, _ptr(bb), d, seed,
                                _ptr(At), n, _ptr(bt))
     return At, bt
+
+
+def sketch_residual_csr(row_ptr, col, val, m: int, b, x, d: int, seed: int):
+    """S (b - A x) for a CSR A with FP32 values (orc_sketch_residual_csr)."""
+    row_ptr = _c(row_ptr, np.int64)
+    col = _c(col, np.int32)
+    val = _c(val, np.float32)
+    bb = _c(b, np.float64)
+    xx = _c(x, np.float64)
+    r = np.empty(d, np.float64)
+    _load().orc_sketch_residual_csr(_ptr(row_ptr), _ptr(col), _ptr(val), m, _ptr(bb), _ptr(xx), d, seed, _ptr(r))
+    return r
 
 
 def round_f64_to_f32(a):

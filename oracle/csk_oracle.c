@@ -236,6 +236,27 @@ void orc_sketch_csr_f32(const int64_t* row_ptr, const int32_t* col, const float*
     }
 }
 
+/* The sketched residual through the original system: S (b - A x) for a CSR
+ * A (Definition 1's S applied to the residual of A x = b).  It equals
+ * bt - At x of the sketch in exact arithmetic, since S is linear; the mixed
+ * precision loop on the sketch of a sparse A can take its exact residual
+ * this way.  y_i = b_i - (sum over row i's stored entries, in stored order
+ * from zero, of val * x_col); r_h(i) accumulates D_ii y_i in ascending row
+ * order. */
+void orc_sketch_residual_csr(const int64_t* row_ptr, const int32_t* col, const float* val, int64_t m,
+                             const double* b, const double* x, int64_t d, uint64_t seed, double* r)
+{
+    for (int64_t j = 0; j < d; ++j) r[j] = 0.0;
+    for (int64_t i = 0; i < m; ++i) {
+        double s = 0.0;
+        for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) s = s + (double)val[p] * x[col[p]];
+        double y = b[i] - s;
+        uint64_t w = orc_row_word(seed, (uint64_t)i);
+        int64_t h = (int64_t)orc_bucket_of(w, (uint64_t)d);
+        r[h] = r[h] + (double)orc_sign_of(w) * y;
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Precision reduction of the finished sketch (not part of the paper).       */
 /* ------------------------------------------------------------------------ */

@@ -10,7 +10,7 @@ import importlib
 
 _BINDING_NAMES = {
     "CskError", "SketchOut", "CsrSketchOut", "SolveResult", "csk_hash", "csk_sketch", "csk_sketch_csr",
-    "csk_sketch_csr_sparse", "csk_solve", "csk_solve_noalloc", "csk_solve_csr", "csk_solve_rgrk", "csk_solve_rk",
+    "csk_sketch_csr_sparse", "csk_solve", "csk_solve_noalloc", "csk_solve_csr_refresh", "csk_solve_csr", "csk_solve_rgrk", "csk_solve_rk",
     "csk_pipeline_capture", "Pipeline",
     "csk_solve_batched", "csk_solve_batched_sketches", "csk_solve_mrhs", "csk_tune_solve", "csk_tune_lookup", "csk_tune_clear",
     "csk_tune_mrhs", "csk_tune_batched", "csk_tune_save", "csk_tune_load",

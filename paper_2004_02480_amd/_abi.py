@@ -36,6 +36,7 @@ EXPORTED = [
     "csk_sketch_csr_workspace_size", "csk_sketch_csr",
     "csk_sketch_csr_sparse_workspace_size", "csk_sketch_csr_sparse",
     "csk_solve_workspace_size", "csk_solve", "csk_solve_noalloc",
+    "csk_solve_csr_refresh_workspace_size", "csk_solve_csr_refresh",
     "csk_solve_csr_workspace_size", "csk_solve_csr",
     "csk_solve_rgrk_workspace_size", "csk_solve_rgrk",
     "csk_solve_rk_workspace_size", "csk_solve_rk",
@@ -178,6 +179,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.csk_solve.restype = I32
     lib.csk_solve.argtypes = [P, I32, I64, P, I64, I64, I64, P, P, P, P,
                               ctypes.POINTER(SolveOpts), P, P, SZ, P]
+    lib.csk_solve_csr_refresh_workspace_size.restype = I32
+    lib.csk_solve_csr_refresh_workspace_size.argtypes = [I64, I64, I64, PSZ]
+    lib.csk_solve_csr_refresh.restype = I32
+    lib.csk_solve_csr_refresh.argtypes = [P, I32, I64, P, I64, I64, I64, P, P, P, I64, P, U64, P, P, P, P,
+                                          ctypes.POINTER(SolveOpts), P, P, SZ, P]
     lib.csk_solve_noalloc.restype = I32
     lib.csk_solve_noalloc.argtypes = [P, I32, I64, P, I64, I64, I64, P, P, P, P,
                                       ctypes.POINTER(SolveOpts), P, P]

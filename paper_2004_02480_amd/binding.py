@@ -25,7 +25,7 @@ from ._abi import (CSK_BF16, CSK_CANCELLED, CSK_ERR_DEGENERATE, CSK_ERR_DEVICE, 
 
 _lib = _abi.load()
 
-__all__ = ["CskError", "SketchOut", "SolveResult", "csk_hash", "csk_sketch", "csk_sketch_csr",
+__all__ = ["CskError", "SketchOut", "SolveResult", "csk_hash", "csk_sketch", "csk_sketch_csr", "csk_solve_csr_refresh",
            "csk_solve", "csk_solve_noalloc", "csk_solve_batched", "csk_solve_batched_sketches", "csk_solve_mrhs", "csk_tune_solve",
            "csk_tune_mrhs", "csk_tune_batched", "csk_tune_save", "csk_tune_load",
            "csk_tune_lookup", "csk_tune_clear", "csk_status_string", "lib"]
@@ -367,6 +367,51 @@ def csk_solve(At: torch.Tensor, bt: torch.Tensor, *, At64: Optional[torch.Tensor
     _check(_lib.csk_solve(_ptr(At), at_code, ldat, _ptr(At64), ldat64, d, n, _ptr(bt), _ptr(nu2), _ptr(x0),
                           _ptr(x), ctypes.byref(o), _ptr(res), _ptr(workspace), workspace.numel(),
                           _stream(stream)), "csk_solve")
+    if not sync:
+        return x, res
+    (stream or torch.cuda.current_stream()).synchronize()
+    it, st, fb, meas, nref = parse_results(res)[0]
+    return SolveResult(x, it, st, fb, meas, nref)
+
+
+def csk_solve_csr_refresh(At: torch.Tensor, bt: torch.Tensor, row_ptr: torch.Tensor, col: torch.Tensor,
+                          val: torch.Tensor, b: torch.Tensor, seed: int, *, At64: torch.Tensor,
+                          nu2: Optional[torch.Tensor] = None, x0: Optional[torch.Tensor] = None,
+                          x_ref: Optional[torch.Tensor] = None, tol: float = 1e-10, maxit: int = 100000,
+                          stop_mode: Optional[int] = None, refresh_every: int = 64, cancel: Optional[int] = None,
+                          check_every: int = 256, grid: int = 0, single_wg: int = -1,
+                          out: Optional[torch.Tensor] = None, result: Optional[torch.Tensor] = None,
+                          workspace: Optional[torch.Tensor] = None, trace_idx: Optional[torch.Tensor] = None,
+                          sync: bool = True, stream=None):
+    """Mixed-precision MWRK on the sketch of a CSR matrix with each refresh
+    residual formed as S (b - A x) from the CSR A (row_ptr int64, col int32,
+    val float32, b float64; seed of the sketch) instead of bt - At64 x.
+    At: d x n float32/float16/bfloat16; At64 the FP64 sketch (projections and
+    the FP64 fallback).  Returns as csk_solve."""
+    _need_cuda(At, "At")
+    ldat = _rowmajor(At, "At")
+    ldat64 = _rowmajor(At64, "At64")
+    d, n = At.shape
+    m = row_ptr.numel() - 1
+    at_code = _TORCH_TO_CSK[At.dtype]
+    if row_ptr.dtype != torch.int64 or col.dtype != torch.int32 or val.dtype != torch.float32 \
+            or b.dtype != torch.float64:
+        raise TypeError("row_ptr int64, col int32, val float32 and b float64 expected")
+    if stop_mode is None:
+        stop_mode = CSK_STOP_REL_ERR if x_ref is not None else CSK_STOP_REL_RESID
+    dev = At.device
+    x = out if out is not None else torch.empty(n, dtype=torch.float64, device=dev)
+    res = result if result is not None else torch.zeros(_abi.RESULT_BYTES, dtype=torch.uint8, device=dev)
+    if workspace is None:
+        nbytes = ctypes.c_size_t(0)
+        _check(_lib.csk_solve_csr_refresh_workspace_size(m, d, n, ctypes.byref(nbytes)),
+               "csk_solve_csr_refresh_workspace_size")
+        workspace = _workspace(nbytes.value, dev)
+    o = _opts(tol, maxit, stop_mode, refresh_every, x_ref, cancel, check_every, grid, single_wg, trace_idx)
+    _check(_lib.csk_solve_csr_refresh(_ptr(At), at_code, ldat, _ptr(At64), ldat64, d, n, _ptr(row_ptr), _ptr(col),
+                                      _ptr(val), m, _ptr(b), seed, _ptr(bt), _ptr(nu2), _ptr(x0), _ptr(x),
+                                      ctypes.byref(o), _ptr(res), _ptr(workspace), workspace.numel(),
+                                      _stream(stream)), "csk_solve_csr_refresh")
     if not sync:
         return x, res
     (stream or torch.cuda.current_stream()).synchronize()

@@ -414,7 +414,7 @@ namespace {
 csk_status solve_entry(const void* At, csk_dtype at_dtype, int64_t ldat, const double* At64, int64_t ldat64,
                        int64_t d, int64_t n, const double* bt, const double* nu2, const double* x0, double* x,
                        const csk_solve_opts* opts, csk_solve_result* res, void* ws, size_t ws_bytes, void* stream,
-                       bool from_scratch)
+                       bool from_scratch, const CsrRef* cref = nullptr)
 {
     g_err[0] = 0;
     csk_status st = check_opts(opts);
@@ -465,10 +465,67 @@ csk_status solve_entry(const void* At, csk_dtype at_dtype, int64_t ldat, const d
     S.d = (int32_t)d;
     S.n = (int32_t)n;
     S.stop_mode = opts->stop_mode;
-    return solve_run(S, at_dtype, opts, ws, ws_bytes, as_stream(stream));
+    return solve_run(S, at_dtype, opts, ws, ws_bytes, as_stream(stream), nullptr, cref);
+}
+
+// Workspace of csk_solve_csr_refresh: the bucket grouping, y (m doubles),
+// the refresh's grid-barrier flags, then the solve's own.
+struct CsrRefreshLayout {
+    size_t group, y, flags, solve, total;
+};
+static CsrRefreshLayout csr_refresh_layout(int64_t m, int64_t d, int64_t n)
+{
+    auto up = [](size_t v) { return (v + 255) / 256 * 256; };
+    CsrRefreshLayout L{};
+    L.group = up(group_ws_bytes(m, d));
+    L.y = up((size_t)m * 8);
+    L.flags = up((size_t)kRefreshFlags * 4);
+    L.solve = solve_ws_bytes(d, n, 65536);
+    L.total = L.group + L.y + L.flags + L.solve;
+    return L;
 }
 
 }  // namespace
+
+csk_status csk_solve_csr_refresh_workspace_size(int64_t m, int64_t d, int64_t n, size_t* bytes)
+{
+    g_err[0] = 0;
+    if (!bytes || m < 1 || d < 1 || n < 1) { set_error("bad sizes"); return CSK_ERR_INVALID_ARG; }
+    *bytes = csr_refresh_layout(m, d, n).total;
+    return CSK_OK;
+}
+
+csk_status csk_solve_csr_refresh(const void* At, csk_dtype at_dtype, int64_t ldat, const double* At64,
+                                 int64_t ldat64, int64_t d, int64_t n, const int64_t* row_ptr, const int32_t* col,
+                                 const float* val, int64_t m, const double* b, uint64_t seed, const double* bt,
+                                 const double* nu2, const double* x0, double* x, const csk_solve_opts* opts,
+                                 csk_solve_result* res, void* ws, size_t ws_bytes, void* stream)
+{
+    g_err[0] = 0;
+    if (!lp_ok(at_dtype)) { set_error("the refresh from a CSR A needs a low-precision At"); return CSK_ERR_INVALID_ARG; }
+    if (!row_ptr || !col || !val || !b) { set_error("row_ptr, col, val and b are required"); return CSK_ERR_INVALID_ARG; }
+    if (m < 1 || m > INT32_MAX || d < 1 || d > INT32_MAX) { set_error("need 1 <= m, d < 2^31"); return CSK_ERR_INVALID_ARG; }
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u)) { set_error("workspace NULL or unaligned"); return CSK_ERR_INVALID_ARG; }
+    const CsrRefreshLayout L = csr_refresh_layout(m, d, n);
+    if (ws_bytes < L.total) {
+        set_error("workspace: need %zu bytes, got %zu", L.total, ws_bytes);
+        return CSK_ERR_WORKSPACE;
+    }
+    char* base = static_cast<char*>(ws);
+    CsrRef R{};
+    R.rp = row_ptr;
+    R.col = col;
+    R.val = val;
+    R.b = b;
+    R.y = reinterpret_cast<double*>(base + L.group);
+    R.flags = reinterpret_cast<uint32_t*>(base + L.group + L.y);
+    R.m = m;
+    R.seed = seed;
+    csk_status st = group_only(m, d, seed, base, L.group, &R.perm, &R.ptr, as_stream(stream));
+    if (st != CSK_OK) return st;
+    return solve_entry(At, at_dtype, ldat, At64, ldat64, d, n, bt, nu2, x0, x, opts, res,
+                       base + L.group + L.y + L.flags, L.solve, stream, false, &R);
+}
 
 csk_status csk_solve(const void* At, csk_dtype at_dtype, int64_t ldat, const double* At64, int64_t ldat64,
                      int64_t d, int64_t n, const double* bt, const double* nu2, const double* x0, double* x,

@@ -54,6 +54,11 @@ csk_status sketch_run(const SketchJob* jobs, int32_t nsys, csk_dtype a_dtype, cs
 // CSR sketch (FP32 values), single system: dense outputs, or (sparse) At as
 // CSR with FP64 values.  Workspace bytes of either.
 size_t sketch_csr_ws_bytes(int64_t m, int64_t d, bool sparse);
+// The rows 0..m-1 grouped by bucket (seed, d buckets), ascending within a
+// bucket: perm (m) and ptr (d + 1), both inside ws (group_ws_bytes).
+size_t group_ws_bytes(int64_t m, int64_t d);
+csk_status group_only(int64_t m, int64_t d, uint64_t seed, void* ws, size_t ws_bytes, const uint32_t** perm,
+                      const uint32_t** ptr, hipStream_t st);
 csk_status sketch_csr_sparse_run(const int64_t* row_ptr, const int32_t* col, const float* val, int64_t m,
                                  int64_t n, const double* b, int64_t d, uint64_t seed, int64_t* at_rp,
                                  int32_t* at_col, double* at_val, double* bt, double* nu2, void* ws, size_t ws_bytes,

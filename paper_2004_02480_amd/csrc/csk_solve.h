@@ -22,6 +22,25 @@ struct SolveSys {
     int32_t npad;         // LDS length of the operand vectors (>= n, zero-padded)
 };
 
+// Mixed precision on the sketch of a CSR matrix: the refresh residual taken
+// as r_ref = S (b - A x) from the CSR A itself, in place of bt - At64 x.
+// rp/col/val/b: the CSR A (m rows) and b; perm/ptr: the rows grouped by
+// bucket, ascending within a bucket (the sketch's grouping for seed); y: m
+// doubles of scratch; flags: kRefreshFlags grid-barrier words.
+constexpr int kRefreshFlags = 1024;
+struct CsrRef {
+    const int64_t* rp;
+    const int32_t* col;
+    const float* val;
+    const double* b;
+    const uint32_t* perm;
+    const uint32_t* ptr;
+    double* y;
+    uint32_t* flags;
+    int64_t m;
+    uint64_t seed;
+};
+
 struct SolvePlan {
     int lpr;        // lanes per row in the residual product
     int vw;         // elements per vector load (1 = scalar path)
@@ -38,8 +57,10 @@ int64_t solve_npad(int64_t n, csk_dtype at_dtype, int lpr, bool vec);
 int solve_batch_lpr();
 
 // forced: a launch shape to use instead of the planned one (tuning), or null.
+// cref: the refresh from a CSR A (mixed precision only), or null.
 csk_status solve_run(const SolveSys& sys, csk_dtype at_dtype, const csk_solve_opts* o,
-                     void* ws, size_t ws_bytes, hipStream_t st, const SolvePlan* forced = nullptr);
+                     void* ws, size_t ws_bytes, hipStream_t st, const SolvePlan* forced = nullptr,
+                     const CsrRef* cref = nullptr);
 
 // The relaxed greedy randomized selection rule (FP64 At64 only; theta in
 // [0, 1], selection stream seed sel_seed) in place of the greedy one.

@@ -1360,6 +1360,21 @@ csk_status launch_segsum_csr(const Batch& b, const int64_t* row_ptr, const int32
 
 }  // namespace
 
+size_t group_ws_bytes(int64_t m, int64_t d) { return sketch_csr_ws_bytes(m, d, false); }
+
+csk_status group_only(int64_t m, int64_t d, uint64_t seed, void* ws, size_t ws_bytes, const uint32_t** perm,
+                      const uint32_t** ptr, hipStream_t st)
+{
+    Batch bt_;
+    uint32_t* queue = nullptr;
+    const csk_status r = csr_setup(nullptr, nullptr, nullptr, m, 1, d, seed, nullptr, 0, nullptr, 0, ws, ws_bytes,
+                                   false, bt_, &queue, nullptr, st);
+    if (r != CSK_OK) return r;
+    *perm = bt_.perm;
+    *ptr = bt_.ptr;
+    return CSK_OK;
+}
+
 size_t sketch_csr_ws_bytes(int64_t m, int64_t d, bool sparse)
 {
     return sketch_ws_bytes(m, d, d, 1) + (size_t)(d + 1) * 4 + 256 + (sparse ? (size_t)(d + 1) * 4 + 256 : 0);

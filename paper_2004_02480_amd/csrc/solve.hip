@@ -78,6 +78,7 @@ struct Ctl {
     double theta;          // ... its relaxation parameter
     uint64_t sel_seed;     // ... and the seed of its selection stream
     int64_t* trace;        // nullable: row projected at each iteration
+    CsrRef cref;           // mixed precision: refresh from a CSR A (cref.rp non-null)
 };
 
 // Element access.  A chunk slot holds one 16-byte vector per k (VW elements)
@@ -556,6 +557,75 @@ __device__ __forceinline__ double rgrk_threshold(double theta, double M, double 
     return t > M ? M : t;
 }
 
+// The candidate of one row from its residual r and squared norm nn (the
+// weighted-residual rule; rows of zero norm are never selected).
+__device__ __forceinline__ void row_candidate(Red& loc, uint32_t row, double r, double nn)
+{
+    loc.r2 += r * r;
+    if (nn > 0.0) {
+        const double score = (r * r) / nn;
+        if (!isfinite(score)) {
+            loc.flags |= kFlagNonfinite;
+        } else if (cand_better(score, row, loc.score, loc.idx)) {
+            loc.score = score;
+            loc.r = r / nn;
+            loc.idx = row;
+        }
+    } else if (isnan(nn)) {
+        loc.flags |= kFlagNonfinite;
+    }
+}
+
+// The refresh residual of the mixed loop from a CSR A: r_ref = S (b - A x)
+// (equal to bt - At x in exact arithmetic, and reading the CSR A, about
+// 12 bytes per stored entry, instead of the d x n FP64 sketch).  Every
+// workgroup forms y_i = b_i - sum_e val_e x_col(e) for its share of the m
+// rows (the row's stored entries in order, summed from zero in FP64) and
+// publishes it; after a grid barrier each workgroup sums, for each of its
+// rows j of the sketch, D_ii y_i over the rows i of bucket j in ascending
+// order (the sketch's order), stores r_ref and the LDS copy of resident
+// rows, and forms the candidates as the streamed refresh does.
+template <int LPR>
+__device__ void refresh_from_csr(const CsrRef& R, const SolveSys& S, const double* __restrict__ sx, int r0, int r1,
+                                 int nrow_res, double* lrhs, Red& loc, int wg, int G, uint32_t epoch, uint32_t* s_ok,
+                                 bool& ok)
+{
+    constexpr int NG = kNT / LPR;
+    const int64_t per = (R.m + G - 1) / G;
+    const int64_t i0 = min(R.m, (int64_t)wg * per), i1 = min(R.m, i0 + per);
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kNT) {
+        const int64_t e0 = R.rp[i], e1 = R.rp[i + 1];
+        double s = 0.0;
+        for (int64_t e = e0; e < e1; ++e) s += static_cast<double>(R.val[e]) * sx[R.col[e]];
+        coh_store(&R.y[i], R.b[i] - s);
+    }
+    ok = grid_barrier_flags(R.flags, wg, G, epoch, s_ok) && ok;
+    for (int j = r0 + (int)threadIdx.x; j < r1; j += kNT) {
+        const uint32_t p0 = R.ptr[j], p1 = R.ptr[j + 1];
+        double r = 0.0;
+        uint32_t p = p0;
+        // four rows' loads in flight, added in order
+        for (; p + 4 <= p1; p += 4) {
+            uint32_t i[4];
+            double v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) i[u] = R.perm[p + u];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = coh_load(&R.y[i[u]]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) r += draw_sign(draw_word(R.seed, i[u])) * v[u];
+        }
+        for (; p < p1; ++p) {
+            const uint32_t i = R.perm[p];
+            r += draw_sign(draw_word(R.seed, i)) * coh_load(&R.y[i]);
+        }
+        S.rref[j] = r;
+        const int lj = j - r0;
+        if (lj / NG < nrow_res) lrhs[(lj / NG) * NG + lj % NG] = r;
+        row_candidate(loc, static_cast<uint32_t>(j), r, S.nu2[j]);
+    }
+}
+
 // SEL 0: the greedy rule of Algorithm 1 (largest weighted residual).
 // SEL 1: the relaxed greedy randomized rule (FP64 only): after the first
 // reduction (largest score M, ||r||^2 = R, stop measure) every workgroup
@@ -577,6 +647,8 @@ __device__ __forceinline__ void solve_loop(const SolveSys& S, const Ctl& C, XRec
     constexpr int LAYER = kNT * chunk_k<Tag>() * 16;
     __shared__ Red slots[kNW];
     __shared__ Red slots2[kNW];  // the exchange's reduction (one barrier each)
+    __shared__ uint32_t s_bar;   // grid barrier of the refresh from a CSR A
+    uint32_t csr_epoch = 0;
 
     const int tid = threadIdx.x;
     const int n = S.n;
@@ -666,7 +738,13 @@ __device__ __forceinline__ void solve_loop(const SolveSys& S, const Ctl& C, XRec
         const bool refresh = MIXED && !fp64 && (need_refresh || (k - k_ref) >= C.refresh_every);
         const bool exact = !MIXED || fp64 || refresh;
         Red loc = red_identity();
-        if (MIXED && refresh) {
+        if (MIXED && refresh && C.cref.rp) {
+            // the refresh residual from the CSR A; every workgroup of the
+            // grid (or the one workgroup) takes part
+            bool ok = true;
+            refresh_from_csr<LPR>(C.cref, S, sx, r0, r1, nrow_res, lrhs, loc, wg, G, ++csr_epoch, &s_bar, ok);
+            if (!ok) loc.flags |= kFlagTimeout;
+        } else if (MIXED && refresh) {
             // the refresh product of the mixed mode runs once per window: a
             // shallower ring leaves the registers to the working-precision one
             // (it streams every chunk: the resident ones are low precision)
@@ -1218,7 +1296,7 @@ size_t solve_ws_bytes(int64_t d, int64_t n, int grid)
 }
 
 csk_status solve_run(const SolveSys& sys_in, csk_dtype at_dtype, const csk_solve_opts* o,
-                     void* ws, size_t ws_bytes, hipStream_t st, const SolvePlan* forced)
+                     void* ws, size_t ws_bytes, hipStream_t st, const SolvePlan* forced, const CsrRef* cref)
 {
     SolveSys S = sys_in;
     SolvePlan plan = forced ? *forced : solve_plan(S.d, S.n, at_dtype, S.ldat, S.At, o);
@@ -1234,6 +1312,15 @@ csk_status solve_run(const SolveSys& sys_in, csk_dtype at_dtype, const csk_solve
     C.exch = c.take<XRec>(2 * (size_t)std::max(plan.grid, 1));
     S.rref = c.take<double>(S.d);
     double* nu2_ws = c.take<double>(S.d);
+    if (cref) {
+        if (at_dtype == CSK_F64 || plan.grid > kRefreshFlags) {
+            set_error("the refresh from a CSR A needs a low-precision sketch and at most %d workgroups", kRefreshFlags);
+            return CSK_ERR_INVALID_ARG;
+        }
+        C.cref = *cref;
+        k_zero_words<<<4, 256, 0, st>>>(cref->flags, kRefreshFlags);
+        CSK_LAUNCH_CHECK("k_zero_words");
+    }
     if (c.bytes() > ws_bytes) {
         set_error("solve workspace too small: need %zu bytes, got %zu", c.bytes(), ws_bytes);
         return CSK_ERR_WORKSPACE;
