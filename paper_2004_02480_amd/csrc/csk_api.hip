@@ -469,9 +469,10 @@ csk_status solve_entry(const void* At, csk_dtype at_dtype, int64_t ldat, const d
 }
 
 // Workspace of csk_solve_csr_refresh: the bucket grouping, y (m doubles),
-// the refresh's grid-barrier flags, then the solve's own.
+// the refresh's grid-barrier flags, the device copy of its descriptor, then
+// the solve's own.
 struct CsrRefreshLayout {
-    size_t group, y, flags, solve, total;
+    size_t group, y, flags, ref, solve, total;
 };
 static CsrRefreshLayout csr_refresh_layout(int64_t m, int64_t d, int64_t n)
 {
@@ -480,8 +481,9 @@ static CsrRefreshLayout csr_refresh_layout(int64_t m, int64_t d, int64_t n)
     L.group = up(group_ws_bytes(m, d));
     L.y = up((size_t)m * 8);
     L.flags = up((size_t)kRefreshFlags * 4);
+    L.ref = up(sizeof(CsrRef));
     L.solve = solve_ws_bytes(d, n, 65536);
-    L.total = L.group + L.y + L.flags + L.solve;
+    L.total = L.group + L.y + L.flags + L.ref + L.solve;
     return L;
 }
 
@@ -521,10 +523,11 @@ csk_status csk_solve_csr_refresh(const void* At, csk_dtype at_dtype, int64_t lda
     R.flags = reinterpret_cast<uint32_t*>(base + L.group + L.y);
     R.m = m;
     R.seed = seed;
+    R.self = reinterpret_cast<CsrRef*>(base + L.group + L.y + L.flags);
     csk_status st = group_only(m, d, seed, base, L.group, &R.perm, &R.ptr, as_stream(stream));
     if (st != CSK_OK) return st;
     return solve_entry(At, at_dtype, ldat, At64, ldat64, d, n, bt, nu2, x0, x, opts, res,
-                       base + L.group + L.y + L.flags, L.solve, stream, false, &R);
+                       base + L.group + L.y + L.flags + L.ref, L.solve, stream, false, &R);
 }
 
 csk_status csk_solve(const void* At, csk_dtype at_dtype, int64_t ldat, const double* At64, int64_t ldat64,

@@ -26,7 +26,8 @@ struct SolveSys {
 // as r_ref = S (b - A x) from the CSR A itself, in place of bt - At64 x.
 // rp/col/val/b: the CSR A (m rows) and b; perm/ptr: the rows grouped by
 // bucket, ascending within a bucket (the sketch's grouping for seed); y: m
-// doubles of scratch; flags: kRefreshFlags grid-barrier words.
+// doubles of scratch; flags: kRefreshFlags grid-barrier words; self: device
+// memory for a copy of this descriptor (the kernel reads it from there).
 constexpr int kRefreshFlags = 1024;
 struct CsrRef {
     const int64_t* rp;
@@ -39,6 +40,7 @@ struct CsrRef {
     uint32_t* flags;
     int64_t m;
     uint64_t seed;
+    CsrRef* self;
 };
 
 struct SolvePlan {

@@ -78,7 +78,7 @@ struct Ctl {
     double theta;          // ... its relaxation parameter
     uint64_t sel_seed;     // ... and the seed of its selection stream
     int64_t* trace;        // nullable: row projected at each iteration
-    CsrRef cref;           // mixed precision: refresh from a CSR A (cref.rp non-null)
+    const CsrRef* cref;    // mixed precision: refresh from a CSR A (device copy), or null
 };
 
 // Element access.  A chunk slot holds one 16-byte vector per k (VW elements)
@@ -738,11 +738,11 @@ __device__ __forceinline__ void solve_loop(const SolveSys& S, const Ctl& C, XRec
         const bool refresh = MIXED && !fp64 && (need_refresh || (k - k_ref) >= C.refresh_every);
         const bool exact = !MIXED || fp64 || refresh;
         Red loc = red_identity();
-        if (MIXED && refresh && C.cref.rp) {
+        if (MIXED && refresh && C.cref) {
             // the refresh residual from the CSR A; every workgroup of the
             // grid (or the one workgroup) takes part
             bool ok = true;
-            refresh_from_csr<LPR>(C.cref, S, sx, r0, r1, nrow_res, lrhs, loc, wg, G, ++csr_epoch, &s_bar, ok);
+            refresh_from_csr<LPR>(*C.cref, S, sx, r0, r1, nrow_res, lrhs, loc, wg, G, ++csr_epoch, &s_bar, ok);
             if (!ok) loc.flags |= kFlagTimeout;
         } else if (MIXED && refresh) {
             // the refresh product of the mixed mode runs once per window: a
@@ -948,6 +948,10 @@ __global__ __launch_bounds__(kNT) void k_solve_batched(const SolveSys* __restric
         __syncthreads();
     }
 }
+
+// The refresh descriptor into device memory (a kernel, so the call records
+// into a captured graph like any other launch).
+__global__ void k_store_csr_ref(CsrRef v, CsrRef* dst) { *dst = v; }
 
 __global__ void k_zero_words(uint32_t* p, int64_t words)
 {
@@ -1317,7 +1321,13 @@ csk_status solve_run(const SolveSys& sys_in, csk_dtype at_dtype, const csk_solve
             set_error("the refresh from a CSR A needs a low-precision sketch and at most %d workgroups", kRefreshFlags);
             return CSK_ERR_INVALID_ARG;
         }
-        C.cref = *cref;
+        if (!cref->self) {
+            set_error("the refresh from a CSR A needs a device copy of its descriptor");
+            return CSK_ERR_INVALID_ARG;
+        }
+        k_store_csr_ref<<<1, 1, 0, st>>>(*cref, cref->self);
+        CSK_LAUNCH_CHECK("k_store_csr_ref");
+        C.cref = cref->self;
         k_zero_words<<<4, 256, 0, st>>>(cref->flags, kRefreshFlags);
         CSK_LAUNCH_CHECK("k_zero_words");
     }
