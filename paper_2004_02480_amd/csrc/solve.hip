@@ -288,6 +288,7 @@ __device__ __forceinline__ void fill_regres(RegRes<Tag, RG>& G, const typename E
     const int span = r1 - r0;
     const int nrows = span > g ? (span - g + NG - 1) / NG : 0;
     const int nchunk = nrows * nseg;
+    if (span <= 0) return;  // no rows: nothing to hold (and r0 may be d, past the last row)
 #pragma unroll
     for (int u = 0; u < RG; ++u) {
         const int c = L + u;
@@ -495,6 +496,9 @@ __device__ void fill_resident(const typename Elem<Tag>::S* __restrict__ A, int64
     const int span = r1 - r0;
     const int nrows = span > g ? (span - g + NG - 1) / NG : 0;
     const int nchunk = nrows * nseg;
+    // a workgroup past the last row (r0 = d) holds nothing: none of its
+    // chunks is ever read, and row r0 would lie outside the matrix
+    if (span <= 0) return;
     for (int c = 0; c < L; ++c) {
         const int crow = c / nseg, seg = c - (c / nseg) * nseg;
         uint4 v[KK];
