@@ -390,14 +390,18 @@ __global__ __launch_bounds__(kNT) void k_mrhs(MCtl C)
 // (words as in exchange(): 32 bits of payload, the iteration tag k + 1 in
 // the upper half, two slots alternating by parity):
 //   1. every workgroup (row block rb, column block cb) forms its residual
-//      block and publishes, per live column, its best row (one 64-byte
-//      record of eight tagged words);
+//      block and publishes, per live column, its best row (a record of
+//      eight tagged words, stored word-major: word f of the records of
+//      column j from row blocks 0..RB-1 is one contiguous run);
 //   2. the owner of column j (workgroup (j mod RB, cb) of its column block)
-//      polls the RB records of j, reduces them in fixed order, applies the
+//      polls one word of each of the RB records of j (a wave's polls cover
+//      consecutive row blocks, so a few cache lines) and reads a record
+//      once that word is fresh, reduces them in fixed order, applies the
 //      stop test and publishes (i_j, alpha_j) (four tagged words; a final
 //      status carries the tag kFinal in both slots), then projects its own
 //      FP64 copy of X[:, j] with the FP64 row;
-//   3. every workgroup polls the results of its 128 columns and adds
+//   3. every workgroup polls one word of the results of its 128 columns,
+//      reads the four once it is fresh, and adds
 //      alpha_j At_lp^(i_j) to its copy of Delta[:, j] = X - X_ref, which each
 //      lane keeps in registers, in the 16-bit type, for the k positions it
 //      feeds to the matrix cores (each update summed in FP32 and rounded
@@ -408,6 +412,11 @@ __global__ __launch_bounds__(kNT) void k_mrhs(MCtl C)
 // where the owner's X accumulates the FP64 ones; every refresh restarts both
 // from the exact FP64 residual of the published X.  Owners publish X (and a flag per
 // column) at the end of the iteration before each refresh.
+// Polling one word instead of the whole record, and the word-major candidate
+// layout, cut the device-coherent requests that every poll round puts on the
+// fabric (with about 250 workgroups polling at once) by 8x and then by the
+// record count per cache line; at 256 right-hand sides over d = 10000 an
+// iteration went from 25.5 to 20.7 us.
 constexpr uint32_t kFinalTag = 0xFFFFFFFFu;
 constexpr int kRdMaxNpad = 512;  // Delta in registers: 32 * KS k positions, KS <= 16
 
@@ -420,7 +429,7 @@ struct RdCtl {
     const double* nu2;         // d
     double* XT;                // Rpad x npad: X published at refreshes (X0 at launch)
     const double* XuT;         // Rpad x npad: reference solution, or null
-    uint64_t* cand;            // [2][RB][Rpad][8] tagged words, zero at launch
+    uint64_t* cand;            // [2][8][Rpad][RB] tagged words (word-major), zero at launch
     uint64_t* resw;            // [2][Rpad][4] tagged words, zero at launch
     uint32_t* xflag;           // Rpad: last refresh iteration whose X is published, zero at launch
     const double* colref2;     // Rpad: ||Xref[:, j]||^2
@@ -618,7 +627,7 @@ __global__ __launch_bounds__(kNT) void k_mrhs_rd(RdCtl C)
             if (!done && k > 0) {
                 uint32_t spins = 0;
                 while (static_cast<int32_t>(coh_load(&C.xflag[mycol]) - static_cast<uint32_t>(k)) < 0) {
-                    __builtin_amdgcn_s_sleep(1);
+                    __builtin_amdgcn_s_sleep(2);
                     if (++spins > kSpinLimit) { fail = true; done = true; break; }
                 }
             }
@@ -692,18 +701,19 @@ __global__ __launch_bounds__(kNT) void k_mrhs_rd(RdCtl C)
             cv = red_combine(cv, o);
         }
         if (!done && lg == 0) {
-            uint64_t* rec = C.cand + (((size_t)slot * RB + rb) * C.Rpad + mycol) * 8;
+            const size_t fs = (size_t)C.Rpad * RB;  // stride between the words of a record
+            uint64_t* rec = C.cand + ((size_t)slot * 8 * C.Rpad + mycol) * RB + rb;
             const uint64_t sb = static_cast<uint64_t>(__double_as_longlong(cv.score));
             const uint64_t ab = static_cast<uint64_t>(__double_as_longlong(cv.r));
             const uint64_t rb2 = static_cast<uint64_t>(__double_as_longlong(cv.r2));
-            coh_store(&rec[0], tagw(static_cast<uint32_t>(sb), tag));
-            coh_store(&rec[1], tagw(static_cast<uint32_t>(sb >> 32), tag));
-            coh_store(&rec[2], tagw(static_cast<uint32_t>(ab), tag));
-            coh_store(&rec[3], tagw(static_cast<uint32_t>(ab >> 32), tag));
-            coh_store(&rec[4], tagw(static_cast<uint32_t>(rb2), tag));
-            coh_store(&rec[5], tagw(static_cast<uint32_t>(rb2 >> 32), tag));
-            coh_store(&rec[6], tagw(cv.idx, tag));
-            coh_store(&rec[7], tagw(cv.flags, tag));
+            coh_store(&rec[0 * fs], tagw(static_cast<uint32_t>(sb), tag));
+            coh_store(&rec[1 * fs], tagw(static_cast<uint32_t>(sb >> 32), tag));
+            coh_store(&rec[2 * fs], tagw(static_cast<uint32_t>(ab), tag));
+            coh_store(&rec[3 * fs], tagw(static_cast<uint32_t>(ab >> 32), tag));
+            coh_store(&rec[4 * fs], tagw(static_cast<uint32_t>(rb2), tag));
+            coh_store(&rec[5 * fs], tagw(static_cast<uint32_t>(rb2 >> 32), tag));
+            coh_store(&rec[6 * fs], tagw(cv.idx, tag));
+            coh_store(&rec[7 * fs], tagw(cv.flags, tag));
         }
 
         // 2. owners: poll the row blocks' records of their columns (thread t:
@@ -717,20 +727,24 @@ __global__ __launch_bounds__(kNT) void k_mrhs_rd(RdCtl C)
             if (c < C.nown && jl < kCols && cb * kCols + jl < C.R &&
                 !__hip_atomic_load(&s_odone[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
                 const int j = cb * kCols + jl;
-                const uint64_t* rec = C.cand + (((size_t)slot * RB + b) * C.Rpad + j) * 8;
-                uint64_t v[8];
+                const size_t fs = (size_t)C.Rpad * RB;
+                const uint64_t* rec = C.cand + ((size_t)slot * 8 * C.Rpad + j) * RB + b;
+                uint64_t v[8] = {};
                 uint32_t spins = 0;
                 for (;;) {
+                    // one word per poll, the whole record once that word is fresh
+                    bool fresh = (coh_load(&rec[7 * fs]) >> 32) == tag;
+                    if (fresh) {
 #pragma unroll
-                    for (int f = 0; f < 8; ++f) v[f] = coh_load(&rec[f]);
-                    bool fresh = true;
+                        for (int f = 0; f < 8; ++f) v[f] = coh_load(&rec[f * fs]);
 #pragma unroll
-                    for (int f = 0; f < 8; ++f) fresh = fresh && ((v[f] >> 32) == tag);
+                        for (int f = 0; f < 8; ++f) fresh = fresh && ((v[f] >> 32) == tag);
+                    }
                     if (fresh) break;
                     // the owner wave may finish the column (the previous
                     // iteration's test) while this thread already polls
                     if (__hip_atomic_load(&s_odone[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) { spins = 0; break; }
-                    __builtin_amdgcn_s_sleep(1);
+                    __builtin_amdgcn_s_sleep(2);
                     if (++spins > kSpinLimit) break;
                 }
                 if (spins > kSpinLimit) {
@@ -871,17 +885,22 @@ __global__ __launch_bounds__(kNT) void k_mrhs_rd(RdCtl C)
             uint32_t spins = 0;
             bool fin = false;
             for (;;) {
+                // one word per poll, all four once it carries this
+                // iteration's tag or the final one
+                const uint64_t t3 = coh_load(&rw[3]) >> 32;
+                if (t3 == tag || t3 == kFinalTag) {
 #pragma unroll
-                for (int f = 0; f < 4; ++f) v[f] = coh_load(&rw[f]);
-                bool fresh = true, final_all = true;
+                    for (int f = 0; f < 4; ++f) v[f] = coh_load(&rw[f]);
+                    bool fresh = true, final_all = true;
 #pragma unroll
-                for (int f = 0; f < 4; ++f) {
-                    fresh = fresh && ((v[f] >> 32) == tag);
-                    final_all = final_all && ((v[f] >> 32) == kFinalTag);
+                    for (int f = 0; f < 4; ++f) {
+                        fresh = fresh && ((v[f] >> 32) == tag);
+                        final_all = final_all && ((v[f] >> 32) == kFinalTag);
+                    }
+                    if (final_all) { fin = true; break; }
+                    if (fresh) break;
                 }
-                if (final_all) { fin = true; break; }
-                if (fresh) break;
-                __builtin_amdgcn_s_sleep(1);
+                __builtin_amdgcn_s_sleep(2);
                 if (++spins > kSpinLimit) { fail = true; break; }
             }
             if (fin || fail) {
