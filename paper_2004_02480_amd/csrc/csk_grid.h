@@ -231,14 +231,14 @@ __device__ __forceinline__ T group_sum_t(T v)
     return v;
 }
 
-// One workgroup's published contribution to an iteration (tagged words, see
-// exchange()).
+// Storage of one workgroup's published contribution to an iteration (eight
+// tagged words; exchange() interleaves the words of four records).
 struct alignas(64) XRec {
     uint64_t w[8];
 };
 
 // Publish this workgroup's record for iteration k and reduce all G records
-// (grid loops).  A record is one 64-byte line of eight 64-bit words, each
+// (grid loops).  A record is eight 64-bit words, each
 // carrying 32 bits of payload and, in its upper half, the iteration tag
 // k + 1 (tags start at zero; two slots alternate by parity, so a stale word
 // is never mistaken for a fresh one).  Words are written and read with
@@ -248,6 +248,21 @@ struct alignas(64) XRec {
 // in L2).  Payload: score, alpha, the stop measure (||x - x_ref||^2 part or
 // ||r||^2 part), row index, flags; with `both`, ||r||^2 and ||x - x_ref||^2
 // in place of alpha and the stop measure (alpha then reads zero).
+// Layout: records in groups of four consecutive workgroups, word-major inside
+// a group (word f of the group's records in one 32-byte run; a short last
+// group takes the same form with fewer records), so the polled first words
+// of 64 records lie in 16 cache lines of 128 bytes, each written by four
+// workgroups.  Against one record per 64 bytes (32 lines per poll, two
+// writers per line) this took the FP64 solve of a 200000 x 1000 system
+// sketched to d = 20000 (256 workgroups) from 126.0 to 124.8 ms, and the
+// BF16 iteration at d = 10000, n = 1000 from 9.19 to 9.02 us; groups of
+// eight (eight lines, eight writers), whole word-major rows (four lines,
+// sixteen writers) and one record per 128-byte line (64 lines, one writer)
+// were each 1 to 10% slower.
+__host__ __device__ constexpr size_t xrec_word(int f, int w, int G)
+{
+    return (size_t)(w & ~3) * 8 + (size_t)f * (G - (w & ~3) < 4 ? G - (w & ~3) : 4) + (w & 3);
+}
 __device__ __forceinline__ double join_f64(uint64_t lo, uint64_t hi)
 {
     return __longlong_as_double((long long)((hi << 32) | (lo & 0xFFFFFFFFull)));
@@ -257,7 +272,7 @@ template <int NT>
 __device__ __forceinline__ GridRed exchange(const GridRed& mine, XRec* exch, int wg, int G, int64_t k, GridRed* slots,
                                             bool rel_err, bool both = false)  // slots: reduced with block_red1
 {
-    XRec* slot = exch + (size_t)(k & 1) * G;
+    uint64_t* slot = reinterpret_cast<uint64_t*>(exch + (size_t)(k & 1) * G);  // words xrec_word(f, w, G)
     const uint64_t tag = static_cast<uint64_t>(static_cast<uint32_t>(k + 1)) << 32;
     if (threadIdx.x < 8) {
         const int f = threadIdx.x;
@@ -267,7 +282,7 @@ __device__ __forceinline__ GridRed exchange(const GridRed& mine, XRec* exch, int
         const uint64_t bits = static_cast<uint64_t>(__double_as_longlong(dv));
         const uint32_t p = f < 6 ? static_cast<uint32_t>((f & 1) ? (bits >> 32) : bits)
                                  : (f == 6 ? mine.idx : mine.flags);
-        coh_store(&slot[wg].w[f], tag | p);
+        coh_store(&slot[xrec_word(f, wg, G)], tag | p);
     }
     bool ok = true;
     GridRed all = red_identity();
@@ -281,7 +296,7 @@ __device__ __forceinline__ GridRed exchange(const GridRed& mine, XRec* exch, int
         } else {
             // Poll one word of the record (one request per record and round:
             // the G x G polls of a grid are the exchange's main traffic), then
-            // read the line; its eight words leave in one store instruction, so
+            // read the record; its eight words leave in one store instruction, so
             // a stale word after a fresh first one is rare and just re-read.
             // Between polls a thread sleeps about 0.3 us (12 x 64 cycles): at
             // 256 workgroups, polling every 0.05 us made the solve 0.3%
@@ -289,7 +304,7 @@ __device__ __forceinline__ GridRed exchange(const GridRed& mine, XRec* exch, int
             // up to 4% slower at 9 us (a fresh record is seen later).
             uint64_t v[8];
             uint32_t spins = 0;
-            while ((coh_load(&slot[w].w[0]) & 0xFFFFFFFF00000000ull) != tag) {
+            while ((coh_load(&slot[xrec_word(0, w, G)]) & 0xFFFFFFFF00000000ull) != tag) {
                 __builtin_amdgcn_s_sleep(12);
                 if (++spins > kSpinLimit) {
                     ok = false;
@@ -298,7 +313,7 @@ __device__ __forceinline__ GridRed exchange(const GridRed& mine, XRec* exch, int
             }
             while (ok) {
 #pragma unroll
-                for (int f = 0; f < 8; ++f) v[f] = coh_load(&slot[w].w[f]);
+                for (int f = 0; f < 8; ++f) v[f] = coh_load(&slot[xrec_word(f, w, G)]);
                 bool fresh = true;
 #pragma unroll
                 for (int f = 0; f < 8; ++f) fresh = fresh && ((v[f] & 0xFFFFFFFF00000000ull) == tag);
