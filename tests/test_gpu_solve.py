@@ -65,6 +65,24 @@ def test_iterates_match_oracle_step_by_step(gpu, orc, path, K):
     assert_iterate_close(r.x, o.x)
 
 
+@pytest.mark.parametrize("grid", [5, 13, 22, 255])
+def test_exchange_with_a_short_last_record_group(gpu, orc, grid):
+    # the grid exchange interleaves the records of four workgroups; with a
+    # grid that is not a multiple of four the last group is shorter (one,
+    # one, two and three records here) and must still map every word once
+    s = W.gaussian(12000, 90, seed=21, device=DEV)
+    sk = sketched(gpu, s, 1100, 22)
+    K = 40
+    tr = new_trace(K)
+    r = gpu.csk_solve(sk.At64, sk.bt, nu2=sk.nu2, x_ref=s.x_star, tol=0.0, maxit=K, trace_idx=tr, single_wg=0,
+                      grid=grid)
+    assert r.status == gpu.CSK_NOT_CONVERGED and r.iters == K
+    At, bt = orc.sketch_dense(s.A.cpu().numpy(), s.b.cpu().numpy(), 1100, 22)
+    o = orc.mwrk(At, bt, xref=s.x_star.cpu().numpy(), tol=0.0, maxit=K, trace=True)
+    assert_trace_equal(tr, o.idx, f"grid={grid}")
+    assert_iterate_close(r.x, o.x, what=f"grid={grid}")
+
+
 @pytest.mark.parametrize("path,m,n,d,grid", [("single", 8000, 60, 1500, 1), ("grid", 60000, 90, 9000, 8),
                                               ("grid", 40000, 1000, 20000, 16)])
 def test_alternating_walk_iterates_match_oracle(gpu, orc, path, m, n, d, grid):
